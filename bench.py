@@ -1,0 +1,213 @@
+"""Benchmark: APG solves/s and p50/p99 solve latency at a fixed dual tolerance.
+
+One step is one full solve of a scenario-tree stochastic MPC instance to the
+tolerance: the per-solve data step, every APG iteration (backward sweep,
+forward sweep with the fused prox/dual update and residual, Nesterov
+extrapolation, stop test) and the final cost evaluation, starting from a
+zero dual.  The offline factor step and the step size (power iteration for
+the Lipschitz constant, cached per tree) run before the timed region and are
+reported separately.
+
+Default workload ``dwn128``: a synthetic network with the paper's dimensions
+(63 tanks, 114 pumps/valves, 88 demands, 17 mixing nodes), horizon 24, a
+tree branching 4 then 2 up to 128 scenarios (K = 2429 nodes), FP64, run to a
+residual of 1e-4.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "APG solves/sec and p50/p99 solve latency at fixed dual tolerance, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+
+def sweep_bytes(nx, nu, elem, widths, kind):
+    """Algorithmic bytes of one launch of a stage kernel, summed over the
+    launches of one iteration (list per stage)."""
+    out = []
+    for w in widths:
+        if kind == "fwd":
+            per_node = 9 * nx + 6 * nu + 1
+            per_launch = nu * nu + nx * nx + nx * nu + 3 * nx + 2 * nu
+        else:
+            per_node = 6 * nx + 5 * nu
+            per_launch = 2 * nu * nu + nx * nx + nx * nu
+        out.append((per_node * w + per_launch) * elem + (8 * w if kind == "bwd" else 4 * w))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="dwn128")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--max-iter", type=int, default=400000)
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import dwn_synth as ds
+    from paper_1904_10548_amd import tapg
+
+    try:
+        import torch
+        have_torch = torch.cuda.is_available()
+    except Exception:  # torch is optional plumbing here
+        have_torch = False
+
+    P = ds.config_problem(args.config)
+    net, w = P.net, P.weights
+    prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
+    elem = 8 if prec == tapg.TAPG_FP64 else 4
+    t0 = time.perf_counter()
+    S = tapg.Solver(dict(A=net.A, B=net.B, Gd=net.Gd, E=net.E, Ed=net.Ed, xmin=net.xmin,
+                         xmax=net.xmax, xs=net.xs, umin=net.umin, umax=net.umax),
+                    dict(W_alpha=w.W_alpha, W_s=w.W_s, W_x=w.W_x, alpha0=w.alpha0,
+                         c_energy=w.c_energy, W_u=w.W_u),
+                    P.tree.N, gamma=0.0, tol=args.tol, max_iter=args.max_iter,
+                    check_every=args.check_every, precision=prec)
+    factor_s = time.perf_counter() - t0
+    tree = S.add_tree(P.tree.nodes_per_stage, P.tree.anc, P.tree.prob, P.data.demand,
+                      P.data.price)
+    t0 = time.perf_counter()
+    L = tapg.tapg_estimate_lipschitz(S.h, tree, 100)
+    lipschitz_s = time.perf_counter() - t0
+    print(f"[bench] {args.config} K={P.tree.K} L={L:.6g} factor {factor_s:.3f}s "
+          f"power {lipschitz_s:.3f}s", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        st, u0, res = S.solve(tree, P.p, P.q)
+        print(f"[bench] warmup {i}: iters={res.iters} res={res.primal_res:.3e} "
+              f"{res.solve_ms:.1f} ms", file=sys.stderr, flush=True)
+
+    if have_torch:
+        torch.cuda.synchronize()
+    lat = []
+    results = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t1 = time.perf_counter()
+        st, u0, res = S.solve(tree, P.p, P.q)
+        lat.append(time.perf_counter() - t1)
+        results.append(res.as_dict())
+        print(f"[bench] step {i}: iters={res.iters} res={res.primal_res:.3e} "
+              f"cost={res.cost:.10g} {lat[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    if have_torch:
+        torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    lat_ms = np.array(lat) * 1e3
+    iters = results[-1]["iters"]
+
+    roof = None
+    kt = None
+    if not args.no_kernel_timing:
+        # Device time of every sweep-kernel launch, HIP events on the solver's
+        # stream, over one more solve of the same workload.
+        tapg.tapg_kernel_timing(S.h, True)
+        S.solve(tree, P.p, P.q)
+        kt = tapg.tapg_kernel_times(S.h)
+        tapg.tapg_kernel_timing(S.h, False)
+        widths = [int(v) for v in P.tree.nodes_per_stage]
+        kinds = {}
+        for kind in ("bwd", "fwd"):
+            ms, n = kt[kind]
+            b_iter = sum(sweep_bytes(net.nx, net.nu, elem, widths, kind))
+            n_iter = len(widths)
+            its = n / n_iter
+            kinds[kind] = dict(ms=ms, launches=n, bytes=b_iter * its, avg_us=1e3 * ms / max(n, 1))
+        dom = max(kinds, key=lambda k: kinds[k]["ms"])
+        d = kinds[dom]
+        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": f"{dom}_stage_kernel", "avg_launch_us": round(d["avg_us"], 3),
+                "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1),
+                "other": {k: {"avg_launch_us": round(v["avg_us"], 3), "launches": v["launches"],
+                              "ms": round(v["ms"], 3)} for k, v in kinds.items()},
+                "iteration_end_ms": round(kt["end"][0], 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P, results[-1]["gamma"], iters, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / total, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == tapg.TAPG_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: nx=63 nu=114 nd=88 ns=17 N=24, "
+                               f"{P.tree.n_scenarios} scenarios, K={P.tree.K}, "
+                               f"tol={args.tol:g}, cold start",
+                   "K": P.tree.K, "N": P.tree.N, "tol": args.tol, "precision": args.precision},
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "iters": iters,
+        "ms_per_iter": round(float(np.median(lat_ms)) / max(iters, 1), 5),
+        "final_residual": results[-1]["primal_res"],
+        "cost": results[-1]["cost"],
+        "factor_step_s": round(factor_s, 4),
+        "lipschitz_s": round(lipschitz_s, 4),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    S.close()
+
+
+def cpu_baseline(P, gamma, gpu_iters, seconds):
+    """The FP64 oracle on the host: time a bounded number of its iterations and
+    scale to the iteration count of one solve."""
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    f = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    t0 = time.perf_counter()
+    O.apg(P, gamma, f, 3)
+    per = (time.perf_counter() - t0) / 3
+    n = max(3, min(gpu_iters, int(seconds / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    O.apg(P, gamma, f, n)
+    per = (time.perf_counter() - t0) / n
+    return {"value": round(1.0 / (per * gpu_iters), 6), "unit": "solves/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} oracle APG iterations (NumPy FP64, per-stage einsum) on the same "
+                      f"instance; per-iteration time {per * 1e3:.2f} ms scaled to the "
+                      f"{gpu_iters} iterations of one solve"}
+
+
+if __name__ == "__main__":
+    main()

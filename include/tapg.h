@@ -1,0 +1,183 @@
+/*
+ * tapg.h - C ABI of the MI355X dual-APG solver for scenario-tree stochastic
+ * MPC of drinking-water networks (Sopasakis et al., "Uncertainty-aware demand
+ * management of water distribution networks in deregulated energy markets",
+ * arXiv 1904.10548).
+ *
+ * The problem (Sec. 3.4, problem SMPC) on a scenario tree (Sec. 3.3) with
+ * nodes n = 0..K-1 at decision stages 0..N-1:
+ *
+ *   minimise  sum_n p_n [ W_alpha (alpha0 + pi_n c_E)'u_n + du_n' W_u du_n ]
+ *             + sum_n [ W_x dist(x_n | [xmin, xmax]) + W_s dist(x_n | [xs, inf)) ]
+ *   s.t.      x_n = A x_anc(n) + B u_n + Gd d_n        (Sec. 2, eq. dynamics)
+ *             E u_n + Ed d_n = 0                       (eq. input-disturbance coupling)
+ *             umin <= u_n <= umax                      (eq. input constraints)
+ *
+ * with du_n = u_n - u_anc(n), x_anc(root) = p and u_anc(root) = q (problem SMPC,
+ * initial conditions).  dist is the Euclidean distance.  It is solved by the
+ * accelerated proximal gradient method on the Fenchel dual (Sec. 4.3, eqs.
+ * apg:1-apg:2), with the dual gradient computed by a backward/forward sweep
+ * over the tree (Sec. 4.4).
+ *
+ * Conventions
+ *  - Every matrix is dense, row-major, float64, owned by the caller; the
+ *    library copies what it needs during the call.  Output arrays are
+ *    allocated by the caller.
+ *  - Handles are opaque.  The library owns all device memory.
+ *  - Every function returns a tapg_status; on failure tapg_last_error()
+ *    returns a message for the calling thread.  No function aborts or throws.
+ *  - Node numbering is breadth-first: stage 0 (the root) first, then stage
+ *    1, and so on; the children of a node are contiguous and ordered like
+ *    their parents.  Every leaf is at stage N-1.
+ *  - One solver per host thread; calls on one solver are not thread safe.
+ */
+#ifndef TAPG_H
+#define TAPG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tapg_network_s* tapg_network;
+typedef struct tapg_tree_s* tapg_tree;
+typedef struct tapg_solver_s* tapg_solver;
+
+typedef enum {
+  TAPG_OK = 0,
+  TAPG_ENOTCONV = 1,  /* max_iter reached before tol; outputs are valid but inexact */
+  TAPG_EINVAL = -1,   /* null handle/pointer, out-of-range value, invalid tree */
+  TAPG_EDIM = -2,     /* dimension mismatch or unsupported size */
+  TAPG_ENOMEM = -3,   /* host or device allocation failed */
+  TAPG_EDEVICE = -4,  /* HIP runtime error or no usable gfx950 device */
+  TAPG_ESTATE = -5,   /* call out of order (e.g. solve before the factor step) */
+  TAPG_ENUMERIC = -6  /* non-finite iterate or failed factorisation */
+} tapg_status;
+
+enum { TAPG_FP64 = 0, TAPG_FP32 = 1 };
+
+/* Solver configuration (the paper's SmpcConfiguration, Sec. 5.1: tuning
+ * weights, tolerance, maximum iterations). */
+typedef struct {
+  double W_alpha;          /* economic-cost scale (Sec. 3.1), > 0 */
+  double W_s;              /* safety-level penalty weight, > 0 */
+  double W_x;              /* state-box penalty weight, > 0 */
+  const double* alpha0;    /* [nu] production cost */
+  const double* c_energy;  /* [nu] energy coefficient; node price vector = pi_n * c_energy */
+  const double* W_u;       /* [nu*nu] row-major symmetric positive definite */
+  double gamma;            /* dual step size; <= 0 selects 1/(1.02 L), L by power iteration */
+  double tol;              /* stop when max|H x_hat - t| <= tol; <= 0 runs max_iter iterations */
+  int max_iter;            /* >= 1 */
+  int check_every;         /* iterations between host checks of the stop flag (>= 1) */
+  int precision;           /* TAPG_FP64, or TAPG_FP32 sweeps (factor step and stop test stay FP64) */
+  int power_iters;         /* power iterations for L when gamma <= 0 (0 selects 100) */
+  int device;              /* HIP device ordinal */
+  void* hip_stream;        /* hipStream_t to launch on; NULL: the solver creates its own */
+} tapg_config;
+
+typedef struct {
+  int iters;          /* APG iterations performed (dual-gradient evaluations) */
+  int converged;      /* 1 if the residual reached tol */
+  double primal_res;  /* max|H x_hat(w) - t| of the last iteration (FP64) */
+  double cost;        /* primal cost of (u_hat, x_hat) without the input-box indicator (FP64) */
+  double viol_box;    /* max_n distance of u_hat_n to [umin, umax] (inf-norm) */
+  double viol_eq;     /* max of |E u + Ed d|_inf and the dynamics residual */
+  double gamma;       /* step size used */
+  double solve_ms;    /* device time of the solve (data step + iterations), HIP events */
+} tapg_result;
+
+/* Network (the paper's DwnNetwork, Sec. 5.1; model of Sec. 2).
+ * A [nx*nx], B [nx*nu], Gd [nx*nd], E [ns*nu], Ed [ns*nd]; bounds of length
+ * nx (xmin, xmax, xs) and nu (umin, umax).  Requirements: 1 <= nx, nu <= 256,
+ * nd >= 1, 0 <= ns < nu, E of full row rank, umin <= umax, xmin <= xmax.
+ * Errors: TAPG_EINVAL (null pointer), TAPG_EDIM (sizes), TAPG_ENUMERIC (E rank
+ * deficient or non-finite entries). */
+tapg_status tapg_network_create(int nx, int nu, int nd, int ns, const double* A,
+                                const double* B, const double* Gd, const double* E,
+                                const double* Ed, const double* xmin, const double* xmax,
+                                const double* xs, const double* umin, const double* umax,
+                                tapg_network* out);
+void tapg_network_destroy(tapg_network net);
+
+/* Scenario tree (the paper's ScenarioTree, Sec. 3.3 and 5.1).
+ * nodes_per_stage [N] (mu_0 = 1), ancestor [K] (ancestor[0] = -1), prob [K]
+ * (prob[0] = 1, children's probabilities add up to their parent's within
+ * 1e-12 relative, all > 0), demand [K*nd] (node-major), price [K] (the scalar
+ * pi_n).  K = sum(nodes_per_stage).  Validation errors return TAPG_EINVAL with
+ * the offending node in tapg_last_error(). */
+tapg_status tapg_tree_create(int N, const int* nodes_per_stage, const int* ancestor,
+                             const double* prob, int nd, const double* demand,
+                             const double* price, tapg_tree* out);
+/* Replace the node data of an existing tree (receding horizon: same tree
+ * shape, new forecasts).  demand [K*nd], price [K]. */
+tapg_status tapg_tree_set_data(tapg_tree tree, const double* demand, const double* price);
+/* K of a tree (number of nodes), or -1 for a null handle. */
+int tapg_tree_num_nodes(tapg_tree tree);
+void tapg_tree_destroy(tapg_tree tree);
+
+/* Solver bound to one network and one device (the paper's SmpcController with
+ * its Engine).  The configuration is copied.  Errors: TAPG_EINVAL,
+ * TAPG_ENUMERIC (W_u not SPD), TAPG_EDEVICE (device unavailable). */
+tapg_status tapg_solver_create(tapg_network net, const tapg_config* cfg, tapg_solver* out);
+void tapg_solver_destroy(tapg_solver solver);
+
+/* Offline factor step for horizon N (the paper's Engine::factorStep, Sec. 5.1;
+ * the recursion quantities of the dual-gradient DP, Sec. 4.4), in FP64 on the
+ * host, then copied to the device (FP64 and FP32 copies).  For s = N-1..0:
+ * Qbar_s = W_u + Pbar_{s+1} (Pbar_N = 0), Fbar_s = Z (Z'Qbar_s Z)^{-1} Z' with Z a
+ * basis of ker E, Kbar_s = Fbar_s W_u, Gammabar_s = I - Fbar_s Qbar_s,
+ * Pbar_s = W_u - W_u Fbar_s W_u.  Every tree of horizon N shares them. */
+tapg_status tapg_factor_step(tapg_solver solver, int N);
+/* Copy the stage-s factors (row-major nu*nu each; any pointer may be NULL). */
+tapg_status tapg_get_factors(tapg_solver solver, int stage, double* Fbar, double* Kbar,
+                             double* Gbar);
+
+/* Solve the problem on `tree` from x_{k|k} = p [nx], u_{k-1|k} = q [nu] (the
+ * paper's controlAction).  warm_start != 0 starts from the dual of this
+ * tree's previous solve on this solver (y^0 = y^-1 = that dual, theta reset);
+ * otherwise from zero.  u0_out [nu] (may be NULL) receives u_hat at the root,
+ * the input to apply.  res (may be NULL) receives the statistics.
+ * Returns TAPG_OK, TAPG_ENOTCONV (max_iter reached), or an error. */
+tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, const double* q,
+                       int warm_start, double* u0_out, tapg_result* res);
+
+/* Primal iterate of the last solve: u [K*nu], x [K*nx] (node-major). */
+tapg_status tapg_get_primal(tapg_solver solver, tapg_tree tree, double* u, double* x);
+/* Dual iterate y^{nu*+1} of the last solve, node-major blocks (y1 [nx], y2 [nx],
+ * y3 [nu]) per node: y [K*(2nx+nu)]. */
+tapg_status tapg_get_dual(tapg_solver solver, tapg_tree tree, double* y);
+/* Set the dual used by the next warm-started solve of this tree. */
+tapg_status tapg_set_dual(tapg_solver solver, tapg_tree tree, const double* y);
+/* Residual history of the last solve: hist [min(n, iters)] (FP64); returns the
+ * number of entries written through *written. */
+tapg_status tapg_residual_history(tapg_solver solver, tapg_tree tree, double* hist, int n,
+                                  int* written);
+/* Statistics of the last solve of this tree (primal residual, cost,
+ * violations); same fields as tapg_solve's result. */
+tapg_status tapg_residuals(tapg_solver solver, tapg_tree tree, tapg_result* res);
+
+/* Lipschitz constant of the dual gradient of this tree by `iters` power
+ * iterations on the device (step-size selection; see tapg_config.gamma). */
+tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iters, double* L);
+
+/* Profiling aid: with enable != 0, later solves time every sweep-kernel launch
+ * with a pair of HIP events on the solver's stream (iteration graphs are not
+ * used meanwhile, and the host checks the stop flag after every iteration).
+ * tapg_kernel_times returns, for the last timed solve, the summed device time
+ * (ms[3]) and launch counts (launches[3]) of: [0] backward-stage kernels,
+ * [1] forward-stage kernels (with the fused prox/dual update), [2] the
+ * end-of-iteration kernel. */
+tapg_status tapg_kernel_timing(tapg_solver solver, int enable);
+tapg_status tapg_kernel_times(tapg_solver solver, double* ms, long long* launches);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* tapg_last_error(void);
+/* Library version string. */
+const char* tapg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TAPG_H */

@@ -1,0 +1,509 @@
+// C-ABI entry points: argument validation, host objects, the offline FP64
+// factor step, and dispatch to the device layer.  No exception crosses the
+// ABI; every failure becomes a tapg_status plus a thread-local message.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+#include "solver.h"
+
+namespace tapg {
+
+namespace {
+thread_local std::string g_last_error;
+std::atomic<uint64_t> g_next_uid{1};
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+template <typename F>
+tapg_status guarded(F&& f) {
+  try {
+    clear_error();
+    return f();
+  } catch (const Fail& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return TAPG_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return TAPG_EINVAL;
+  } catch (...) {
+    set_error("unknown failure");
+    return TAPG_EINVAL;
+  }
+}
+
+[[noreturn]] void fail(tapg_status c, const std::string& m) { throw Fail{c, m}; }
+
+void need(const void* p, const char* what) {
+  if (p == nullptr) fail(TAPG_EINVAL, std::string(what) + " is NULL");
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+// Offline factor step (the Engine's factorStep): the per-stage quantities of
+// the Riccati-type recursion of the dual-gradient DP, Sec. 4.4.  Because the
+// children's probabilities add up to the parent's and W_u, E do not depend on
+// the node, the factor of node n is p_n-scaled from one per-stage factor:
+//   Qbar_s = W_u + Pbar_{s+1},  Pbar_N = 0
+//   Fbar_s = Z (Z' Qbar_s Z)^{-1} Z',  Kbar_s = Fbar_s W_u,
+//   Gammabar_s = I - Fbar_s Qbar_s,    Pbar_s = W_u - W_u Fbar_s W_u.
+static void factor_step(tapg_solver_s* S, int N) {
+  const NetworkHost& h = S->net;
+  const int nu = h.nu;
+  const Mat Wu = Mat::from(S->Wu.data(), nu, nu);
+  const Mat& Z = h.Z;
+  const Mat Zt = transpose(Z);
+  Mat P(nu, nu);
+  S->Fbar.assign((size_t)N * nu * nu, 0.0);
+  S->Kbar.assign((size_t)N * nu * nu, 0.0);
+  S->Gbar.assign((size_t)N * nu * nu, 0.0);
+  const Mat I = Mat::eye(nu);
+  for (int s = N - 1; s >= 0; --s) {
+    const Mat Q = add(Wu, P);
+    Mat M = matmul(matmul(Zt, Q), Z);
+    if (!cholesky(M)) fail(TAPG_ENUMERIC, "factor step: Z'(W_u + P)Z is not positive definite");
+    Mat X = Zt;  // m x nu
+    chol_solve(M, X);
+    const Mat F = matmul(Z, X);
+    const Mat Kb = matmul(F, Wu);
+    const Mat G = add(I, matmul(F, Q), -1.0);
+    Mat Pn = add(Wu, matmul(matmul(Wu, F), Wu), -1.0);
+    for (int i = 0; i < nu; ++i)
+      for (int j = i + 1; j < nu; ++j) {
+        const double v = 0.5 * (Pn(i, j) + Pn(j, i));
+        Pn(i, j) = v;
+        Pn(j, i) = v;
+      }
+    std::copy(F.a.begin(), F.a.end(), S->Fbar.begin() + (size_t)s * nu * nu);
+    std::copy(Kb.a.begin(), Kb.a.end(), S->Kbar.begin() + (size_t)s * nu * nu);
+    std::copy(G.a.begin(), G.a.end(), S->Gbar.begin() + (size_t)s * nu * nu);
+    if (!finite_all(F.a.data(), F.a.size())) fail(TAPG_ENUMERIC, "factor step: non-finite factor");
+    P = Pn;
+  }
+  S->N = N;
+}
+
+}  // namespace tapg
+
+using namespace tapg;
+
+extern "C" {
+
+const char* tapg_last_error(void) { return g_last_error.c_str(); }
+
+const char* tapg_version(void) { return "tapg 0.1 (gfx950)"; }
+
+tapg_status tapg_network_create(int nx, int nu, int nd, int ns, const double* A, const double* B,
+                                const double* Gd, const double* E, const double* Ed,
+                                const double* xmin, const double* xmax, const double* xs,
+                                const double* umin, const double* umax, tapg_network* out) {
+  return guarded([&]() -> tapg_status {
+    need(out, "out");
+    *out = nullptr;
+    if (nx < 1 || nu < 1 || nd < 1 || ns < 0 || nx > 256 || nu > 256 || ns >= nu || nd > 4096)
+      fail(TAPG_EDIM, "need 1 <= nx, nu <= 256, 1 <= nd <= 4096 and 0 <= ns < nu");
+    need(A, "A");
+    need(B, "B");
+    need(Gd, "Gd");
+    if (ns > 0) {
+      need(E, "E");
+      need(Ed, "Ed");
+    }
+    need(xmin, "xmin");
+    need(xmax, "xmax");
+    need(xs, "xs");
+    need(umin, "umin");
+    need(umax, "umax");
+    if (!finite_all(A, (size_t)nx * nx) || !finite_all(B, (size_t)nx * nu) ||
+        !finite_all(Gd, (size_t)nx * nd) || (ns > 0 && !finite_all(E, (size_t)ns * nu)) ||
+        (ns > 0 && !finite_all(Ed, (size_t)ns * nd)) || !finite_all(xmin, nx) ||
+        !finite_all(xmax, nx) || !finite_all(xs, nx) || !finite_all(umin, nu) ||
+        !finite_all(umax, nu))
+      fail(TAPG_ENUMERIC, "non-finite network data");
+    for (int i = 0; i < nu; ++i)
+      if (umin[i] > umax[i]) fail(TAPG_EINVAL, "umin > umax at input " + std::to_string(i));
+    for (int i = 0; i < nx; ++i)
+      if (xmin[i] > xmax[i]) fail(TAPG_EINVAL, "xmin > xmax at state " + std::to_string(i));
+    auto net = std::make_unique<tapg_network_s>();
+    NetworkHost& h = net->h;
+    h.nx = nx;
+    h.nu = nu;
+    h.nd = nd;
+    h.ns = ns;
+    h.A = Mat::from(A, nx, nx);
+    h.B = Mat::from(B, nx, nu);
+    h.Gd = Mat::from(Gd, nx, nd);
+    h.E = ns > 0 ? Mat::from(E, ns, nu) : Mat(0, nu);
+    h.Ed = ns > 0 ? Mat::from(Ed, ns, nd) : Mat(0, nd);
+    h.xmin.assign(xmin, xmin + nx);
+    h.xmax.assign(xmax, xmax + nx);
+    h.xs.assign(xs, xs + nx);
+    h.umin.assign(umin, umin + nu);
+    h.umax.assign(umax, umax + nu);
+    if (ns > 0) {
+      if (!null_space_and_particular(h.E, h.Ed, h.Z, h.Pd))
+        fail(TAPG_ENUMERIC, "E does not have full row rank");
+    } else {
+      h.Z = Mat::eye(nu);
+      h.Pd = Mat(nu, nd);
+    }
+    *out = net.release();
+    return TAPG_OK;
+  });
+}
+
+void tapg_network_destroy(tapg_network net) { delete net; }
+
+static void check_tree(const TreeHost& t) {
+  // nodes_per_stage, ancestors (breadth-first, contiguous children), every
+  // leaf at stage N-1, probabilities.
+  if (t.mu[0] != 1) fail(TAPG_EINVAL, "nodes_per_stage[0] must be 1");
+  for (int s = 0; s < t.N; ++s)
+    if (t.mu[s] < 1) fail(TAPG_EINVAL, "nodes_per_stage[" + std::to_string(s) + "] < 1");
+  if (t.anc[0] != -1) fail(TAPG_EINVAL, "ancestor[0] must be -1");
+  for (int s = 1; s < t.N; ++s) {
+    int prev = -1;
+    for (int n = t.offset[s]; n < t.offset[s + 1]; ++n) {
+      const int a = t.anc[n];
+      if (a < t.offset[s - 1] || a >= t.offset[s])
+        fail(TAPG_EINVAL, "ancestor of node " + std::to_string(n) + " is not in the previous stage");
+      if (a < prev)
+        fail(TAPG_EINVAL, "children are not contiguous / breadth-first at node " + std::to_string(n));
+      prev = a;
+    }
+  }
+  for (int n = 0; n < (t.N > 1 ? t.offset[t.N - 1] : 0); ++n)
+    if (t.cend[n] <= t.cbeg[n])
+      fail(TAPG_EINVAL, "node " + std::to_string(n) + " has no child but is not at the last stage");
+  if (!(std::fabs(t.prob[0] - 1.0) <= 1e-12)) fail(TAPG_EINVAL, "prob[0] must be 1");
+  for (int n = 0; n < t.K; ++n) {
+    if (!(t.prob[n] > 0.0) || !std::isfinite(t.prob[n]))
+      fail(TAPG_EINVAL, "prob[" + std::to_string(n) + "] must be positive and finite");
+    if (t.cend[n] > t.cbeg[n]) {
+      double s = 0.0;
+      for (int c = t.cbeg[n]; c < t.cend[n]; ++c) s += t.prob[c];
+      if (!(std::fabs(s - t.prob[n]) <= 1e-12 * t.prob[n] + 1e-300))
+        fail(TAPG_EINVAL, "children's probabilities do not add up to node " + std::to_string(n));
+    }
+  }
+}
+
+tapg_status tapg_tree_create(int N, const int* nodes_per_stage, const int* ancestor,
+                             const double* prob, int nd, const double* demand, const double* price,
+                             tapg_tree* out) {
+  return guarded([&]() -> tapg_status {
+    need(out, "out");
+    *out = nullptr;
+    if (N < 1 || N > 100000) fail(TAPG_EDIM, "N must be in [1, 100000]");
+    if (nd < 1) fail(TAPG_EDIM, "nd must be >= 1");
+    need(nodes_per_stage, "nodes_per_stage");
+    need(ancestor, "ancestor");
+    need(prob, "prob");
+    need(demand, "demand");
+    need(price, "price");
+    auto tr = std::make_unique<tapg_tree_s>();
+    TreeHost& t = tr->h;
+    t.uid = g_next_uid.fetch_add(1);
+    t.version = 0;
+    t.N = N;
+    t.nd = nd;
+    t.mu.assign(nodes_per_stage, nodes_per_stage + N);
+    t.offset.assign(N + 1, 0);
+    long long K = 0;
+    for (int s = 0; s < N; ++s) {
+      if (t.mu[s] < 1) fail(TAPG_EINVAL, "nodes_per_stage[" + std::to_string(s) + "] < 1");
+      t.offset[s] = (int)K;
+      K += t.mu[s];
+      if (K > (1ll << 28)) fail(TAPG_EDIM, "tree too large");
+    }
+    t.offset[N] = (int)K;
+    t.K = (int)K;
+    t.anc.assign(ancestor, ancestor + K);
+    t.prob.assign(prob, prob + K);
+    t.stage.assign(K, 0);
+    for (int s = 0; s < N; ++s)
+      for (int n = t.offset[s]; n < t.offset[s + 1]; ++n) t.stage[n] = s;
+    for (int n = 1; n < K; ++n)
+      if (t.anc[n] < 0 || t.anc[n] >= n)
+        fail(TAPG_EINVAL, "ancestor of node " + std::to_string(n) + " out of range");
+    // first/last child of every node from the ancestors of the next stage
+    // (contiguity is checked by check_tree)
+    t.cbeg.assign(K, 0);
+    t.cend.assign(K, 0);
+    for (int s = 1; s < N; ++s) {
+      for (int n = t.offset[s]; n < t.offset[s + 1]; ++n) {
+        const int a = t.anc[n];
+        if (t.cend[a] == 0) t.cbeg[a] = n;
+        t.cend[a] = n + 1;
+      }
+    }
+    check_tree(t);
+    if (!finite_all(demand, (size_t)K * nd) || !finite_all(price, K))
+      fail(TAPG_ENUMERIC, "non-finite demand or price");
+    t.demand.assign(demand, demand + (size_t)K * nd);
+    t.price.assign(price, price + K);
+    *out = tr.release();
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_tree_set_data(tapg_tree tree, const double* demand, const double* price) {
+  return guarded([&]() -> tapg_status {
+    need(tree, "tree");
+    need(demand, "demand");
+    need(price, "price");
+    TreeHost& t = tree->h;
+    if (!finite_all(demand, (size_t)t.K * t.nd) || !finite_all(price, t.K))
+      fail(TAPG_ENUMERIC, "non-finite demand or price");
+    std::copy(demand, demand + (size_t)t.K * t.nd, t.demand.begin());
+    std::copy(price, price + t.K, t.price.begin());
+    t.version += 1;
+    return TAPG_OK;
+  });
+}
+
+int tapg_tree_num_nodes(tapg_tree tree) { return tree ? tree->h.K : -1; }
+
+void tapg_tree_destroy(tapg_tree tree) { delete tree; }
+
+tapg_status tapg_solver_create(tapg_network net, const tapg_config* cfg, tapg_solver* out) {
+  return guarded([&]() -> tapg_status {
+    need(out, "out");
+    *out = nullptr;
+    need(net, "net");
+    need(cfg, "cfg");
+    const NetworkHost& h = net->h;
+    need(cfg->alpha0, "cfg->alpha0");
+    need(cfg->c_energy, "cfg->c_energy");
+    need(cfg->W_u, "cfg->W_u");
+    if (!(cfg->W_alpha > 0) || !(cfg->W_s > 0) || !(cfg->W_x > 0))
+      fail(TAPG_EINVAL, "W_alpha, W_s and W_x must be positive");
+    if (cfg->max_iter < 1) fail(TAPG_EINVAL, "max_iter must be >= 1");
+    if (cfg->check_every < 1) fail(TAPG_EINVAL, "check_every must be >= 1");
+    if (cfg->precision != TAPG_FP64 && cfg->precision != TAPG_FP32)
+      fail(TAPG_EINVAL, "precision must be TAPG_FP64 or TAPG_FP32");
+    if (!std::isfinite(cfg->gamma) || !std::isfinite(cfg->tol)) fail(TAPG_EINVAL, "non-finite gamma/tol");
+    if (!finite_all(cfg->W_u, (size_t)h.nu * h.nu) || !finite_all(cfg->alpha0, h.nu) ||
+        !finite_all(cfg->c_energy, h.nu))
+      fail(TAPG_ENUMERIC, "non-finite weights");
+    Mat W = Mat::from(cfg->W_u, h.nu, h.nu);
+    for (int i = 0; i < h.nu; ++i)
+      for (int j = 0; j < i; ++j)
+        if (std::fabs(W(i, j) - W(j, i)) > 1e-12 * (std::fabs(W(i, j)) + std::fabs(W(j, i)) + 1e-300))
+          fail(TAPG_EINVAL, "W_u is not symmetric");
+    Mat Wc = W;
+    if (!cholesky(Wc)) fail(TAPG_ENUMERIC, "W_u is not positive definite");
+    auto S = std::make_unique<tapg_solver_s>();
+    S->net = h;
+    S->cfg = *cfg;
+    S->alpha0.assign(cfg->alpha0, cfg->alpha0 + h.nu);
+    S->cE.assign(cfg->c_energy, cfg->c_energy + h.nu);
+    S->Wu.assign(cfg->W_u, cfg->W_u + (size_t)h.nu * h.nu);
+    S->cfg.alpha0 = S->alpha0.data();
+    S->cfg.c_energy = S->cE.data();
+    S->cfg.W_u = S->Wu.data();
+    S->device = cfg->device;
+    S->stream = static_cast<hipStream_t>(cfg->hip_stream);
+    S->fp32 = cfg->precision == TAPG_FP32;
+    S->LDX = round_up(h.nx, 16);
+    S->LDU = round_up(h.nu, 16);
+    S->LDY = 2 * S->LDX + S->LDU;
+    const char* env = std::getenv("TAPG_USE_GRAPH");
+    S->use_graph = !(env && env[0] == '0');
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+      fail(TAPG_EDEVICE, "no HIP device available");
+    if (cfg->device < 0 || cfg->device >= ndev) fail(TAPG_EDEVICE, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess)
+      fail(TAPG_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      fail(TAPG_EDEVICE, std::string("this build targets gfx950; device is ") + prop.gcnArchName);
+    try {
+      dev_init(S.get());
+    } catch (...) {
+      dev_release(S.get());
+      throw;
+    }
+    *out = S.release();
+    return TAPG_OK;
+  });
+}
+
+void tapg_solver_destroy(tapg_solver solver) {
+  if (!solver) return;
+  try {
+    dev_release(solver);
+  } catch (...) {
+  }
+  delete solver;
+}
+
+tapg_status tapg_factor_step(tapg_solver solver, int N) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    if (N < 1 || N > 100000) fail(TAPG_EDIM, "N must be in [1, 100000]");
+    factor_step(solver, N);
+    dev_upload_factors(solver);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_get_factors(tapg_solver solver, int stage, double* Fbar, double* Kbar,
+                             double* Gbar) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    if (solver->N == 0) fail(TAPG_ESTATE, "factor step not run");
+    if (stage < 0 || stage >= solver->N) fail(TAPG_EINVAL, "stage out of range");
+    const size_t nn = (size_t)solver->net.nu * solver->net.nu;
+    if (Fbar) std::copy_n(solver->Fbar.begin() + stage * nn, nn, Fbar);
+    if (Kbar) std::copy_n(solver->Kbar.begin() + stage * nn, nn, Kbar);
+    if (Gbar) std::copy_n(solver->Gbar.begin() + stage * nn, nn, Gbar);
+    return TAPG_OK;
+  });
+}
+
+static void check_pair(tapg_solver solver, tapg_tree tree) {
+  need(solver, "solver");
+  need(tree, "tree");
+  if (solver->N == 0) fail(TAPG_ESTATE, "factor step not run");
+  if (tree->h.N != solver->N)
+    fail(TAPG_EDIM, "tree horizon " + std::to_string(tree->h.N) + " != factored horizon " +
+                        std::to_string(solver->N));
+  if (tree->h.nd != solver->net.nd) fail(TAPG_EDIM, "tree nd does not match the network");
+}
+
+static double solver_gamma(tapg_solver solver, const TreeHost& t, Slot& sl) {
+  if (solver->cfg.gamma > 0) return solver->cfg.gamma;
+  if (!sl.L_valid) {
+    const int it = solver->cfg.power_iters > 0 ? solver->cfg.power_iters : 100;
+    sl.L = dev_power(solver, t, sl, it);
+    if (!(sl.L > 0) || !std::isfinite(sl.L)) fail(TAPG_ENUMERIC, "power iteration failed");
+    sl.L_valid = true;
+  }
+  return 1.0 / (1.02 * sl.L);
+}
+
+tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, const double* q,
+                       int warm_start, double* u0_out, tapg_result* res) {
+  return guarded([&]() -> tapg_status {
+    check_pair(solver, tree);
+    need(p, "p");
+    need(q, "q");
+    if (!finite_all(p, solver->net.nx) || !finite_all(q, solver->net.nu))
+      fail(TAPG_ENUMERIC, "non-finite p or q");
+    const TreeHost& t = tree->h;
+    Slot& sl = dev_slot(solver, t);
+    const double gamma = solver_gamma(solver, t, sl);
+    tapg_result r{};
+    dev_solve(solver, t, sl, p, q, warm_start != 0, gamma, r);
+    if (u0_out) dev_get_root_input(solver, sl, u0_out);  // the root is node 0
+    if (res) *res = r;
+    return r.converged || solver->cfg.tol <= 0 ? TAPG_OK : TAPG_ENOTCONV;
+  });
+}
+
+static Slot& existing_slot(tapg_solver solver, tapg_tree tree) {
+  check_pair(solver, tree);
+  auto it = solver->slots.find(tree->h.uid);
+  if (it == solver->slots.end() || !it->second.has_result)
+    fail(TAPG_ESTATE, "tree has not been solved on this solver");
+  return it->second;
+}
+
+tapg_status tapg_get_primal(tapg_solver solver, tapg_tree tree, double* u, double* x) {
+  return guarded([&]() -> tapg_status {
+    Slot& sl = existing_slot(solver, tree);
+    dev_get_primal(solver, sl, u, x);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_get_dual(tapg_solver solver, tapg_tree tree, double* y) {
+  return guarded([&]() -> tapg_status {
+    need(y, "y");
+    check_pair(solver, tree);
+    auto it = solver->slots.find(tree->h.uid);
+    if (it == solver->slots.end() || !it->second.has_dual)
+      fail(TAPG_ESTATE, "no dual iterate for this tree");
+    dev_get_dual(solver, it->second, y);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_set_dual(tapg_solver solver, tapg_tree tree, const double* y) {
+  return guarded([&]() -> tapg_status {
+    need(y, "y");
+    check_pair(solver, tree);
+    const size_t m = (size_t)tree->h.K * (2 * solver->net.nx + solver->net.nu);
+    if (!finite_all(y, m)) fail(TAPG_ENUMERIC, "non-finite dual");
+    Slot& sl = dev_slot(solver, tree->h);
+    dev_set_dual(solver, sl, y);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_residual_history(tapg_solver solver, tapg_tree tree, double* hist, int n,
+                                  int* written) {
+  return guarded([&]() -> tapg_status {
+    need(hist, "hist");
+    Slot& sl = existing_slot(solver, tree);
+    const int w = dev_get_history(solver, sl, hist, std::max(0, n));
+    if (written) *written = w;
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_residuals(tapg_solver solver, tapg_tree tree, tapg_result* res) {
+  return guarded([&]() -> tapg_status {
+    need(res, "res");
+    Slot& sl = existing_slot(solver, tree);
+    *res = sl.last;
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iters, double* L) {
+  return guarded([&]() -> tapg_status {
+    need(L, "L");
+    check_pair(solver, tree);
+    if (iters < 1) fail(TAPG_EINVAL, "iters must be >= 1");
+    Slot& sl = dev_slot(solver, tree->h);
+    *L = dev_power(solver, tree->h, sl, iters);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_kernel_timing(tapg_solver solver, int enable) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    dev_set_kernel_timing(solver, enable != 0);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_kernel_times(tapg_solver solver, double* ms, long long* launches) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    need(ms, "ms");
+    need(launches, "launches");
+    for (int k = 0; k < 3; ++k) {
+      ms[k] = solver->kt_ms[k];
+      launches[k] = solver->kt_n[k];
+    }
+    return TAPG_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Internal declarations of the tapg library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tapg.h"
+
+namespace tapg {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Fail {
+  tapg_status code;
+  std::string msg;
+};
+
+#define TAPG_HIP(call)                                                          \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      throw ::tapg::Fail{TAPG_EDEVICE, std::string(#call) + ": " +              \
+                                           hipGetErrorString(e_)};              \
+  } while (0)
+
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// ---------------------------------------------------------------------------
+// Host dense linear algebra (row-major, FP64), used by the offline factor step
+// ---------------------------------------------------------------------------
+struct Mat {
+  int r = 0, c = 0;
+  std::vector<double> a;
+  Mat() = default;
+  Mat(int rows, int cols) : r(rows), c(cols), a((size_t)rows * cols, 0.0) {}
+  double& operator()(int i, int j) { return a[(size_t)i * c + j]; }
+  double operator()(int i, int j) const { return a[(size_t)i * c + j]; }
+  static Mat eye(int n);
+  static Mat from(const double* p, int rows, int cols);
+};
+
+Mat matmul(const Mat& A, const Mat& B);
+Mat transpose(const Mat& A);
+Mat add(const Mat& A, const Mat& B, double beta = 1.0);  // A + beta B
+// Householder QR of E' (nu x ns).  Returns false if E is rank deficient.
+// Z (nu x m) spans ker E with orthonormal columns; Pd = -E^+ Ed (nu x nd).
+bool null_space_and_particular(const Mat& E, const Mat& Ed, Mat& Z, Mat& Pd);
+// In-place Cholesky (lower); false if not positive definite.
+bool cholesky(Mat& M);
+// Solve (L L') X = B in place of B, L from cholesky().
+void chol_solve(const Mat& L, Mat& B);
+
+// ---------------------------------------------------------------------------
+// Host objects behind the opaque handles
+// ---------------------------------------------------------------------------
+struct NetworkHost {
+  int nx, nu, nd, ns;
+  Mat A, B, Gd, E, Ed;
+  std::vector<double> xmin, xmax, xs, umin, umax;
+  Mat Z, Pd;  // ker E basis and -E^+ Ed
+};
+
+struct TreeHost {
+  uint64_t uid;       // unique id, never reused
+  uint64_t version;   // bumped by set_data
+  int N, K, nd;
+  std::vector<int> mu, offset, anc, cbeg, cend, stage;
+  std::vector<double> prob, demand, price;
+};
+
+// Device control block of one tree slot (read by every kernel, written by
+// the per-iteration end kernel).
+struct DevCtl {
+  int iter;         // iterations completed
+  int done;         // stop flag
+  int converged;    // residual reached tol
+  int numeric;      // non-finite residual seen
+  int max_iter;
+  int pad0;
+  double tol;
+  double gamma;
+  double theta, theta_prev, beta;
+  double last_res;
+  unsigned long long res_bits;  // running max |r| of the current iteration (bits of a double >= 0)
+  double pw_scale;              // power iteration: 1/|v|
+  double L;                     // power iteration: latest |M v| estimate
+};
+
+// Per-(solver, tree) device buffers.
+struct Slot {
+  uint64_t tree_uid = 0, data_version = ~0ull;
+  int K = 0, N = 0;
+  size_t elem = 8;  // sizeof(T) of the sweep buffers
+  // structure
+  int *d_anc = nullptr, *d_cbeg = nullptr, *d_cend = nullptr, *d_stage = nullptr;
+  double* d_prob64 = nullptr;
+  void* d_invp = nullptr;  // T[K]
+  // data
+  double *d_demand = nullptr, *d_price = nullptr;
+  void *d_kappa = nullptr, *d_g = nullptr, *d_pq = nullptr;
+  double* d_pq64 = nullptr;
+  void *d_P0 = nullptr, *d_P1 = nullptr;  // power-iteration vectors
+  // iterates
+  void *d_Y0 = nullptr, *d_Y1 = nullptr, *d_lam = nullptr, *d_j = nullptr, *d_u = nullptr,
+       *d_x = nullptr;
+  DevCtl* d_ctl = nullptr;
+  double* d_hist = nullptr;
+  int hist_cap = 0;
+  double* d_part = nullptr;  // per-tile partials (power iteration) and per-node cost terms
+  int part_cap = 0;
+  // tiling per stage: node range [node_offset[s], node_offset[s+1]) in tiles of
+  // nb_of_stage[s] nodes; tile_offset[s] numbers the tiles across stages
+  std::vector<int> node_offset, nb_of_stage, tiles_of_stage, tile_offset;
+  int total_tiles = 0;
+  // state
+  bool has_dual = false;
+  int last_iter_parity = 0;
+  double L = 0.0;
+  bool L_valid = false;
+  tapg_result last{};
+  bool has_result = false;
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+};
+
+struct SolverState;
+
+// Device-side pieces of a solver (defined in solver.hip).
+struct DeviceNet;
+
+}  // namespace tapg
+
+struct tapg_network_s {
+  tapg::NetworkHost h;
+};
+
+struct tapg_tree_s {
+  tapg::TreeHost h;
+};

@@ -1,0 +1,76 @@
+// Solver object shared by the C-ABI layer (api.cpp) and the device layer
+// (solver.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace tapg {
+
+template <typename T>
+struct NetDev {
+  // Sweep operands, column-major (element (r, k) at [k * ld + r]):
+  // At = A' (nx x nx, ld LDX), Bt = B' (nu x nx, ld LDU), A (nx x nx, ld LDX),
+  // B (nx x nu, ld LDX); stage factors Fbar, Kbar (N blocks of nu x nu, ld LDU).
+  T *At = nullptr, *Bt = nullptr, *A = nullptr, *B = nullptr;
+  T *xmin = nullptr, *xmax = nullptr, *xs = nullptr, *umin = nullptr, *umax = nullptr;
+  T *F = nullptr, *Kb = nullptr;
+};
+
+struct DevExtra {
+  // FP64 operands of the data step and of the cost evaluation.
+  double *Gd = nullptr;    // nx x nd, col-major ld LDX
+  double *Pd = nullptr;    // nu x nd, col-major ld LDU  (-E^+ Ed)
+  double *Gbar = nullptr;  // N x (nu x nu), col-major ld LDU
+  double *E = nullptr;     // ns x nu row-major
+  double *Ed = nullptr;    // ns x nd row-major
+  double *Wu = nullptr;    // nu x nu col-major ld LDU
+  double *alpha0 = nullptr, *cE = nullptr;  // LDU
+  double *red = nullptr;   // 8 doubles of reduction output
+};
+
+}  // namespace tapg
+
+struct tapg_solver_s {
+  tapg::NetworkHost net;
+  tapg_config cfg;
+  std::vector<double> alpha0, cE, Wu;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int LDX = 0, LDU = 0, LDY = 0;
+  int N = 0;  // horizon of the factor step, 0 = not factored
+  std::vector<double> Fbar, Kbar, Gbar;  // host FP64, N blocks of nu*nu row-major
+  bool fp32 = false;
+  tapg::NetDev<double> d64;
+  tapg::NetDev<float> d32;
+  tapg::DevExtra dx;
+  std::map<uint64_t, tapg::Slot> slots;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool use_graph = true;
+  // optional per-launch timing of the sweep kernels (HIP events around each
+  // launch; graphs are bypassed while it is on)
+  bool time_kernels = false;
+  std::vector<hipEvent_t> tev;      // pairs, reused per chunk
+  double kt_ms[3] = {0, 0, 0};      // backward stages, forward stages, iteration end
+  long long kt_n[3] = {0, 0, 0};
+};
+
+namespace tapg {
+
+// Device layer (solver.hip).
+void dev_init(tapg_solver_s* S);             // streams, events, network buffers
+void dev_release(tapg_solver_s* S);          // frees everything the solver owns
+void dev_upload_factors(tapg_solver_s* S);   // Fbar/Kbar/Gbar to the device
+Slot& dev_slot(tapg_solver_s* S, const TreeHost& t);  // allocate/upload as needed
+void dev_solve(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
+               const double* q, bool warm, double gamma, tapg_result& res);
+double dev_power(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters);
+void dev_get_primal(tapg_solver_s* S, Slot& sl, double* u, double* x);
+void dev_get_dual(tapg_solver_s* S, Slot& sl, double* y);
+void dev_get_root_input(tapg_solver_s* S, Slot& sl, double* u0);
+void dev_set_dual(tapg_solver_s* S, Slot& sl, const double* y);
+int dev_get_history(tapg_solver_s* S, Slot& sl, double* h, int n);
+void dev_set_kernel_timing(tapg_solver_s* S, bool on);
+void dev_free_slot(Slot& sl);
+
+}  // namespace tapg

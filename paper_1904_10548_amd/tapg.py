@@ -1,0 +1,353 @@
+"""ctypes binding of the tapg C ABI (``include/tapg.h``).
+
+Functions carry the C names and only marshal arguments: numpy arrays become
+float64/int32 pointers, status codes become :class:`TapgError`.  Every
+computation runs inside ``libtapg.so`` (HIP kernels for gfx950 and the
+library's host code); there is no Python or CPU fallback: if the library is
+missing, :func:`lib` raises.
+
+:class:`Solver` is a small owner object over the handles for tests and
+benchmarks.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtapg.so")
+
+TAPG_OK = 0
+TAPG_ENOTCONV = 1
+TAPG_EINVAL = -1
+TAPG_EDIM = -2
+TAPG_ENOMEM = -3
+TAPG_EDEVICE = -4
+TAPG_ESTATE = -5
+TAPG_ENUMERIC = -6
+TAPG_FP64 = 0
+TAPG_FP32 = 1
+
+EXPORTED = [
+    "tapg_network_create", "tapg_network_destroy", "tapg_tree_create", "tapg_tree_set_data",
+    "tapg_tree_num_nodes", "tapg_tree_destroy", "tapg_solver_create", "tapg_solver_destroy",
+    "tapg_factor_step", "tapg_get_factors", "tapg_solve", "tapg_get_primal", "tapg_get_dual",
+    "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
+    "tapg_kernel_timing", "tapg_kernel_times", "tapg_last_error", "tapg_version",
+]
+
+
+class TapgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"tapg status {status}: {message}")
+        self.status = status
+
+
+class TapgConfig(ctypes.Structure):
+    _fields_ = [
+        ("W_alpha", ctypes.c_double),
+        ("W_s", ctypes.c_double),
+        ("W_x", ctypes.c_double),
+        ("alpha0", ctypes.POINTER(ctypes.c_double)),
+        ("c_energy", ctypes.POINTER(ctypes.c_double)),
+        ("W_u", ctypes.POINTER(ctypes.c_double)),
+        ("gamma", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("check_every", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("power_iters", ctypes.c_int),
+        ("device", ctypes.c_int),
+        ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class TapgResult(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("primal_res", ctypes.c_double),
+        ("cost", ctypes.c_double),
+        ("viol_box", ctypes.c_double),
+        ("viol_eq", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libtapg.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1904_10548_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "tapg_network_create": ([ctypes.c_int] * 4 + [_D] * 10 + [ctypes.POINTER(_P)], ctypes.c_int),
+        "tapg_network_destroy": ([_P], None),
+        "tapg_tree_create": ([ctypes.c_int, _I, _I, _D, ctypes.c_int, _D, _D, ctypes.POINTER(_P)],
+                             ctypes.c_int),
+        "tapg_tree_set_data": ([_P, _D, _D], ctypes.c_int),
+        "tapg_tree_num_nodes": ([_P], ctypes.c_int),
+        "tapg_tree_destroy": ([_P], None),
+        "tapg_solver_create": ([_P, ctypes.POINTER(TapgConfig), ctypes.POINTER(_P)], ctypes.c_int),
+        "tapg_solver_destroy": ([_P], None),
+        "tapg_factor_step": ([_P, ctypes.c_int], ctypes.c_int),
+        "tapg_get_factors": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
+        "tapg_solve": ([_P, _P, _D, _D, ctypes.c_int, _D, ctypes.POINTER(TapgResult)], ctypes.c_int),
+        "tapg_get_primal": ([_P, _P, _D, _D], ctypes.c_int),
+        "tapg_get_dual": ([_P, _P, _D], ctypes.c_int),
+        "tapg_set_dual": ([_P, _P, _D], ctypes.c_int),
+        "tapg_residual_history": ([_P, _P, _D, ctypes.c_int, _I], ctypes.c_int),
+        "tapg_residuals": ([_P, _P, ctypes.POINTER(TapgResult)], ctypes.c_int),
+        "tapg_estimate_lipschitz": ([_P, _P, ctypes.c_int, _D], ctypes.c_int),
+        "tapg_kernel_timing": ([_P, ctypes.c_int], ctypes.c_int),
+        "tapg_kernel_times": ([_P, _D, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+        "tapg_last_error": ([], ctypes.c_char_p),
+        "tapg_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, ret) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ret
+    _lib = L
+    return L
+
+
+def _f64(a, n=None):
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and arr.size != n:
+        raise ValueError(f"expected {n} values, got {arr.size}")
+    return arr
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _check(status: int, allow=(TAPG_OK,)):
+    if status not in allow:
+        raise TapgError(status, lib().tapg_last_error().decode())
+    return status
+
+
+# --------------------------------------------------------------------------
+# C-named functions
+# --------------------------------------------------------------------------
+def tapg_version() -> str:
+    return lib().tapg_version().decode()
+
+
+def tapg_last_error() -> str:
+    return lib().tapg_last_error().decode()
+
+
+def tapg_network_create(A, B, Gd, E, Ed, xmin, xmax, xs, umin, umax):
+    A, B, Gd = _f64(A), _f64(B), _f64(Gd)
+    nx, nu = B.shape
+    nd = Gd.shape[1]
+    E = _f64(E).reshape(-1, nu)
+    ns = E.shape[0]
+    Ed = _f64(Ed).reshape(ns, nd)
+    arrs = [A, B, Gd, E, Ed, _f64(xmin, nx), _f64(xmax, nx), _f64(xs, nx), _f64(umin, nu),
+            _f64(umax, nu)]
+    out = _P()
+    _check(lib().tapg_network_create(nx, nu, nd, ns, *[_ptr(a) for a in arrs], ctypes.byref(out)))
+    return out
+
+
+def tapg_network_destroy(h):
+    lib().tapg_network_destroy(h)
+
+
+def tapg_tree_create(nodes_per_stage, ancestor, prob, demand, price):
+    mu = np.ascontiguousarray(nodes_per_stage, dtype=np.int32)
+    anc = np.ascontiguousarray(ancestor, dtype=np.int32)
+    K = int(mu.sum())
+    if anc.size != K:
+        raise ValueError("ancestor must have sum(nodes_per_stage) entries")
+    demand = _f64(demand).reshape(K, -1)
+    prob = _f64(prob, K)
+    price = _f64(price, K)
+    out = _P()
+    _check(lib().tapg_tree_create(len(mu), mu.ctypes.data_as(_I), anc.ctypes.data_as(_I),
+                                  _ptr(prob), demand.shape[1], _ptr(demand), _ptr(price),
+                                  ctypes.byref(out)))
+    return out
+
+
+def tapg_tree_set_data(tree, demand, price):
+    K = lib().tapg_tree_num_nodes(tree)
+    demand = _f64(demand)
+    if demand.size % max(K, 1):
+        raise ValueError("demand must have K*nd values")
+    _check(lib().tapg_tree_set_data(tree, _ptr(demand), _ptr(_f64(price, K))))
+
+
+def tapg_tree_num_nodes(tree) -> int:
+    return lib().tapg_tree_num_nodes(tree)
+
+
+def tapg_tree_destroy(h):
+    lib().tapg_tree_destroy(h)
+
+
+def make_config(nu, W_alpha, W_s, W_x, alpha0, c_energy, W_u, gamma=0.0, tol=1e-4,
+                max_iter=10000, check_every=100, precision=TAPG_FP64, power_iters=100,
+                device=0, stream=None):
+    """A :class:`TapgConfig` plus the arrays it points to (keep both alive)."""
+    keep = [_f64(alpha0, nu), _f64(c_energy, nu), _f64(W_u, nu * nu)]
+    cfg = TapgConfig(W_alpha, W_s, W_x, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), gamma, tol,
+                     max_iter, check_every, precision, power_iters, device,
+                     ctypes.c_void_p(stream) if stream else None)
+    return cfg, keep
+
+
+def tapg_solver_create(net, cfg: TapgConfig):
+    out = _P()
+    _check(lib().tapg_solver_create(net, ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def tapg_solver_destroy(h):
+    lib().tapg_solver_destroy(h)
+
+
+def tapg_factor_step(solver, N: int):
+    _check(lib().tapg_factor_step(solver, int(N)))
+
+
+def tapg_get_factors(solver, stage: int, nu: int):
+    F, Kb, G = (np.zeros((nu, nu)) for _ in range(3))
+    _check(lib().tapg_get_factors(solver, stage, _ptr(F), _ptr(Kb), _ptr(G)))
+    return F, Kb, G
+
+
+def tapg_solve(solver, tree, p, q, warm_start=False, nu=None):
+    """Returns ``(status, u0, result)``; status is TAPG_OK or TAPG_ENOTCONV."""
+    q = _f64(q)
+    u0 = np.zeros(q.size if nu is None else nu)
+    res = TapgResult()
+    st = _check(lib().tapg_solve(solver, tree, _ptr(_f64(p)), _ptr(q), int(bool(warm_start)),
+                                 _ptr(u0), ctypes.byref(res)), allow=(TAPG_OK, TAPG_ENOTCONV))
+    return st, u0, res
+
+
+def tapg_get_primal(solver, tree, K, nx, nu):
+    u = np.zeros((K, nu))
+    x = np.zeros((K, nx))
+    _check(lib().tapg_get_primal(solver, tree, _ptr(u), _ptr(x)))
+    return u, x
+
+
+def tapg_get_dual(solver, tree, K, m):
+    y = np.zeros((K, m))
+    _check(lib().tapg_get_dual(solver, tree, _ptr(y)))
+    return y
+
+
+def tapg_set_dual(solver, tree, y):
+    _check(lib().tapg_set_dual(solver, tree, _ptr(_f64(y))))
+
+
+def tapg_residual_history(solver, tree, n):
+    h = np.zeros(max(n, 1))
+    w = ctypes.c_int(0)
+    _check(lib().tapg_residual_history(solver, tree, _ptr(h), n, ctypes.byref(w)))
+    return h[:w.value]
+
+
+def tapg_residuals(solver, tree) -> TapgResult:
+    r = TapgResult()
+    _check(lib().tapg_residuals(solver, tree, ctypes.byref(r)))
+    return r
+
+
+def tapg_estimate_lipschitz(solver, tree, iters=100) -> float:
+    L = ctypes.c_double(0.0)
+    _check(lib().tapg_estimate_lipschitz(solver, tree, int(iters), ctypes.byref(L)))
+    return L.value
+
+
+def tapg_kernel_timing(solver, enable: bool):
+    _check(lib().tapg_kernel_timing(solver, int(bool(enable))))
+
+
+def tapg_kernel_times(solver):
+    """``{'bwd': (ms, launches), 'fwd': (...), 'end': (...)}`` of the last timed solve."""
+    ms = np.zeros(3)
+    n = (ctypes.c_longlong * 3)()
+    _check(lib().tapg_kernel_times(solver, _ptr(ms), n))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(["bwd", "fwd", "end"])}
+
+
+# --------------------------------------------------------------------------
+# Owner object
+# --------------------------------------------------------------------------
+class Solver:
+    """Network + solver handles for one set of weights; trees are added with
+    :meth:`add_tree` and released with the solver."""
+
+    def __init__(self, net_arrays: dict, weights: dict, N: int, **cfg_kw):
+        self.nx = int(np.asarray(net_arrays["B"]).shape[0])
+        self.nu = int(np.asarray(net_arrays["B"]).shape[1])
+        self.net = tapg_network_create(**net_arrays)
+        self.cfg, self._keep = make_config(self.nu, **weights, **cfg_kw)
+        try:
+            self.h = tapg_solver_create(self.net, self.cfg)
+        except Exception:
+            tapg_network_destroy(self.net)
+            raise
+        self.trees = []
+        tapg_factor_step(self.h, N)
+
+    def add_tree(self, nodes_per_stage, ancestor, prob, demand, price):
+        t = tapg_tree_create(nodes_per_stage, ancestor, prob, demand, price)
+        self.trees.append(t)
+        return t
+
+    def solve(self, tree, p, q, warm_start=False):
+        return tapg_solve(self.h, tree, p, q, warm_start, nu=self.nu)
+
+    def primal(self, tree):
+        return tapg_get_primal(self.h, tree, tapg_tree_num_nodes(tree), self.nx, self.nu)
+
+    def dual(self, tree):
+        return tapg_get_dual(self.h, tree, tapg_tree_num_nodes(tree), 2 * self.nx + self.nu)
+
+    def close(self):
+        if getattr(self, "h", None):
+            tapg_solver_destroy(self.h)
+            self.h = None
+        for t in self.trees:
+            tapg_tree_destroy(t)
+        self.trees = []
+        if getattr(self, "net", None):
+            tapg_network_destroy(self.net)
+            self.net = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

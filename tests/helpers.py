@@ -8,12 +8,14 @@ from dwn_synth.generate import make_network, make_node_data, make_tree, make_wei
 
 
 def tiny_problem(N=3, b1=2, S=2, seed=7, p_level=5.0, price_scale=1.0, irregular=False,
-                 max_children=3, max_width=64):
-    """Small-network instance (nx=4, nu=6, nd=3, ns=2) on a short tree."""
+                 max_children=3, max_width=64, wu=1.0):
+    """Small-network instance (nx=4, nu=6, nd=3, ns=2) on a short tree, with
+    ``W_u = wu I``."""
     ss = np.random.SeedSequence(seed)
     rn, rt, rd = [np.random.default_rng(s) for s in ss.spawn(3)]
     net = make_network(rn, 4, 6, 3, 2, 4)
     w = make_weights(rn, net)
+    w.W_u = wu * np.eye(net.nu)
     if irregular:
         tree = make_irregular_tree(rt, N, max_children, max_width)
     else:

@@ -1,0 +1,116 @@
+"""The C-ABI library: it loads, exports every declared symbol, and rejects
+invalid networks and trees on the host (no GPU needed for these calls)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import dwn_synth as ds
+from paper_1904_10548_amd import tapg
+
+from helpers import tiny_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tapg.h")).read()
+    return sorted(set(re.findall(r"\b(tapg_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tapg.lib()
+    decl = _declared()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) == set(tapg.EXPORTED)
+    assert "gfx950" in tapg.tapg_version()
+
+
+def _net_args(P):
+    n = P.net
+    return [n.A, n.B, n.Gd, n.E, n.Ed, n.xmin, n.xmax, n.xs, n.umin, n.umax]
+
+
+def test_network_create_and_validation():
+    P = ds.config_problem("small")
+    h = tapg.tapg_network_create(*_net_args(P))
+    tapg.tapg_network_destroy(h)
+    # rank-deficient E
+    bad = _net_args(P)
+    bad[3] = np.vstack([P.net.E[0], P.net.E[0]])
+    with pytest.raises(tapg.TapgError) as e:
+        tapg.tapg_network_create(*bad)
+    assert e.value.status == tapg.TAPG_ENUMERIC
+    # umin > umax
+    bad = _net_args(P)
+    bad[8] = P.net.umax + 1.0
+    with pytest.raises(tapg.TapgError) as e:
+        tapg.tapg_network_create(*bad)
+    assert e.value.status == tapg.TAPG_EINVAL
+    # non-finite
+    bad = _net_args(P)
+    bad[0] = P.net.A.copy()
+    bad[0][0, 0] = np.nan
+    with pytest.raises(tapg.TapgError):
+        tapg.tapg_network_create(*bad)
+
+
+def _tree_args(P):
+    t = P.tree
+    return [t.nodes_per_stage.copy(), t.anc.copy(), t.prob.copy(), P.data.demand.copy(),
+            P.data.price.copy()]
+
+
+def test_tree_create_valid_and_irregular():
+    for P in [ds.config_problem("small"), tiny_problem(N=5, irregular=True, seed=3),
+              ds.config_problem("dwn128")]:
+        h = tapg.tapg_tree_create(*_tree_args(P))
+        assert tapg.tapg_tree_num_nodes(h) == P.tree.K
+        tapg.tapg_tree_set_data(h, P.data.demand * 1.1, P.data.price)
+        tapg.tapg_tree_destroy(h)
+
+
+@pytest.mark.parametrize("case", ["prob_sum", "root_prob", "not_bfs", "leaf_early", "anc_range",
+                                  "mu0", "neg_prob"])
+def test_tree_validation_errors(case):
+    P = ds.config_problem("small")
+    mu, anc, prob, dem, price = _tree_args(P)
+    if case == "prob_sum":
+        prob[5] *= 1.01
+    elif case == "root_prob":
+        prob[0] = 0.9
+    elif case == "not_bfs":
+        # stage 2 nodes 3..6 have parents 1,1,2,2; swap to make them non-contiguous
+        anc[3], anc[5] = anc[5], anc[3]
+    elif case == "leaf_early":
+        # the last stage-4 node loses its child: give it to the previous node
+        anc[-1] = anc[-2]
+        prob[-1] = prob[-1]
+    elif case == "anc_range":
+        anc[4] = 99
+    elif case == "mu0":
+        mu = mu.copy()
+        mu[0], mu[1] = 2, mu[1] - 1
+    elif case == "neg_prob":
+        prob[7] = -prob[7]
+    with pytest.raises(tapg.TapgError) as e:
+        tapg.tapg_tree_create(mu, anc, prob, dem, price)
+    assert e.value.status in (tapg.TAPG_EINVAL, tapg.TAPG_EDIM)
+    assert tapg.tapg_last_error() != ""
+
+
+def test_null_handles_are_errors():
+    L = tapg.lib()
+    assert L.tapg_factor_step(None, 4) == tapg.TAPG_EINVAL
+    assert L.tapg_tree_num_nodes(None) == -1
+    r = tapg.TapgResult()
+    assert L.tapg_residuals(None, None, ctypes.byref(r)) == tapg.TAPG_EINVAL
+    # destroy functions accept NULL
+    L.tapg_tree_destroy(None)
+    L.tapg_network_destroy(None)
+    L.tapg_solver_destroy(None)

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Bars (FP64): primal iterates and duals agree elementwise to 1e-9 of their
+scale, cost to 1e-6 relative and constraint violations to 1e-6 (the stated
+accuracy of the method's FP64 implementation); rounding-order differences
+between the two sides are ~1e-13 here, so the bars leave margin without
+hiding a wrong term.  FP32 sweeps: cost within 1e-4 relative of the FP64
+oracle.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import dwn_synth as ds
+import oracle as O
+from paper_1904_10548_amd import tapg
+
+from gpu_helpers import add_tree, make_solver
+from helpers import tiny_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_run(P, gamma, iters, tol=None, factors=None):
+    f = factors or O.StageFactors(P.net, P.weights.W_u, P.tree)
+    return O.apg(P, gamma, f, iters, tol=tol)
+
+
+def _compare_fixed(P, gamma, iters, precision=tapg.TAPG_FP64, check_every=50, graph=True):
+    os.environ["TAPG_USE_GRAPH"] = "1" if graph else "0"
+    say(P.name, "K", P.tree.K, "iters", iters, "prec", precision, "graph", graph)
+    with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=check_every,
+                     precision=precision) as S:
+        t = add_tree(S, P)
+        st, u0, res = S.solve(t, P.p, P.q)
+        u, x = S.primal(t)
+        y = S.dual(t)
+        hist = tapg.tapg_residual_history(S.h, t, iters)
+    ref = _oracle_run(P, gamma, iters)
+    return st, u0, res, u, x, y, hist, ref
+
+
+def _assert_fp64_parity(P, res, u, x, y, hist, ref, iters):
+    assert res.iters == iters
+    su = max(1.0, np.abs(ref.u).max())
+    sx = max(1.0, np.abs(ref.x).max())
+    sy = max(1.0, np.abs(ref.y).max())
+    assert np.abs(u - ref.u).max() <= 1e-9 * su
+    assert np.abs(x - ref.x).max() <= 1e-9 * sx
+    assert np.abs(y - ref.y).max() <= 1e-9 * sy
+    J = O.primal_cost(P, ref.u, ref.x)
+    vb, ve = O.violations(P, ref.u, ref.x)
+    assert abs(res.cost - J) <= 1e-6 * max(1.0, abs(J))
+    assert abs(res.viol_box - vb) <= 1e-6
+    assert res.viol_eq <= 1e-9 and ve <= 1e-9
+    rh = np.asarray(ref.res_hist)
+    assert np.allclose(hist, rh, rtol=1e-7, atol=1e-12)
+    assert abs(res.primal_res - rh[-1]) <= 1e-7 * max(rh[-1], 1e-12)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_small_500_iterations_fp64(graph):
+    """The small configuration at exactly 500 iterations (no early stop)."""
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 500, graph=graph)
+    assert st == tapg.TAPG_OK
+    _assert_fp64_parity(P, res, u, x, y, hist, ref, 500)
+    assert np.abs(u0 - ref.u[0]).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())
+
+
+def test_irregular_tree_general_A_Wu_fp64():
+    """Irregular branching, non-identity A and dense W_u (generic paths)."""
+    P = tiny_problem(N=6, irregular=True, seed=31, max_children=3, max_width=40)
+    rng = np.random.default_rng(2)
+    P.net.A = np.eye(4) + 0.05 * rng.standard_normal((4, 4))
+    G = rng.standard_normal((6, 6))
+    P.weights.W_u = G @ G.T + 3 * np.eye(6)
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 0.9 / O.lipschitz_power(P, sf, 300)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 300)
+    _assert_fp64_parity(P, res, u, x, y, hist, ref, 300)
+
+
+def test_wide_ragged_tree_fp64_and_fp32():
+    """Stages wide enough for multi-node tiles, with ragged last tiles."""
+    P = tiny_problem(N=5, irregular=True, seed=8, max_children=40, max_width=2500)
+    widths = P.tree.nodes_per_stage
+    assert widths.max() >= 1024 and any(w % 8 for w in widths)
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 0.9 / O.lipschitz_power(P, sf, 200)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 60)
+    _assert_fp64_parity(P, res, u, x, y, hist, ref, 60)
+    st, u0, r32, u, x, y, hist, ref = _compare_fixed(P, gamma, 60, precision=tapg.TAPG_FP32)
+    J = O.primal_cost(P, ref.u, ref.x)
+    assert abs(r32.cost - J) <= 1e-4 * max(1.0, abs(J))
+
+
+def test_dwn128_fixed_iterations_fp64():
+    """Full-size network and tree (K = 2429): 40 iterations, every element."""
+    P = ds.config_problem("dwn128")
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 60))
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40)
+    _assert_fp64_parity(P, res, u, x, y, hist, ref, 40)
+
+
+def test_small_converged_matches_oracle_iteration_count():
+    """Run to a tolerance: same stopping iteration and result as the oracle."""
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    tol = 1e-5
+    ref = _oracle_run(P, gamma, 20000, tol=tol, factors=nf)
+    say("small converged", ref.iters)
+    with make_solver(P, gamma=gamma, tol=tol, max_iter=20000, check_every=64) as S:
+        t = add_tree(S, P)
+        st, u0, res = S.solve(t, P.p, P.q)
+        u, x = S.primal(t)
+    assert st == tapg.TAPG_OK and res.converged
+    assert abs(res.iters - ref.iters) <= 1
+    J = O.primal_cost(P, ref.u, ref.x)
+    assert abs(res.cost - J) <= 1e-6 * max(1.0, abs(J))
+    if res.iters == ref.iters:
+        assert np.abs(u - ref.u).max() <= 1e-8
+
+
+def test_factor_step_matches_oracle_stage_factors():
+    P = ds.config_problem("dwn128")
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    with make_solver(P, gamma=1e-3, tol=0.0, max_iter=1) as S:
+        for s in [0, 11, 23]:
+            F, Kb, G = tapg.tapg_get_factors(S.h, s, P.net.nu)
+            assert np.abs(F - sf.Fbar[s]).max() <= 1e-11 * np.abs(sf.Fbar[s]).max()
+            assert np.abs(Kb - sf.Kbar[s]).max() <= 1e-11 * max(1.0, np.abs(sf.Kbar[s]).max())
+            assert np.abs(G - sf.Gbar[s]).max() <= 1e-11 * max(1.0, np.abs(sf.Gbar[s]).max())
+
+
+def test_power_iteration_lipschitz():
+    """Device power iteration approaches the largest eigenvalue from below."""
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    L = O.lipschitz_dense(P, nf)
+    with make_solver(P, gamma=1e-3, tol=0.0, max_iter=1) as S:
+        t = add_tree(S, P)
+        Lg = tapg.tapg_estimate_lipschitz(S.h, t, 400)
+    assert Lg <= L * (1 + 1e-10)
+    assert Lg >= L * (1 - 1e-6)
+
+
+def test_auto_gamma_and_warm_start():
+    """gamma = 0 selects 1/(1.02 L); a warm-started re-solve of the same data
+    needs fewer iterations and returns the same answer within the tolerance;
+    get/set dual round-trips."""
+    P = ds.config_problem("small")
+    with make_solver(P, gamma=0.0, tol=1e-4, max_iter=20000, check_every=50) as S:
+        t = add_tree(S, P)
+        st, u0, r1 = S.solve(t, P.p, P.q)
+        nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+        L = O.lipschitz_dense(P, nf)
+        assert abs(r1.gamma - 1.0 / (1.02 * L)) <= 1e-6 * r1.gamma
+        y1 = S.dual(t)
+        st, u0b, r2 = S.solve(t, P.p, P.q, warm_start=True)
+        assert r2.iters < r1.iters
+        assert abs(r2.cost - r1.cost) <= 1e-3 * max(1.0, abs(r1.cost))
+        tapg.tapg_set_dual(S.h, t, y1)
+        np.testing.assert_array_equal(S.dual(t), y1)
+
+
+def test_deterministic_repeat():
+    P = ds.config_problem("dwn128")
+    out = []
+    with make_solver(P, gamma=1e-7, tol=0.0, max_iter=30, check_every=30) as S:
+        t = add_tree(S, P)
+        for _ in range(2):
+            S.solve(t, P.p, P.q)
+            u, x = S.primal(t)
+            out.append((u, x, S.dual(t)))
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_edge_cases_single_node_and_chain():
+    """N = 1 (root only) and a single scenario chain."""
+    for P in [tiny_problem(N=1, b1=1, S=1, seed=2), tiny_problem(N=7, b1=1, S=1, seed=2)]:
+        sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+        gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 200))
+        st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 120)
+        _assert_fp64_parity(P, res, u, x, y, hist, ref, 120)
+
+
+def test_interior_problem_stops_after_one_iteration():
+    P = tiny_problem(N=4, b1=2, S=4, seed=9)
+    d0 = P.data.demand[0]
+    P.data.demand[:] = d0
+    P.data.price[:] = 0.0
+    P.weights.alpha0[:] = 0.0
+    from dwn_synth.generate import steady_input
+    P.q = steady_input(P.net, d0) + 0.3 * np.array([k == "src_tank" for k in P.net.kind])
+    with make_solver(P, gamma=1e-2, tol=1e-9, max_iter=100, check_every=10) as S:
+        t = add_tree(S, P)
+        st, u0, res = S.solve(t, P.p, P.q)
+        u, x = S.primal(t)
+    u_k, x_k = O.dual_gradient_kkt(P, np.zeros((P.tree.K, 14)))
+    assert res.iters == 1 and res.converged and res.primal_res <= 1e-12
+    assert np.abs(u - u_k).max() <= 1e-10
+
+
+def test_fp32_sweeps_small_cost_error():
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 500, precision=tapg.TAPG_FP32)
+    J = O.primal_cost(P, ref.u, ref.x)
+    assert abs(res.cost - J) <= 1e-4 * max(1.0, abs(J))
+    assert res.viol_eq <= 1e-4
