@@ -33,19 +33,19 @@ METRIC = "APG solves/sec and p50/p99 solve latency at fixed dual tolerance, 1 MI
 HBM_PEAK_GBS = 8000.0
 
 
-def sweep_bytes(nx, nu, elem, widths, kind):
-    """Algorithmic bytes of one launch of a stage kernel, summed over the
-    launches of one iteration (list per stage)."""
-    out = []
-    for w in widths:
-        if kind == "fwd":
-            per_node = 9 * nx + 6 * nu + 1
-            per_launch = nu * nu + nx * nx + nx * nu + 3 * nx + 2 * nu
-        else:
-            per_node = 6 * nx + 5 * nu
-            per_launch = 2 * nu * nu + nx * nx + nx * nu
-        out.append((per_node * w + per_launch) * elem + (8 * w if kind == "bwd" else 4 * w))
-    return out
+def sweep_bytes(nx, nu, elem, K, N, kind):
+    """Algorithmic HBM bytes of one sweep direction over one iteration.
+
+    Backward, per node: y and y_prev (2 (2nx+nu)), kappa (nu) read, j (nu)
+    written.  Forward, per node: j (nu), 1/p, g (nx), y and y_prev read,
+    u (nu), x (nx) and y_next (2nx+nu) written.  Children and parents inside
+    a workgroup's subtree stay on chip.  Per stage, the stage factor (nu^2)
+    is read once."""
+    if kind == "bwd":
+        per_node = 4 * nx + 4 * nu
+    else:
+        per_node = 8 * nx + 5 * nu + 1
+    return (per_node * K + N * nu * nu) * elem
 
 
 def main():
@@ -129,20 +129,18 @@ def main():
         S.solve(tree, P.p, P.q)
         kt = tapg.tapg_kernel_times(S.h)
         tapg.tapg_kernel_timing(S.h, False)
-        widths = [int(v) for v in P.tree.nodes_per_stage]
         kinds = {}
         for kind in ("bwd", "fwd"):
             ms, n = kt[kind]
-            b_iter = sum(sweep_bytes(net.nx, net.nu, elem, widths, kind))
-            n_iter = len(widths)
-            its = n / n_iter
+            b_iter = sweep_bytes(net.nx, net.nu, elem, P.tree.K, P.tree.N, kind)
+            its = iters  # one timed solve of the same workload
             kinds[kind] = dict(ms=ms, launches=n, bytes=b_iter * its, avg_us=1e3 * ms / max(n, 1))
         dom = max(kinds, key=lambda k: kinds[k]["ms"])
         d = kinds[dom]
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": f"{dom}_stage_kernel", "avg_launch_us": round(d["avg_us"], 3),
+                "kernel": f"seg_{dom}_kernel", "avg_launch_us": round(d["avg_us"], 3),
                 "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1),
                 "other": {k: {"avg_launch_us": round(v["avg_us"], 3), "launches": v["launches"],
                               "ms": round(v["ms"], 3)} for k, v in kinds.items()},

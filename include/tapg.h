@@ -161,6 +161,20 @@ tapg_status tapg_residuals(tapg_solver solver, tapg_tree tree, tapg_result* res)
  * iterations on the device (step-size selection; see tapg_config.gamma). */
 tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iters, double* L);
 
+/* Sweep schedule of a tree (host only, no device needed).  The sweeps run
+ * as "levels" of consecutive stages; a level's workgroups each own a group of
+ * consecutive nodes of its first stage and all their descendants inside the
+ * level, at most 4 (FP64) or 16 (FP32) nodes per stage.  With levels == NULL
+ * the library's planner chooses the cuts and group sizes (a cost model of
+ * launch, stage and per-node costs); otherwise `levels` is "s0:g0,s1:g1,..."
+ * (first stage and group size of each level, s0 = 0).  out[5*l .. 5*l+4]
+ * receives (first stage, last stage, group size, workgroups, widest
+ * workgroup stage) for l < cap; *nlevels the number of levels.  The same
+ * choice is made by tapg_solve (the TAPG_LEVELS environment variable
+ * overrides it there). */
+tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels, int* out,
+                               int cap, int* nlevels);
+
 /* Profiling aid: with enable != 0, later solves time every sweep-kernel launch
  * with a pair of HIP events on the solver's stream (iteration graphs are not
  * used meanwhile, and the host checks the stop flag after every iteration).

@@ -316,8 +316,11 @@ tapg_status tapg_solver_create(tapg_network net, const tapg_config* cfg, tapg_so
     S->device = cfg->device;
     S->stream = static_cast<hipStream_t>(cfg->hip_stream);
     S->fp32 = cfg->precision == TAPG_FP32;
+    // The segment kernels (nx, nu <= 128) use a u-dimension padded to 128.
+    const char* seg_env = std::getenv("TAPG_SEGMENTS");
+    S->seg_ok = h.nx <= 128 && h.nu <= 128 && !(seg_env && seg_env[0] == '0');
     S->LDX = round_up(h.nx, 16);
-    S->LDU = round_up(h.nu, 16);
+    S->LDU = S->seg_ok ? 128 : round_up(h.nu, 16);
     S->LDY = 2 * S->LDX + S->LDU;
     const char* env = std::getenv("TAPG_USE_GRAPH");
     S->use_graph = !(env && env[0] == '0');
@@ -481,6 +484,33 @@ tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iter
     if (iters < 1) fail(TAPG_EINVAL, "iters must be >= 1");
     Slot& sl = dev_slot(solver, tree->h);
     *L = dev_power(solver, tree->h, sl, iters);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels, int* out,
+                               int cap, int* nlevels) {
+  return guarded([&]() -> tapg_status {
+    need(tree, "tree");
+    need(nlevels, "nlevels");
+    if (precision != TAPG_FP64 && precision != TAPG_FP32) fail(TAPG_EINVAL, "bad precision");
+    const TreeHost& t = tree->h;
+    const int nbmax = precision == TAPG_FP32 ? 16 : 4;
+    std::vector<LevelPlan> plans =
+        (levels && levels[0]) ? levels_from_env(t, levels)
+                              : plan_levels(t, nbmax, 114.0 * 114.0 / 64.0 / 2400.0);
+    *nlevels = (int)plans.size();
+    for (size_t l = 0; l < plans.size(); ++l) {
+      int wmax = 0;
+      level_ranges(t, plans[l], wmax);
+      if (out && (int)l < cap) {
+        out[5 * l + 0] = plans[l].s_begin;
+        out[5 * l + 1] = plans[l].s_end;
+        out[5 * l + 2] = plans[l].group;
+        out[5 * l + 3] = plans[l].n_wg;
+        out[5 * l + 4] = wmax;
+      }
+    }
     return TAPG_OK;
   });
 }

@@ -93,6 +93,8 @@ struct DevCtl {
   unsigned long long res_bits;  // running max |r| of the current iteration (bits of a double >= 0)
   double pw_scale;              // power iteration: 1/|v|
   double L;                     // power iteration: latest |M v| estimate
+  unsigned wg_done;             // workgroups of the closing launch that have finished
+  unsigned pad1;
 };
 
 // Per-(solver, tree) device buffers.
@@ -130,6 +132,14 @@ struct Slot {
   bool has_result = false;
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
+  // segment schedule: levels top (stage 0) first
+  struct Level {
+    int s_begin, s_end, n_wg, nbm;
+    int2* d_ranges;
+  };
+  std::vector<Level> levels;
+  bool segmented = false;
+  int part_total = 0;
 };
 
 struct SolverState;

@@ -1,0 +1,118 @@
+// Kernel argument blocks and launch wrappers shared by the device files.
+#pragma once
+
+#include "internal.h"
+
+namespace tapg {
+
+constexpr int kThreads = 256;     // per-stage kernels
+constexpr int kSegThreads = 512;  // segment kernels
+
+// Arguments of the per-stage sweep kernels.
+template <typename T>
+struct SweepArgs {
+  int nx, nu, LDX, LDU, LDY;
+  int s, node0, count, tile_base;
+  int mode;  // 0: APG iteration, 1: power iteration (zero data, no prox)
+  const int* anc;
+  const int* cbeg;
+  const int* cend;
+  const T* invp;
+  const T* F;   // Fbar_s
+  const T* Kb;  // Kbar_s
+  const T* At;
+  const T* Bt;
+  const T* A;
+  const T* B;
+  const T* xmin;
+  const T* xmax;
+  const T* xs;
+  const T* umin;
+  const T* umax;
+  T Wx, Ws;
+  const T* kappa;
+  const T* g;
+  const T* pq;
+  T* Y0;
+  T* Y1;
+  T* lam;
+  T* jv;
+  T* u;
+  T* x;
+  DevCtl* ctl;
+  double* part;
+};
+
+// Arguments of the segment sweep kernels (one launch per level and direction).
+template <typename T>
+struct SegArgs {
+  int nx, nu, LDX, LDU, LDY, LDXR;  // LDXR: power of two >= LDX
+  int s_begin, s_end, nst, N;
+  int mode;        // 0: APG iteration, 1: power iteration
+  int a_ident;     // A == I
+  int wu_scalar;   // W_u == wu I
+  T wu;
+  int last_level;  // forward launch that ends the iteration
+  int part_base, part_total;
+  const int2* ranges;  // [n_wg][nst] node range [lo, hi) per stage
+  const int* anc;
+  const int* cbeg;
+  const int* cend;
+  const T* invp;
+  const T* F;   // Fbar, N blocks of LDU x LDU, column-major
+  const T* Wu;  // W_u, LDU x LDU column-major (general W_u only)
+  const T* A;   // A, LDX x LDX column-major (general A only)
+  const T* At;  // A'
+  const int* Brow;  // CSR of B (nx rows)
+  const int* Bcol;
+  const T* Bval;
+  const int* Btrow;  // CSR of B' (nu rows)
+  const int* Btcol;
+  const T* Btval;
+  const T* xmin;
+  const T* xmax;
+  const T* xs;
+  const T* umin;
+  const T* umax;
+  T Wx, Ws;
+  const T* kappa;
+  const T* g;
+  const T* pq;
+  T* Y0;
+  T* Y1;
+  T* lam;
+  T* jv;
+  T* u;
+  T* x;
+  DevCtl* ctl;
+  double* part;
+  double* hist;
+};
+
+// Launch wrappers (segment_kernels.hip).
+template <typename T>
+void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st);
+
+// Launch wrappers (stage_kernels.hip).
+template <typename T>
+void launch_bwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
+template <typename T>
+void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
+void launch_iter_end(DevCtl* c, double* hist, hipStream_t st);
+void launch_power_end(DevCtl* c, const double* part, int n, hipStream_t st);
+template <typename T>
+void launch_data_step(int K, int nx, int nu, int nd, int LDX, int LDU, const int* stage,
+                      const double* prob, const double* demand, const double* price,
+                      const double* Pd, const double* Gd, const double* Gbar, const double* Fbar,
+                      const double* alpha0, const double* cE, double W_alpha, T* kappa, T* g,
+                      hipStream_t st);
+template <typename T>
+void launch_cost(int K, int nx, int nu, int nd, int ns, int LDX, int LDU, const int* anc,
+                 const double* prob, const double* demand, const double* price, const T* u,
+                 const T* x, const double* pq, const double* A, const double* B,
+                 const double* Gd, const double* E, const double* Ed, const double* Wu,
+                 const double* alpha0, const double* cE, const double* xmin, const double* xmax,
+                 const double* xs, const double* umin, const double* umax, double W_alpha,
+                 double W_x, double W_s, double* part, double* out, hipStream_t st);
+
+}  // namespace tapg

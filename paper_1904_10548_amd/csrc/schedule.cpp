@@ -1,0 +1,119 @@
+// Segment schedule of a tree (host): levels of consecutive stages, each
+// split into workgroups that own groups of consecutive nodes of the level's
+// first stage and all their descendants within the level.
+#include <algorithm>
+#include <string>
+
+#include "solver.h"
+
+namespace tapg {
+
+// ---------------------------------------------------------------------------
+// Segment schedule.  A level covers stages [s, e]; its workgroups own groups
+// of g consecutive nodes of stage s and all their descendants down to e.
+// The cut stages and group sizes minimise a simple per-iteration time model
+// (per launch, per stage and per node-column costs; workgroups beyond the
+// number that fit on the chip at once run in extra rounds) subject to every
+// workgroup holding at most NBmax nodes of any stage.
+// ---------------------------------------------------------------------------
+int nb_template(int w) {
+  int t = 1;
+  while (t < w) t <<= 1;
+  return t;
+}
+
+std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us) {
+  const int N = t.N;
+  const double c_launch = 3.0, c_stage = 0.25;
+  const int conc = 512;  // workgroups resident at once (256 CUs x 2)
+  std::vector<double> best(N + 1, 0.0);
+  std::vector<LevelPlan> choice(N);
+  for (int s = N - 1; s >= 0; --s) {
+    best[s] = 1e300;
+    const int mu = t.mu[s], off = t.offset[s];
+    for (int g = 1; g <= std::max(1, mu); g *= 2) {
+      const int nwg = (mu + g - 1) / g;
+      // widths of every group, stage by stage, extended one stage at a time
+      std::vector<int> lo(nwg), hi(nwg);
+      for (int w = 0; w < nwg; ++w) {
+        lo[w] = off + w * g;
+        hi[w] = std::min(off + (w + 1) * g, off + mu);
+      }
+      double stage_sum = 0.0;
+      for (int e = s; e < N; ++e) {
+        int wmax = 0;
+        for (int w = 0; w < nwg; ++w) wmax = std::max(wmax, hi[w] - lo[w]);
+        if (wmax > nbmax) break;
+        const int rounds = (nwg + conc - 1) / conc;
+        stage_sum += c_stage + node_us * nb_template(wmax);
+        const double cost = 2.0 * (c_launch + rounds * stage_sum);
+        if (cost + best[e + 1] < best[s]) {
+          best[s] = cost + best[e + 1];
+          choice[s] = LevelPlan{s, e, g, 0, nwg, cost};
+        }
+        if (e + 1 < N) {
+          for (int w = 0; w < nwg; ++w) {
+            const int nlo = t.cbeg[lo[w]], nhi = t.cend[hi[w] - 1];
+            lo[w] = nlo;
+            hi[w] = nhi;
+          }
+        }
+      }
+      if (g >= mu) break;
+    }
+  }
+  std::vector<LevelPlan> out;
+  for (int s = 0; s < N;) {
+    out.push_back(choice[s]);
+    s = choice[s].s_end + 1;
+  }
+  return out;
+}
+
+// Optional override: TAPG_LEVELS="s0:g0,s1:g1,..." (first stage and group size
+// of every level, top first).
+std::vector<LevelPlan> levels_from_env(const TreeHost& t, const char* spec) {
+  std::vector<std::pair<int, int>> cuts;
+  std::string str(spec);
+  size_t p = 0;
+  while (p < str.size()) {
+    size_t q = str.find(',', p);
+    if (q == std::string::npos) q = str.size();
+    const std::string item = str.substr(p, q - p);
+    const size_t c = item.find(':');
+    cuts.emplace_back(std::stoi(item.substr(0, c)), c == std::string::npos ? 1 : std::stoi(item.substr(c + 1)));
+    p = q + 1;
+  }
+  std::vector<LevelPlan> out;
+  for (size_t i = 0; i < cuts.size(); ++i) {
+    const int s = cuts[i].first, g = std::max(1, cuts[i].second);
+    const int e = i + 1 < cuts.size() ? cuts[i + 1].first - 1 : t.N - 1;
+    if (s < 0 || s > e || e >= t.N || (i == 0 && s != 0))
+      throw Fail{TAPG_EINVAL, "TAPG_LEVELS does not describe the stages 0..N-1"};
+    out.push_back(LevelPlan{s, e, g, 0, (t.mu[s] + g - 1) / g, 0.0});
+  }
+  return out;
+}
+
+// Node ranges of every workgroup of a level, stage by stage.
+std::vector<std::pair<int, int>> level_ranges(const TreeHost& t, const LevelPlan& L, int& wmax) {
+  const int nst = L.s_end - L.s_begin + 1;
+  std::vector<std::pair<int, int>> rg((size_t)L.n_wg * nst);
+  wmax = 0;
+  const int off = t.offset[L.s_begin], mu = t.mu[L.s_begin];
+  for (int w = 0; w < L.n_wg; ++w) {
+    int lo = off + w * L.group, hi = std::min(off + (w + 1) * L.group, off + mu);
+    for (int k = 0; k < nst; ++k) {
+      rg[(size_t)w * nst + k] = {lo, hi};
+      wmax = std::max(wmax, hi - lo);
+      if (k + 1 < nst) {
+        const int nlo = t.cbeg[lo], nhi = t.cend[hi - 1];
+        lo = nlo;
+        hi = nhi;
+      }
+    }
+  }
+  return rg;
+}
+
+}  // namespace tapg

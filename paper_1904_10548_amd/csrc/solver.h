@@ -14,6 +14,9 @@ struct NetDev {
   T *At = nullptr, *Bt = nullptr, *A = nullptr, *B = nullptr;
   T *xmin = nullptr, *xmax = nullptr, *xs = nullptr, *umin = nullptr, *umax = nullptr;
   T *F = nullptr, *Kb = nullptr;
+  // CSR of B (nx rows) and of B' (nu rows); dense W_u (column-major, ld LDU)
+  int *Brow = nullptr, *Bcol = nullptr, *Btrow = nullptr, *Btcol = nullptr;
+  T *Bval = nullptr, *Btval = nullptr, *Wu = nullptr;
 };
 
 struct DevExtra {
@@ -47,6 +50,10 @@ struct tapg_solver_s {
   std::map<uint64_t, tapg::Slot> slots;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool use_graph = true;
+  // structure of the network and weights (detected at creation)
+  bool a_ident = false, wu_scalar = false;
+  double wu = 1.0;
+  bool seg_ok = false;  // segment kernels apply (nx, nu <= 128)
   // optional per-launch timing of the sweep kernels (HIP events around each
   // launch; graphs are bypassed while it is on)
   bool time_kernels = false;
@@ -56,6 +63,16 @@ struct tapg_solver_s {
 };
 
 namespace tapg {
+
+// Segment schedule (schedule.cpp).
+struct LevelPlan {
+  int s_begin, s_end, group, nbm, n_wg;
+  double cost;
+};
+int nb_template(int w);
+std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us);
+std::vector<LevelPlan> levels_from_env(const TreeHost& t, const char* spec);
+std::vector<std::pair<int, int>> level_ranges(const TreeHost& t, const LevelPlan& L, int& wmax);
 
 // Device layer (solver.hip).
 void dev_init(tapg_solver_s* S);             // streams, events, network buffers

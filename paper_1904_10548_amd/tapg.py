@@ -36,7 +36,8 @@ EXPORTED = [
     "tapg_tree_num_nodes", "tapg_tree_destroy", "tapg_solver_create", "tapg_solver_destroy",
     "tapg_factor_step", "tapg_get_factors", "tapg_solve", "tapg_get_primal", "tapg_get_dual",
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
-    "tapg_kernel_timing", "tapg_kernel_times", "tapg_last_error", "tapg_version",
+    "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_last_error",
+    "tapg_version",
 ]
 
 
@@ -115,6 +116,8 @@ def lib() -> ctypes.CDLL:
         "tapg_residual_history": ([_P, _P, _D, ctypes.c_int, _I], ctypes.c_int),
         "tapg_residuals": ([_P, _P, ctypes.POINTER(TapgResult)], ctypes.c_int),
         "tapg_estimate_lipschitz": ([_P, _P, ctypes.c_int, _D], ctypes.c_int),
+        "tapg_plan_schedule": ([_P, ctypes.c_int, ctypes.c_char_p, _I, ctypes.c_int, _I],
+                               ctypes.c_int),
         "tapg_kernel_timing": ([_P, ctypes.c_int], ctypes.c_int),
         "tapg_kernel_times": ([_P, _D, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
         "tapg_last_error": ([], ctypes.c_char_p),
@@ -281,6 +284,16 @@ def tapg_estimate_lipschitz(solver, tree, iters=100) -> float:
     L = ctypes.c_double(0.0)
     _check(lib().tapg_estimate_lipschitz(solver, tree, int(iters), ctypes.byref(L)))
     return L.value
+
+
+def tapg_plan_schedule(tree, precision=TAPG_FP64, levels=None):
+    """List of (first stage, last stage, group, workgroups, widest stage)."""
+    cap = 256
+    out = np.zeros(5 * cap, dtype=np.int32)
+    n = ctypes.c_int(0)
+    _check(lib().tapg_plan_schedule(tree, precision, levels.encode() if levels else None,
+                                    out.ctypes.data_as(_I), cap, ctypes.byref(n)))
+    return [tuple(int(v) for v in out[5 * i:5 * i + 5]) for i in range(min(n.value, cap))]
 
 
 def tapg_kernel_timing(solver, enable: bool):

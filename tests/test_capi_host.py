@@ -114,3 +114,37 @@ def test_null_handles_are_errors():
     L.tapg_tree_destroy(None)
     L.tapg_network_destroy(None)
     L.tapg_solver_destroy(None)
+
+
+@pytest.mark.parametrize("name", ["small", "dwn128", "dwn2048"])
+@pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
+def test_schedule_plan_covers_stages(name, precision):
+    """The planner's levels cover stages 0..N-1 in order, every workgroup
+    holds at most 4 (FP64) / 16 (FP32) nodes per stage, and the groups of a
+    level cover its first stage."""
+    P = ds.config_problem(name)
+    h = tapg.tapg_tree_create(*_tree_args(P))
+    try:
+        plan = tapg.tapg_plan_schedule(h, precision)
+    finally:
+        tapg.tapg_tree_destroy(h)
+    cap = 4 if precision == tapg.TAPG_FP64 else 16
+    assert plan[0][0] == 0 and plan[-1][1] == P.tree.N - 1
+    for a, b in zip(plan, plan[1:]):
+        assert b[0] == a[1] + 1
+    for s0, s1, g, nwg, wmax in plan:
+        assert wmax <= cap
+        assert nwg == -(-int(P.tree.nodes_per_stage[s0]) // g)
+
+
+def test_schedule_override_and_rejection():
+    P = ds.config_problem("dwn128")
+    h = tapg.tapg_tree_create(*_tree_args(P))
+    try:
+        plan = tapg.tapg_plan_schedule(h, tapg.TAPG_FP64, "0:1,2:2,4:1")
+        assert [p[:3] for p in plan] == [(0, 1, 1), (2, 3, 2), (4, 23, 1)]
+        assert max(p[4] for p in plan) == 4
+        with pytest.raises(tapg.TapgError):
+            tapg.tapg_plan_schedule(h, tapg.TAPG_FP64, "1:1,4:1")  # must start at stage 0
+    finally:
+        tapg.tapg_tree_destroy(h)

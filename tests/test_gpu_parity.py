@@ -25,6 +25,13 @@ from helpers import tiny_problem
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _default_schedule():
+    _schedule_env()
+    yield
+    _schedule_env()
+
+
 def say(*a):
     print("[gpu-case]", *a, flush=True)
     sys.stdout.flush()
@@ -35,9 +42,20 @@ def _oracle_run(P, gamma, iters, tol=None, factors=None):
     return O.apg(P, gamma, f, iters, tol=tol)
 
 
-def _compare_fixed(P, gamma, iters, precision=tapg.TAPG_FP64, check_every=50, graph=True):
+def _schedule_env(graph=True, segments=True, levels=None):
     os.environ["TAPG_USE_GRAPH"] = "1" if graph else "0"
-    say(P.name, "K", P.tree.K, "iters", iters, "prec", precision, "graph", graph)
+    os.environ["TAPG_SEGMENTS"] = "1" if segments else "0"
+    if levels:
+        os.environ["TAPG_LEVELS"] = levels
+    else:
+        os.environ.pop("TAPG_LEVELS", None)
+
+
+def _compare_fixed(P, gamma, iters, precision=tapg.TAPG_FP64, check_every=50, graph=True,
+                   segments=True, levels=None):
+    _schedule_env(graph, segments, levels)
+    say(P.name, "K", P.tree.K, "iters", iters, "prec", precision, "graph", graph,
+        "segments", segments, "levels", levels)
     with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=check_every,
                      precision=precision) as S:
         t = add_tree(S, P)
@@ -64,22 +82,24 @@ def _assert_fp64_parity(P, res, u, x, y, hist, ref, iters):
     assert res.viol_eq <= 1e-9 and ve <= 1e-9
     rh = np.asarray(ref.res_hist)
     assert np.allclose(hist, rh, rtol=1e-7, atol=1e-12)
-    assert abs(res.primal_res - rh[-1]) <= 1e-7 * max(rh[-1], 1e-12)
+    assert abs(res.primal_res - rh[-1]) <= 1e-7 * rh[-1] + 1e-12
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_small_500_iterations_fp64(graph):
+@pytest.mark.parametrize("graph,segments", [(True, True), (False, True), (True, False)])
+def test_small_500_iterations_fp64(graph, segments):
     """The small configuration at exactly 500 iterations (no early stop)."""
     P = ds.config_problem("small")
     nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
     gamma = 1.0 / O.lipschitz_dense(P, nf)
-    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 500, graph=graph)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 500, graph=graph,
+                                                     segments=segments)
     assert st == tapg.TAPG_OK
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 500)
     assert np.abs(u0 - ref.u[0]).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())
 
 
-def test_irregular_tree_general_A_Wu_fp64():
+@pytest.mark.parametrize("segments", [True, False])
+def test_irregular_tree_general_A_Wu_fp64(segments):
     """Irregular branching, non-identity A and dense W_u (generic paths)."""
     P = tiny_problem(N=6, irregular=True, seed=31, max_children=3, max_width=40)
     rng = np.random.default_rng(2)
@@ -88,7 +108,7 @@ def test_irregular_tree_general_A_Wu_fp64():
     P.weights.W_u = G @ G.T + 3 * np.eye(6)
     sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
     gamma = 0.9 / O.lipschitz_power(P, sf, 300)
-    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 300)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 300, segments=segments)
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 300)
 
 
@@ -106,12 +126,21 @@ def test_wide_ragged_tree_fp64_and_fp32():
     assert abs(r32.cost - J) <= 1e-4 * max(1.0, abs(J))
 
 
-def test_dwn128_fixed_iterations_fp64():
-    """Full-size network and tree (K = 2429): 40 iterations, every element."""
+@pytest.mark.parametrize("levels", [None, "0:1,2:2,4:1", "0:1,1:1,3:4,6:8,20:16"])
+def test_dwn128_fixed_iterations_fp64(levels):
+    """Full-size network and tree (K = 2429): 40 iterations, every element;
+    planned schedule and forced multi-level / grouped schedules."""
     P = ds.config_problem("dwn128")
     sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
     gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 60))
-    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40)
+    if levels and levels.endswith(":16"):
+        # wide groups need FP32 (up to 16 nodes per stage and workgroup)
+        st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40,
+                                                         precision=tapg.TAPG_FP32, levels=levels)
+        J = O.primal_cost(P, ref.u, ref.x)
+        assert abs(res.cost - J) <= 1e-4 * max(1.0, abs(J))
+        return
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40, levels=levels)
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 40)
 
 
