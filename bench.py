@@ -33,19 +33,19 @@ METRIC = "APG solves/sec and p50/p99 solve latency at fixed dual tolerance, 1 MI
 HBM_PEAK_GBS = 8000.0
 
 
-def sweep_bytes(nx, nu, elem, K, N, kind):
+def sweep_bytes(nx, nu, elem, K, n_blocks, kind):
     """Algorithmic HBM bytes of one sweep direction over one iteration.
 
     Backward, per node: y and y_prev (2 (2nx+nu)), kappa (nu) read, j (nu)
     written.  Forward, per node: j (nu), 1/p, g (nx), y and y_prev read,
     u (nu), x (nx) and y_next (2nx+nu) written.  Children and parents inside
-    a workgroup's subtree stay on chip.  Per stage, the stage factor (nu^2)
-    is read once."""
+    a workgroup's subtree stay on chip.  Each distinct stage-factor block
+    (nu^2) is read once (stages with equal factors share a block)."""
     if kind == "bwd":
         per_node = 4 * nx + 4 * nu
     else:
         per_node = 8 * nx + 5 * nu + 1
-    return (per_node * K + N * nu * nu) * elem
+    return (per_node * K + n_blocks * nu * nu) * elem
 
 
 def main():
@@ -89,6 +89,7 @@ def main():
                     P.tree.N, gamma=0.0, tol=args.tol, max_iter=args.max_iter,
                     check_every=args.check_every, precision=prec)
     factor_s = time.perf_counter() - t0
+    _, n_blocks = tapg.tapg_factor_blocks(S.h, P.tree.N)
     tree = S.add_tree(P.tree.nodes_per_stage, P.tree.anc, P.tree.prob, P.data.demand,
                       P.data.price)
     t0 = time.perf_counter()
@@ -132,7 +133,7 @@ def main():
         kinds = {}
         for kind in ("bwd", "fwd"):
             ms, n = kt[kind]
-            b_iter = sweep_bytes(net.nx, net.nu, elem, P.tree.K, P.tree.N, kind)
+            b_iter = sweep_bytes(net.nx, net.nu, elem, P.tree.K, n_blocks, kind)
             its = iters  # one timed solve of the same workload
             kinds[kind] = dict(ms=ms, launches=n, bytes=b_iter * its, avg_us=1e3 * ms / max(n, 1))
         dom = max(kinds, key=lambda k: kinds[k]["ms"])
@@ -174,6 +175,7 @@ def main():
         "final_residual": results[-1]["primal_res"],
         "cost": results[-1]["cost"],
         "factor_step_s": round(factor_s, 4),
+        "factor_blocks": n_blocks,
         "lipschitz_s": round(lipschitz_s, 4),
         "roofline": roof,
         "cpu_baseline": cpu,

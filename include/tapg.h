@@ -132,6 +132,14 @@ tapg_status tapg_factor_step(tapg_solver solver, int N);
 /* Copy the stage-s factors (row-major nu*nu each; any pointer may be NULL). */
 tapg_status tapg_get_factors(tapg_solver solver, int stage, double* Fbar, double* Kbar,
                              double* Gbar);
+/* Factor sharing between stages (a property of the factors of Sec. 4.4 that the
+ * sweeps exploit): stage s is served by factor block fid[s] (host array of n >= N
+ * ints, may be NULL), where consecutive stages whose Fbar agree to 16 ulp of the
+ * block's largest entry share the block of the later stage.  With W_u = w I every
+ * Fbar_s equals Z Z' / w, so there is one block.  *n_blocks (may be NULL) gets the
+ * number of distinct blocks.  TAPG_ESTATE before the factor step, TAPG_EINVAL if
+ * n < N. */
+tapg_status tapg_factor_blocks(tapg_solver solver, int* fid, int n, int* n_blocks);
 
 /* Solve the problem on `tree` from x_{k|k} = p [nx], u_{k-1|k} = q [nu] (the
  * paper's controlAction).  warm_start != 0 starts from the dual of this
@@ -164,7 +172,7 @@ tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iter
 /* Sweep schedule of a tree (host only, no device needed).  The sweeps run
  * as "levels" of consecutive stages; a level's workgroups each own a group of
  * consecutive nodes of its first stage and all their descendants inside the
- * level, at most 4 (FP64) or 16 (FP32) nodes per stage.  With levels == NULL
+ * level, at most 4 (FP64) or 8 (FP32) nodes per stage.  With levels == NULL
  * the library's planner chooses the cuts and group sizes (a cost model of
  * launch, stage and per-node costs); otherwise `levels` is "s0:g0,s1:g1,..."
  * (first stage and group size of each level, s0 = 0).  out[5*l .. 5*l+4]

@@ -318,7 +318,10 @@ tapg_status tapg_solver_create(tapg_network net, const tapg_config* cfg, tapg_so
     S->fp32 = cfg->precision == TAPG_FP32;
     // The segment kernels (nx, nu <= 128) use a u-dimension padded to 128.
     const char* seg_env = std::getenv("TAPG_SEGMENTS");
-    S->seg_ok = h.nx <= 128 && h.nu <= 128 && !(seg_env && seg_env[0] == '0');
+    S->nnzB = 0;
+    for (double v : h.B.a) S->nnzB += v != 0.0;
+    S->seg_ok = h.nx <= 128 && h.nu <= 128 && S->nnzB <= 1024 &&
+                !(seg_env && seg_env[0] == '0');
     S->LDX = round_up(h.nx, 16);
     S->LDU = S->seg_ok ? 128 : round_up(h.nu, 16);
     S->LDY = 2 * S->LDX + S->LDU;
@@ -373,6 +376,19 @@ tapg_status tapg_get_factors(tapg_solver solver, int stage, double* Fbar, double
     if (Fbar) std::copy_n(solver->Fbar.begin() + stage * nn, nn, Fbar);
     if (Kbar) std::copy_n(solver->Kbar.begin() + stage * nn, nn, Kbar);
     if (Gbar) std::copy_n(solver->Gbar.begin() + stage * nn, nn, Gbar);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_factor_blocks(tapg_solver solver, int* fid, int n, int* n_blocks) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    if (solver->N == 0) fail(TAPG_ESTATE, "factor step not run");
+    if (fid) {
+      if (n < solver->N) fail(TAPG_EINVAL, "fid holds fewer than N entries");
+      std::copy(solver->fid.begin(), solver->fid.end(), fid);
+    }
+    if (n_blocks) *n_blocks = solver->n_factor_blocks;
     return TAPG_OK;
   });
 }
@@ -495,7 +511,7 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
     need(nlevels, "nlevels");
     if (precision != TAPG_FP64 && precision != TAPG_FP32) fail(TAPG_EINVAL, "bad precision");
     const TreeHost& t = tree->h;
-    const int nbmax = precision == TAPG_FP32 ? 16 : 4;
+    const int nbmax = precision == TAPG_FP32 ? 8 : 4;
     std::vector<LevelPlan> plans =
         (levels && levels[0]) ? levels_from_env(t, levels)
                               : plan_levels(t, nbmax, 114.0 * 114.0 / 64.0 / 2400.0);
@@ -503,6 +519,9 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
     for (size_t l = 0; l < plans.size(); ++l) {
       int wmax = 0;
       level_ranges(t, plans[l], wmax);
+      if (wmax > nbmax)
+        fail(TAPG_EINVAL, "segment schedule: a workgroup would hold more than " +
+                              std::to_string(nbmax) + " nodes of one stage");
       if (out && (int)l < cap) {
         out[5 * l + 0] = plans[l].s_begin;
         out[5 * l + 1] = plans[l].s_end;

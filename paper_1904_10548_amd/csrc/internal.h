@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tapg.h"
+#include "tapg.h"
 
 namespace tapg {
 
@@ -135,6 +135,7 @@ struct Slot {
   // segment schedule: levels top (stage 0) first
   struct Level {
     int s_begin, s_end, n_wg, nbm;
+    int nch;  // most children of one workgroup below the level's last stage
     int2* d_ranges;
   };
   std::vector<Level> levels;

@@ -54,12 +54,15 @@ struct SegArgs {
   T wu;
   int last_level;  // forward launch that ends the iteration
   int part_base, part_total;
+  int nnzB;        // nonzeros of B (= of B')
+  int nch;         // backward: most children of one workgroup below the level's last stage
   const int2* ranges;  // [n_wg][nst] node range [lo, hi) per stage
   const int* anc;
   const int* cbeg;
   const int* cend;
   const T* invp;
   const T* F;   // Fbar, N blocks of LDU x LDU, column-major
+  const int* fid;  // per stage: the block of F that serves it (equal factors share one)
   const T* Wu;  // W_u, LDU x LDU column-major (general W_u only)
   const T* A;   // A, LDX x LDX column-major (general A only)
   const T* At;  // A'
@@ -92,6 +95,8 @@ struct SegArgs {
 // Launch wrappers (segment_kernels.hip).
 template <typename T>
 void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st);
+template <typename T>
+size_t seg_lds(int nbm, const SegArgs<T>& a);
 
 // Launch wrappers (stage_kernels.hip).
 template <typename T>

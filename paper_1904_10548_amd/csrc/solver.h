@@ -43,6 +43,12 @@ struct tapg_solver_s {
   int LDX = 0, LDU = 0, LDY = 0;
   int N = 0;  // horizon of the factor step, 0 = not factored
   std::vector<double> Fbar, Kbar, Gbar;  // host FP64, N blocks of nu*nu row-major
+  // Stage s is served by factor block fid[s]: consecutive stages whose Fbar
+  // agree to rounding share the block of the later one (W_u = w I makes every
+  // Fbar_s equal to Z Z' / w), so a sweep reloads its factor only on a change.
+  std::vector<int> fid;
+  int n_factor_blocks = 0;
+  int* d_fid = nullptr;
   bool fp32 = false;
   tapg::NetDev<double> d64;
   tapg::NetDev<float> d32;
@@ -53,7 +59,9 @@ struct tapg_solver_s {
   // structure of the network and weights (detected at creation)
   bool a_ident = false, wu_scalar = false;
   double wu = 1.0;
-  bool seg_ok = false;  // segment kernels apply (nx, nu <= 128)
+  bool seg_ok = false;  // segment kernels apply (nx, nu <= 128, B with few nonzeros)
+  int nnzB = 0;
+  size_t lds_limit = 64 * 1024;  // dynamic LDS per workgroup (device attribute)
   // optional per-launch timing of the sweep kernels (HIP events around each
   // launch; graphs are bypassed while it is on)
   bool time_kernels = false;

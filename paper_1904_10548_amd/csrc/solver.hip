@@ -162,6 +162,19 @@ SweepArgs<T> make_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode)
 // One APG iteration (mode 0) or one power-iteration step (mode 1) on the
 // solver's stream: backward stages, forward stages, end-of-step kernel.
 template <typename T>
+size_t seg_lds_probe(tapg_solver_s* S, int nbm, int nst, int nch) {
+  SegArgs<T> probe{};
+  probe.nch = nch;
+  probe.nx = S->net.nx;
+  probe.nu = S->net.nu;
+  probe.LDX = S->LDX;
+  probe.LDU = S->LDU;
+  probe.nst = nst;
+  probe.nnzB = S->nnzB;
+  return seg_lds<T>(nbm, probe);
+}
+
+template <typename T>
 SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode) {
   SegArgs<T> a{};
   a.nx = S->net.nx;
@@ -178,11 +191,13 @@ SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mod
   a.wu_scalar = S->wu_scalar ? 1 : 0;
   a.wu = (T)S->wu;
   a.part_total = sl.part_total;
+  a.nnzB = S->nnzB;
   a.anc = sl.d_anc;
   a.cbeg = sl.d_cbeg;
   a.cend = sl.d_cend;
   a.invp = static_cast<const T*>(sl.d_invp);
   a.F = d.F;
+  a.fid = S->d_fid;
   a.Wu = d.Wu;
   a.A = d.A;
   a.At = d.At;
@@ -242,6 +257,7 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
         a.nst = L.s_end - L.s_begin + 1;
         a.ranges = L.d_ranges;
         a.part_base = bases[l];
+        a.nch = L.nch;
         a.last_level = (pass == 1 && l == nl - 1) ? 1 : 0;
         if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
         launch_seg<T>(pass == 1, L.nbm, a, L.n_wg, st);
@@ -492,6 +508,13 @@ double power_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
 // ---------------------------------------------------------------------------
 void dev_init(tapg_solver_s* S) {
   TAPG_HIP(hipSetDevice(S->device));
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, S->device) ==
+            hipSuccess &&
+        lds > 0)
+      S->lds_limit = (size_t)lds;
+  }
   {  // structure of A and W_u; segment kernels need nx, nu <= 128
     const NetworkHost& h = S->net;
     bool ai = true;
@@ -550,6 +573,7 @@ void dev_release(tapg_solver_s* S) {
   free_net(S->d32);
   dfree(S->dx.Gd); dfree(S->dx.Pd); dfree(S->dx.Gbar); dfree(S->dx.E); dfree(S->dx.Ed);
   dfree(S->dx.Wu); dfree(S->dx.alpha0); dfree(S->dx.cE); dfree(S->dx.red);
+  dfree(S->d_fid);
   for (hipEvent_t e : S->tev) (void)hipEventDestroy(e);
   S->tev.clear();
   if (S->ev0) (void)hipEventDestroy(S->ev0);
@@ -573,6 +597,32 @@ void dev_upload_factors(tapg_solver_s* S) {
               (T)src[(size_t)s * nu * nu + (size_t)r * nu + k];
     return out;
   };
+  // factor ids: stage s shares the block of stage s+1's representative when
+  // the two Fbar agree to 16 ulp of the representative's largest entry
+  S->fid.assign(N, 0);
+  S->n_factor_blocks = N > 0 ? 1 : 0;
+  for (int s = N - 1; s >= 0; --s) {
+    if (s == N - 1) {
+      S->fid[s] = s;
+      continue;
+    }
+    const int rep = S->fid[s + 1];
+    const double* Fr = S->Fbar.data() + (size_t)rep * nu * nu;
+    const double* Fs = S->Fbar.data() + (size_t)s * nu * nu;
+    double mx = 0.0, d = 0.0;
+    for (size_t i = 0; i < (size_t)nu * nu; ++i) {
+      mx = std::max(mx, std::fabs(Fr[i]));
+      d = std::max(d, std::fabs(Fs[i] - Fr[i]));
+    }
+    if (d <= 16.0 * 2.220446049250313e-16 * mx) {
+      S->fid[s] = rep;
+    } else {
+      S->fid[s] = s;
+      S->n_factor_blocks++;
+    }
+  }
+  dfree(S->d_fid);
+  S->d_fid = upload(S->fid, st);
   dfree(S->d64.F); dfree(S->d64.Kb); dfree(S->dx.Gbar);
   S->d64.F = upload(pack(S->Fbar, double{}), st);
   S->d64.Kb = upload(pack(S->Kbar, double{}), st);
@@ -655,7 +705,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       sl.tile_offset[t.N] = tot;
       sl.total_tiles = tot;
       if (S->seg_ok) {
-        const int nbmax = S->fp32 ? 16 : 4;
+        const int nbmax = S->fp32 ? 8 : 4;
         const double node_us = (double)S->net.nu * S->net.nu / 64.0 / 2400.0 * (S->fp32 ? 0.5 : 1.0);
         const char* spec = std::getenv("TAPG_LEVELS");
         std::vector<LevelPlan> plans =
@@ -669,7 +719,24 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
           if (wmax > nbmax)
             throw Fail{TAPG_EINVAL, "segment schedule: a workgroup would hold more than " +
                                         std::to_string(nbmax) + " nodes of one stage"};
-          Slot::Level L{P.s_begin, P.s_end, P.n_wg, nb_template(wmax), nullptr};
+          int nch = 0;
+          if (P.s_end + 1 < t.N) {
+            const int nst = P.s_end - P.s_begin + 1;
+            for (int w = 0; w < P.n_wg; ++w) {
+              const auto& q = rp[(size_t)w * nst + nst - 1];
+              nch = std::max(nch, t.cend[q.second - 1] - t.cbeg[q.first]);
+            }
+          }
+          Slot::Level L{P.s_begin, P.s_end, P.n_wg, nb_template(wmax), nch, nullptr};
+          {
+            const int nst = P.s_end - P.s_begin + 1;
+            const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, nst, nch)
+                                       : seg_lds_probe<double>(S, L.nbm, nst, nch);
+            if (lds > S->lds_limit)
+              throw Fail{TAPG_EINVAL, "segment schedule needs " + std::to_string(lds) +
+                                          " bytes of LDS per workgroup (limit " +
+                                          std::to_string(S->lds_limit) + ")"};
+          }
           L.d_ranges = upload(rg, st);
           sl.levels.push_back(L);
           ptot += P.n_wg;

@@ -18,7 +18,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libtapg.so")
+# TAPG_LIBRARY selects another build of the same library (e.g. an experiment).
+LIB_PATH = os.environ.get("TAPG_LIBRARY") or os.path.join(_PKG, "libtapg.so")
 
 TAPG_OK = 0
 TAPG_ENOTCONV = 1
@@ -34,7 +35,7 @@ TAPG_FP32 = 1
 EXPORTED = [
     "tapg_network_create", "tapg_network_destroy", "tapg_tree_create", "tapg_tree_set_data",
     "tapg_tree_num_nodes", "tapg_tree_destroy", "tapg_solver_create", "tapg_solver_destroy",
-    "tapg_factor_step", "tapg_get_factors", "tapg_solve", "tapg_get_primal", "tapg_get_dual",
+    "tapg_factor_step", "tapg_get_factors", "tapg_factor_blocks", "tapg_solve", "tapg_get_primal", "tapg_get_dual",
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
     "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_last_error",
     "tapg_version",
@@ -109,6 +110,7 @@ def lib() -> ctypes.CDLL:
         "tapg_solver_destroy": ([_P], None),
         "tapg_factor_step": ([_P, ctypes.c_int], ctypes.c_int),
         "tapg_get_factors": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
+        "tapg_factor_blocks": ([_P, _I, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_solve": ([_P, _P, _D, _D, ctypes.c_int, _D, ctypes.POINTER(TapgResult)], ctypes.c_int),
         "tapg_get_primal": ([_P, _P, _D, _D], ctypes.c_int),
         "tapg_get_dual": ([_P, _P, _D], ctypes.c_int),
@@ -238,6 +240,14 @@ def tapg_get_factors(solver, stage: int, nu: int):
     F, Kb, G = (np.zeros((nu, nu)) for _ in range(3))
     _check(lib().tapg_get_factors(solver, stage, _ptr(F), _ptr(Kb), _ptr(G)))
     return F, Kb, G
+
+
+def tapg_factor_blocks(solver, N: int):
+    """``(fid, n_blocks)``: the factor block serving each stage and the count."""
+    fid = np.zeros(N, dtype=np.int32)
+    nb = ctypes.c_int(0)
+    _check(lib().tapg_factor_blocks(solver, fid.ctypes.data_as(_I), N, ctypes.byref(nb)))
+    return fid, nb.value
 
 
 def tapg_solve(solver, tree, p, q, warm_start=False, nu=None):

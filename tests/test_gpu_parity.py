@@ -126,15 +126,17 @@ def test_wide_ragged_tree_fp64_and_fp32():
     assert abs(r32.cost - J) <= 1e-4 * max(1.0, abs(J))
 
 
-@pytest.mark.parametrize("levels", [None, "0:1,2:2,4:1", "0:1,1:1,3:4,6:8,20:16"])
-def test_dwn128_fixed_iterations_fp64(levels):
+@pytest.mark.parametrize("levels,fp32", [(None, False), ("0:1,2:2,4:1", False),
+                                         ("0:1,1:1,3:2,5:4", True)])
+def test_dwn128_fixed_iterations(levels, fp32):
     """Full-size network and tree (K = 2429): 40 iterations, every element;
     planned schedule and forced multi-level / grouped schedules."""
     P = ds.config_problem("dwn128")
     sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
     gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 60))
-    if levels and levels.endswith(":16"):
-        # wide groups need FP32 (up to 16 nodes per stage and workgroup)
+    if fp32:
+        # a group of 4 at stage 5 is 8 nodes wide from stage 6 on: FP32 only
+        # (an FP64 workgroup holds at most 4 nodes of a stage)
         st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40,
                                                          precision=tapg.TAPG_FP32, levels=levels)
         J = O.primal_cost(P, ref.u, ref.x)
@@ -173,6 +175,30 @@ def test_factor_step_matches_oracle_stage_factors():
             assert np.abs(F - sf.Fbar[s]).max() <= 1e-11 * np.abs(sf.Fbar[s]).max()
             assert np.abs(Kb - sf.Kbar[s]).max() <= 1e-11 * max(1.0, np.abs(sf.Kbar[s]).max())
             assert np.abs(G - sf.Gbar[s]).max() <= 1e-11 * max(1.0, np.abs(sf.Gbar[s]).max())
+
+
+def test_factor_blocks_shared_when_equal():
+    """Stages whose factors agree to rounding share one block: one block for
+    W_u = w I (Fbar_s = Pi / w at every stage); with a dense W_u every stage's
+    block equals its own factor to 16 ulp."""
+    P = ds.config_problem("dwn128")
+    with make_solver(P, gamma=1e-3, tol=0.0, max_iter=1) as S:
+        fid, nb = tapg.tapg_factor_blocks(S.h, P.tree.N)
+    assert nb == 1 and np.all(fid == P.tree.N - 1)
+    Pg = tiny_problem(N=9, b1=3, S=8, seed=5)
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((Pg.net.nu, Pg.net.nu))
+    Pg.weights.W_u = M @ M.T + Pg.net.nu * np.eye(Pg.net.nu)
+    sf = O.StageFactors(Pg.net, Pg.weights.W_u, Pg.tree)
+    with make_solver(Pg, gamma=1e-3, tol=0.0, max_iter=1) as S:
+        fid, nb = tapg.tapg_factor_blocks(S.h, Pg.tree.N)
+    N = Pg.tree.N
+    assert fid[N - 1] == N - 1 and 1 <= nb <= N
+    assert len(set(fid.tolist())) == nb
+    for s in range(N):
+        assert s <= fid[s] and fid[fid[s]] == fid[s]
+        F, R = sf.Fbar[s], sf.Fbar[fid[s]]
+        assert np.abs(F - R).max() <= 16 * 2.3e-16 * np.abs(R).max() + 1e-15
 
 
 def test_power_iteration_lipschitz():

@@ -79,6 +79,23 @@ def test_node_factors_equal_probability_scaled_stage_factors():
         assert np.abs(nf.G[n] - sf.Gbar[s]).max() <= 1e-12
 
 
+def test_stage_factors_closed_form_for_scalar_Wu():
+    """With W_u = w I the recursion of Sec. 4.4 is stage-invariant: Pbar never
+    acts on ker E, so Fbar_s = Pi / w, Kbar_s = Pi and Gammabar_s = I - Pi at
+    every stage, Pi = I - E'(E E')^{-1} E the orthogonal projector onto ker E
+    (formed here without a null-space basis)."""
+    P = ds.config_problem("dwn128")
+    w = float(P.weights.W_u[0, 0])
+    assert np.array_equal(P.weights.W_u, w * np.eye(P.net.nu))
+    E = P.net.E
+    Pi = np.eye(P.net.nu) - E.T @ np.linalg.solve(E @ E.T, E)
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    for s in range(P.tree.N):
+        assert np.abs(sf.Fbar[s] - Pi / w).max() <= 1e-14 / w
+        assert np.abs(sf.Kbar[s] - Pi).max() <= 1e-13
+        assert np.abs(sf.Gbar[s] - (np.eye(P.net.nu) - Pi)).max() <= 1e-13
+
+
 def test_mass_balance_exact_every_iteration():
     """E u_n + Ed d_n = 0 holds to rounding at every APG iteration."""
     P = ds.config_problem("small")
