@@ -48,6 +48,27 @@ def sweep_bytes(nx, nu, elem, K, n_blocks, kind):
     return (per_node * K + n_blocks * nu * nu) * elem
 
 
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of each sweep kind from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, if it was taken on this workload with the
+    current kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"seg_sweeps_{workload}_{precision}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    line = next((l for l in open(path) if l.startswith("traffic-json:")), None)
+    if line is None:
+        return None
+    data = json.loads(line.split(":", 1)[1])
+    sha = hashlib.sha256()
+    for f in ("paper_1904_10548_amd/csrc/segment_kernels.hip", "paper_1904_10548_amd/csrc/kernels.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            sha.update(fh.read())
+    if data.get("kernel_sources_sha256") != sha.hexdigest():
+        return None
+    return data["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,8 +160,13 @@ def main():
         dom = max(kinds, key=lambda k: kinds[k]["ms"])
         d = kinds[dom]
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        tb = measured_traffic(args.config, args.precision)
+        traffic = None
+        if tb is not None and dom in tb:
+            traffic = round(tb[dom] / (d["avg_us"] * 1e-6) / 1e9, 2)
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "traffic_bytes_per_launch": tb[dom] if traffic is not None else None,
                 "kernel": f"seg_{dom}_kernel", "avg_launch_us": round(d["avg_us"], 3),
                 "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1),
                 "other": {k: {"avg_launch_us": round(v["avg_us"], 3), "launches": v["launches"],

@@ -166,7 +166,10 @@ tapg_status tapg_residual_history(tapg_solver solver, tapg_tree tree, double* hi
 tapg_status tapg_residuals(tapg_solver solver, tapg_tree tree, tapg_result* res);
 
 /* Lipschitz constant of the dual gradient of this tree by `iters` power
- * iterations on the device (step-size selection; see tapg_config.gamma). */
+ * iterations on the device (step-size selection; see tapg_config.gamma).  The
+ * estimate is kept with the tree and used by tapg_solve when cfg.gamma <= 0
+ * (L depends on the tree's structure and probabilities, not on its data).
+ * TAPG_ENUMERIC if the estimate is not a positive finite number. */
 tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iters, double* L);
 
 /* Sweep schedule of a tree (host only, no device needed).  The sweeps run

@@ -500,6 +500,9 @@ tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iter
     if (iters < 1) fail(TAPG_EINVAL, "iters must be >= 1");
     Slot& sl = dev_slot(solver, tree->h);
     *L = dev_power(solver, tree->h, sl, iters);
+    if (!(*L > 0) || !std::isfinite(*L)) fail(TAPG_ENUMERIC, "power iteration failed");
+    sl.L = *L;  // used by tapg_solve when cfg.gamma <= 0
+    sl.L_valid = true;
     return TAPG_OK;
   });
 }
