@@ -98,6 +98,8 @@ def main():
     except Exception:  # torch is optional plumbing here
         have_torch = False
 
+    if args.config == "batch64":
+        return main_batch(args, ds, tapg)
     P = ds.config_problem(args.config)
     net, w = P.net, P.weights
     prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
@@ -204,6 +206,86 @@ def main():
         "factor_blocks": n_blocks,
         "lipschitz_s": round(lipschitz_s, 4),
         "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    S.close()
+
+
+def main_batch(args, ds, tapg):
+    """64 trees of 16..256 scenarios (K from 349 to 4,605) on the Barcelona-sized
+    network, all solved by one tapg_batch_solve per step (cold start, each tree
+    to the tolerance with its own step size).  Value: trees solved per second."""
+    trees_p = [ds.config_problem("batch64", i) for i in range(64)]
+    P0 = trees_p[0]
+    net, w = P0.net, P0.weights
+    prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
+    S = tapg.Solver(dict(A=net.A, B=net.B, Gd=net.Gd, E=net.E, Ed=net.Ed, xmin=net.xmin,
+                         xmax=net.xmax, xs=net.xs, umin=net.umin, umax=net.umax),
+                    dict(W_alpha=w.W_alpha, W_s=w.W_s, W_x=w.W_x, alpha0=w.alpha0,
+                         c_energy=w.c_energy, W_u=w.W_u),
+                    P0.tree.N, gamma=0.0, tol=args.tol, max_iter=args.max_iter,
+                    check_every=args.check_every, precision=prec)
+    trees = [S.add_tree(P.tree.nodes_per_stage, P.tree.anc, P.tree.prob, P.data.demand,
+                        P.data.price) for P in trees_p]
+    ps, qs = [P.p for P in trees_p], [P.q for P in trees_p]
+    K_tot = sum(P.tree.K for P in trees_p)
+    t0 = time.perf_counter()
+    for t in trees:
+        tapg.tapg_estimate_lipschitz(S.h, t, 100)
+    lipschitz_s = time.perf_counter() - t0
+    print(f"[bench] batch64: 64 trees, {K_tot} nodes, power {lipschitz_s:.3f}s",
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        st, _, res = S.batch_solve(trees, ps, qs)
+        print(f"[bench] warmup {i}: iters {min(r.iters for r in res)}..{max(r.iters for r in res)} "
+              f"{res[0].solve_ms:.1f} ms", file=sys.stderr, flush=True)
+    lat, last = [], None
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t1 = time.perf_counter()
+        st, _, res = S.batch_solve(trees, ps, qs)
+        lat.append(time.perf_counter() - t1)
+        last = res
+        print(f"[bench] step {i}: iters {min(r.iters for r in res)}..{max(r.iters for r in res)} "
+              f"{lat[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    total = time.perf_counter() - t_start
+    lat_ms = np.array(lat) * 1e3
+    iters = [r.iters for r in last]
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the largest tree, scaled to the batch's total iterations x nodes
+        big = max(range(64), key=lambda k: trees_p[k].tree.K)
+        cb = cpu_baseline(trees_p[big], last[big].gamma, iters[big], args.cpu_seconds)
+        work_big = iters[big] * trees_p[big].tree.K
+        work_all = sum(it * P.tree.K for it, P in zip(iters, trees_p))
+        per_solve_s = (1.0 / cb["value"]) * work_all / work_big
+        cpu = {"value": round(64.0 / per_solve_s, 6), "unit": "trees/s", "cores": cb["cores"],
+               "kind": "oracle",
+               "sample": cb["sample"] + f"; scaled by node-iterations to all 64 trees "
+                                        f"({work_all} node-iterations)"}
+    out = {
+        "metric": METRIC + " (64-tree batch)",
+        "value": round(64 * args.steps / total, 4),
+        "unit": "trees/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == tapg.TAPG_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch64: 64 trees, S in 16..256, K total {K_tot}, "
+                               f"tol={args.tol:g}, cold start, one tapg_batch_solve per step",
+                   "trees": 64, "K_total": K_tot, "tol": args.tol, "precision": args.precision},
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "iters_min": int(min(iters)), "iters_max": int(max(iters)),
+        "converged": int(sum(r.converged for r in last)),
+        "lipschitz_s": round(lipschitz_s, 4),
+        "roofline": None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -150,6 +150,23 @@ tapg_status tapg_factor_blocks(tapg_solver solver, int* fid, int n, int* n_block
 tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, const double* q,
                        int warm_start, double* u0_out, tapg_result* res);
 
+/* Solve several trees in one set of launches (the paper's method on each tree;
+ * Sec. 4.3 iteration, Sec. 4.4 sweeps): the trees, which must share the
+ * factored horizon and appear once each, are swept together as one forest, each
+ * with its own step size (as tapg_solve would choose it), control block and stop
+ * test, so each result equals that of tapg_solve on the tree up to rounding.
+ * p[k] (nx), q[k] (nu): initial condition of tree k; warm_start (may be NULL):
+ * per tree, start from its last dual as tapg_solve would; u0_out (may be NULL,
+ * or hold NULL entries): root input of tree k (nu doubles); res (may be NULL):
+ * ntrees results.  Afterwards every tree can be queried as after tapg_solve.
+ * Returns TAPG_ENUMERIC if any tree's residual became non-finite, else
+ * TAPG_ENOTCONV if any tree stopped at max_iter with tol > 0, else TAPG_OK; the
+ * results of all trees are written in every case.  Needs the segment sweep
+ * kernels (nx, nu <= 128), else TAPG_EINVAL. */
+tapg_status tapg_batch_solve(tapg_solver solver, int ntrees, const tapg_tree* trees,
+                             const double* const* p, const double* const* q, const int* warm_start,
+                             double* const* u0_out, tapg_result* res);
+
 /* Primal iterate of the last solve: u [K*nu], x [K*nx] (node-major). */
 tapg_status tapg_get_primal(tapg_solver solver, tapg_tree tree, double* u, double* x);
 /* Dual iterate y^{nu*+1} of the last solve, node-major blocks (y1 [nx], y2 [nx],
@@ -175,7 +192,7 @@ tapg_status tapg_estimate_lipschitz(tapg_solver solver, tapg_tree tree, int iter
 /* Sweep schedule of a tree (host only, no device needed).  The sweeps run
  * as "levels" of consecutive stages; a level's workgroups each own a group of
  * consecutive nodes of its first stage and all their descendants inside the
- * level, at most 4 (FP64) or 8 (FP32) nodes per stage.  With levels == NULL
+ * level, at most 4 nodes per stage.  With levels == NULL
  * the library's planner chooses the cuts and group sizes (a cost model of
  * launch, stage and per-node costs); otherwise `levels` is "s0:g0,s1:g1,..."
  * (first stage and group size of each level, s0 = 0).  out[5*l .. 5*l+4]

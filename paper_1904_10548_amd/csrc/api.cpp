@@ -14,6 +14,11 @@ namespace tapg {
 namespace {
 thread_local std::string g_last_error;
 std::atomic<uint64_t> g_next_uid{1};
+}  // namespace
+
+uint64_t next_uid() { return g_next_uid.fetch_add(1); }
+
+namespace {
 
 bool finite_all(const double* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
@@ -433,6 +438,49 @@ tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, cons
   });
 }
 
+tapg_status tapg_batch_solve(tapg_solver solver, int ntrees, const tapg_tree* trees,
+                             const double* const* p, const double* const* q, const int* warm_start,
+                             double* const* u0_out, tapg_result* res) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    need(trees, "trees");
+    need(p, "p");
+    need(q, "q");
+    if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
+    std::vector<const TreeHost*> th(ntrees);
+    std::vector<Slot*> own(ntrees);
+    std::vector<double> gamma(ntrees);
+    std::vector<uint64_t> ids;
+    for (int k = 0; k < ntrees; ++k) {
+      check_pair(solver, trees[k]);
+      need(p[k], "p[k]");
+      need(q[k], "q[k]");
+      if (!finite_all(p[k], solver->net.nx) || !finite_all(q[k], solver->net.nu))
+        fail(TAPG_ENUMERIC, "non-finite p or q of tree " + std::to_string(k));
+      th[k] = &trees[k]->h;
+      ids.push_back(th[k]->uid);
+    }
+    std::sort(ids.begin(), ids.end());
+    if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+      fail(TAPG_EINVAL, "a tree appears twice in the batch");
+    for (int k = 0; k < ntrees; ++k) {
+      own[k] = &dev_slot(solver, *th[k]);
+      gamma[k] = solver_gamma(solver, *th[k], *own[k]);
+    }
+    std::vector<tapg_result> r(ntrees);
+    dev_batch_solve(solver, th, own, p, q, warm_start, gamma, r.data());
+    tapg_status worst = TAPG_OK;
+    for (int k = 0; k < ntrees; ++k) {
+      if (u0_out && u0_out[k]) dev_get_root_input(solver, *own[k], u0_out[k]);
+      if (res) res[k] = r[k];
+      if (own[k]->numeric) worst = TAPG_ENUMERIC;
+      else if (worst == TAPG_OK && !r[k].converged && solver->cfg.tol > 0) worst = TAPG_ENOTCONV;
+    }
+    if (worst == TAPG_ENUMERIC) set_error("a tree of the batch has a non-finite dual residual");
+    return worst;
+  });
+}
+
 static Slot& existing_slot(tapg_solver solver, tapg_tree tree) {
   check_pair(solver, tree);
   auto it = solver->slots.find(tree->h.uid);
@@ -514,7 +562,7 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
     need(nlevels, "nlevels");
     if (precision != TAPG_FP64 && precision != TAPG_FP32) fail(TAPG_EINVAL, "bad precision");
     const TreeHost& t = tree->h;
-    const int nbmax = precision == TAPG_FP32 ? 8 : 4;
+    const int nbmax = kSegNbMax;
     std::vector<LevelPlan> plans =
         (levels && levels[0]) ? levels_from_env(t, levels)
                               : plan_levels(t, nbmax, 114.0 * 114.0 / 64.0 / 2400.0);

@@ -75,6 +75,18 @@ struct TreeHost {
   int N, K, nd;
   std::vector<int> mu, offset, anc, cbeg, cend, stage;
   std::vector<double> prob, demand, price;
+  // A forest (a batch of trees sharing the horizon) uses the same layout: the
+  // stage-s nodes of tree 0, then those of tree 1, ...; the root of tree k has
+  // ancestor -1 - k.  tstart[s * (ntrees + 1) + k] is the first node of tree k
+  // at stage s (empty for a single tree).
+  int ntrees = 1;
+  std::vector<int> tstart;
+  int seg_begin(int s, int k) const {
+    return tstart.empty() ? offset[s] : tstart[(size_t)s * (ntrees + 1) + k];
+  }
+  int seg_end(int s, int k) const {
+    return tstart.empty() ? offset[s + 1] : tstart[(size_t)s * (ntrees + 1) + k + 1];
+  }
 };
 
 // Device control block of one tree slot (read by every kernel, written by
@@ -93,8 +105,7 @@ struct DevCtl {
   unsigned long long res_bits;  // running max |r| of the current iteration (bits of a double >= 0)
   double pw_scale;              // power iteration: 1/|v|
   double L;                     // power iteration: latest |M v| estimate
-  unsigned wg_done;             // workgroups of the closing launch that have finished
-  unsigned pad1;
+  unsigned pad1, pad2;
 };
 
 // Per-(solver, tree) device buffers.
@@ -130,6 +141,7 @@ struct Slot {
   bool L_valid = false;
   tapg_result last{};
   bool has_result = false;
+  bool numeric = false;  // the last solve hit a non-finite residual
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
   // segment schedule: levels top (stage 0) first
@@ -137,11 +149,25 @@ struct Slot {
     int s_begin, s_end, n_wg, nbm;
     int nch;  // most children of one workgroup below the level's last stage
     int2* d_ranges;
+    int* d_wgtree;  // tree of each workgroup (forests only)
   };
   std::vector<Level> levels;
   bool segmented = false;
   int part_total = 0;
+  int ntrees = 1;                // trees of the forest held by this slot
+  unsigned* d_counter = nullptr; // closing-launch workgroup counter
 };
+
+// Unique ids of trees and forests (never reused).
+uint64_t next_uid();
+
+// A batch of trees as one forest (forest.cpp); map[map_off[k] + n] is the
+// forest index of node n of tree k.
+TreeHost build_forest(const std::vector<const TreeHost*>& trees, std::vector<int>& map,
+                      std::vector<int>& map_off);
+// Copy the members' current demand and price into the forest (new version).
+void refresh_forest_data(const std::vector<const TreeHost*>& trees, const std::vector<int>& map,
+                         const std::vector<int>& map_off, TreeHost& f);
 
 struct SolverState;
 

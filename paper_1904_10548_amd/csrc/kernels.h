@@ -7,6 +7,9 @@ namespace tapg {
 
 constexpr int kThreads = 256;     // per-stage kernels
 constexpr int kSegThreads = 512;  // segment kernels
+// static LDS of a segment kernel (reductions, gamma-scaled bounds), reserved
+// out of the per-workgroup limit when the dynamic part is checked
+constexpr int kSegStaticLds = 16 * 1024;
 
 // Arguments of the per-stage sweep kernels.
 template <typename T>
@@ -87,9 +90,14 @@ struct SegArgs {
   T* jv;
   T* u;
   T* x;
-  DevCtl* ctl;
+  DevCtl* ctl;       // control block of each tree of the forest (one for a tree)
   double* part;
-  double* hist;
+  double* hist;      // residual history, hist_stride entries per tree
+  const int* wgtree; // tree of each workgroup of the launch (nullptr: one tree)
+  int ntrees;
+  int hist_stride;
+  int pq_stride;     // (p, q) of tree k at pq + k * pq_stride
+  unsigned* counter; // workgroups of the closing launch that have finished
 };
 
 // Launch wrappers (segment_kernels.hip).
@@ -119,5 +127,13 @@ void launch_cost(int K, int nx, int nu, int nd, int ns, int LDX, int LDU, const 
                  const double* alpha0, const double* cE, const double* xmin, const double* xmax,
                  const double* xs, const double* umin, const double* umax, double W_alpha,
                  double W_x, double W_s, double* part, double* out, hipStream_t st);
+// Per-tree (cost, box violation, equality violation) of a forest from the
+// per-node terms written by launch_cost: out[3 k .. 3 k + 2].
+void launch_cost_reduce_forest(const double* part, const int* tstart, int N, int ntrees,
+                               double* out, hipStream_t st);
+// Row gather (dst[r] = src[idx[r]]) or scatter (dst[idx[r]] = src[r]).
+template <typename T>
+void launch_copy_rows(const T* src, int ld_src, T* dst, int ld_dst, const int* idx, int rows,
+                      int width, bool scatter, hipStream_t st);
 
 }  // namespace tapg

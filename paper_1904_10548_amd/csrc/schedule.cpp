@@ -22,23 +22,42 @@ int nb_template(int w) {
   return t;
 }
 
+// Groups of g consecutive nodes of stage s, formed tree by tree, so that no
+// group (hence no workgroup) holds nodes of two trees of a forest.
+static void stage_groups(const TreeHost& t, int s, int g, std::vector<int>& lo,
+                         std::vector<int>& hi) {
+  lo.clear();
+  hi.clear();
+  for (int k = 0; k < t.ntrees; ++k) {
+    const int a = t.seg_begin(s, k), b = t.seg_end(s, k);
+    for (int x = a; x < b; x += g) {
+      lo.push_back(x);
+      hi.push_back(std::min(x + g, b));
+    }
+  }
+}
+
+// Widest stage-s segment of one tree.
+static int widest_tree_stage(const TreeHost& t, int s) {
+  int w = 0;
+  for (int k = 0; k < t.ntrees; ++k) w = std::max(w, t.seg_end(s, k) - t.seg_begin(s, k));
+  return w;
+}
+
 std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us) {
   const int N = t.N;
   const double c_launch = 3.0, c_stage = 0.25;
   const int conc = 512;  // workgroups resident at once (256 CUs x 2)
   std::vector<double> best(N + 1, 0.0);
   std::vector<LevelPlan> choice(N);
+  std::vector<int> lo, hi;
   for (int s = N - 1; s >= 0; --s) {
     best[s] = 1e300;
-    const int mu = t.mu[s], off = t.offset[s];
+    const int mu = widest_tree_stage(t, s);
     for (int g = 1; g <= std::max(1, mu); g *= 2) {
-      const int nwg = (mu + g - 1) / g;
       // widths of every group, stage by stage, extended one stage at a time
-      std::vector<int> lo(nwg), hi(nwg);
-      for (int w = 0; w < nwg; ++w) {
-        lo[w] = off + w * g;
-        hi[w] = std::min(off + (w + 1) * g, off + mu);
-      }
+      stage_groups(t, s, g, lo, hi);
+      const int nwg = (int)lo.size();
       double stage_sum = 0.0;
       for (int e = s; e < N; ++e) {
         int wmax = 0;
@@ -90,7 +109,9 @@ std::vector<LevelPlan> levels_from_env(const TreeHost& t, const char* spec) {
     const int e = i + 1 < cuts.size() ? cuts[i + 1].first - 1 : t.N - 1;
     if (s < 0 || s > e || e >= t.N || (i == 0 && s != 0))
       throw Fail{TAPG_EINVAL, "TAPG_LEVELS does not describe the stages 0..N-1"};
-    out.push_back(LevelPlan{s, e, g, 0, (t.mu[s] + g - 1) / g, 0.0});
+    std::vector<int> lo, hi;
+    stage_groups(t, s, g, lo, hi);
+    out.push_back(LevelPlan{s, e, g, 0, (int)lo.size(), 0.0});
   }
   return out;
 }
@@ -100,9 +121,11 @@ std::vector<std::pair<int, int>> level_ranges(const TreeHost& t, const LevelPlan
   const int nst = L.s_end - L.s_begin + 1;
   std::vector<std::pair<int, int>> rg((size_t)L.n_wg * nst);
   wmax = 0;
-  const int off = t.offset[L.s_begin], mu = t.mu[L.s_begin];
+  std::vector<int> glo, ghi;
+  stage_groups(t, L.s_begin, L.group, glo, ghi);
+  if ((int)glo.size() != L.n_wg) throw Fail{TAPG_EINVAL, "level plan does not match the tree"};
   for (int w = 0; w < L.n_wg; ++w) {
-    int lo = off + w * L.group, hi = std::min(off + (w + 1) * L.group, off + mu);
+    int lo = glo[w], hi = ghi[w];
     for (int k = 0; k < nst; ++k) {
       rg[(size_t)w * nst + k] = {lo, hi};
       wmax = std::max(wmax, hi - lo);

@@ -75,6 +75,52 @@ __device__ __forceinline__ T ldm(const T* __restrict__ p, size_t idx, bool ok) {
   return ok ? v : T(0);
 }
 
+// Four consecutive elements of an LDS vector (one 16-byte read for FP32, two
+// for FP64); p is 4-element aligned.
+__device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+// Register-resident GEMV slice: red[(ks*NB + b)*128 + r] = sum_{j<32} m[j] X[b*128 + kb + j]
+// for the columns b < ncols.  NC columns run together with four partial sums
+// each, so the FMAs do not form one dependent chain, and every lane of a wave
+// reads the same X addresses (kb is wave-uniform), 4 elements at a time.
+template <typename T, int NB, int NC>
+__device__ __forceinline__ void gemv_cols(const T (&m)[kKC], const T* X, int kb, int ks, int r,
+                                          int ncols, T* red) {
+  static_assert(NC == 1 || NC == 2, "one or two columns at a time");
+#pragma unroll
+  for (int b0 = 0; b0 < NB; b0 += NC) {
+    if (b0 < ncols) {
+      T acc[NC][4];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[c][q] = T(0);
+#pragma unroll
+      for (int j = 0; j < kKC; j += 4) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T v[4];
+          ld4(X + (b0 + c) * kLDU + kb + j, v);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[c][q] += m[j + q] * v[q];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (b0 + c < ncols)
+          red[(ks * NB + b0 + c) * kRT + r] = (acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3]);
+    }
+  }
+}
+
 // Streamed GEMV partials for a general matrix (A, A' or W_u), used only when
 // A != I or W_u is not a multiple of I: red[(ks*NB + b)*128 + r] =
 // sum_{k in slice ks} M(r, k) X[b][k].
@@ -103,11 +149,37 @@ __device__ __forceinline__ T sum_partials(const T* red, int b, int r) {
   return s;
 }
 
-// Sum over the 64 lanes of a wave by a xor butterfly: every lane gets the
-// same, run-to-run identical value (each pairwise sum is commutative).
+// A double moved across lanes by a DPP pattern (each 32-bit half separately).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), every lane getting the
+// same value: each step adds to a lane the value of a partner lane in the
+// other half of its current group, and both partners form the same sum (a + b
+// = b + a), so the result is identical in every lane and from run to run.
+// Steps: xor 1 and xor 2 inside a quad, mirror inside 8 and 16 lanes (DPP),
+// then rows 16 apart and halves 32 apart (gfx950 permlane swaps: with both
+// operands equal to v, the pair returned holds v of the lower and of the
+// upper partner in the same order in every lane).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  }
   return v;
 }
 
@@ -134,6 +206,40 @@ __device__ __forceinline__ double block_sum512(double v, double* s) {
   __syncthreads();
   return r;
 }
+
+// The first K entries of one CSR row held in registers (the row is the same
+// at every stage), the rest of the row, rare in a flow network whose rows have
+// a few entries each, read from LDS.  apply() adds the row's products in CSR
+// order; the register entries' loads are independent of each other.
+template <typename T, int K>
+struct RegRow {
+  int col[K];
+  T val[K];
+  int n, xb, xe;  // entries in registers; LDS range [xb, xe) of the others
+  __device__ __forceinline__ void load(const int* srow, const int* scol, const T* sval, int i,
+                                       bool ok) {
+    const int p0 = ok ? srow[i] : 0, p1 = ok ? srow[i + 1] : 0;
+    n = min(p1 - p0, K);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int p = k < n ? p0 + k : 0;
+      col[k] = k < n ? scol[p] : 0;
+      val[k] = k < n ? sval[p] : T(0);
+    }
+    xb = p0 + n;
+    xe = p1;
+  }
+  __device__ __forceinline__ T apply(T acc, const T* X, const int* scol, const T* sval) const {
+    T t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] = X[col[k]];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < n) acc += val[k] * t[k];
+    for (int p = xb; p < xe; ++p) acc += sval[p] * X[scol[p]];
+    return acc;
+  }
+};
 
 // Copy of a CSR matrix into LDS (row pointers, columns, values).
 template <typename T>
@@ -169,7 +275,8 @@ size_t seg_lds_bytes(const SegArgs<T>& a) {
 // ---------------------------------------------------------------------------
 template <typename T, int NB>
 __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
-  const DevCtl* ctl = a.ctl;
+  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
+  const DevCtl* ctl = a.ctl + tree;
   if (ctl->done) return;
   constexpr int QX = NB * 128 / kSegThreads > 0 ? NB * 128 / kSegThreads : 1;
   const int tid = threadIdx.x;
@@ -201,6 +308,13 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
     }
     csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
     __syncthreads();
+  }
+  // this thread's rows of B' (one per u-slot)
+  RegRow<T, 2> brow[QX];
+#pragma unroll
+  for (int q = 0; q < QX; ++q) {
+    const int i = (tid + q * kSegThreads) % LDU;
+    brow[q].load(sRow, sCol, sVal, i, i < nu);
   }
 
   const int r = tid % kRT;
@@ -295,7 +409,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
     const bool kids = s < a.s_end || has_kids_last;  // children are in LDS
 
     // consume the prefetched inputs of this stage
-    T aval[QX], w3v[QX], sig[QX], kap[QX], lsum[QX];
+    T aval[QX], w3v[QX], kap[QX], lsum[QX];
 #pragma unroll
     for (int q = 0; q < QX; ++q) {
       const int idx = tid + q * kSegThreads;
@@ -312,16 +426,8 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
     }
 #pragma unroll
     for (int q = 0; q < QX; ++q) {
-      const int idx = tid + q * kSegThreads;
-      const int b = idx / LDU, i = idx - b * LDU;
-      const bool ok = idx < NB * LDU && b < nb && i < nu;
       w3v[q] = power ? scale * C.pu[q][0] : wext(C.pu[q][0], C.pu[q][1], beta);
       kap[q] = power ? T(0) : C.pu[q][2];
-      T sg = T(0);
-      if (ok && kids) {
-        for (int c = C.cu[q][0]; c < C.cu[q][1]; ++c) sg += sJ[(c - lo_c) * LDU + i];
-      }
-      sig[q] = ok ? sg : T(0);
     }
     flush();
     // the next stage's factor and inputs load while this stage computes.  The
@@ -357,12 +463,15 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
       const int b = idx / LDU, i = idx - b * LDU;
       const bool ok = idx < NB * LDU && b < nb && i < nu;
       T e = w3v[q];
-      if (ok) {
-        const int pe = sRow[i + 1];
-        for (int p = sRow[i]; p < pe; ++p) e += sVal[p] * sLn[b * LDX + sCol[p]];
+      if (ok) e = brow[q].apply(e, sLn + b * LDX, sCol, sVal);
+      // children's j, summed here (after the barrier above) so that the
+      // previous stage needs no closing barrier for its writes to sJ
+      T sg = T(0);
+      if (ok && kids) {
+        for (int c = C.cu[q][0]; c < C.cu[q][1]; ++c) sg += sJ[(c - lo_c) * LDU + i];
       }
-      vv[q] = ok ? T(-0.5) * e + (a.wu_scalar ? a.wu * sig[q] : T(0)) : T(0);
-      if (idx < NB * LDU) sV[idx] = a.wu_scalar ? vv[q] : sig[q];
+      vv[q] = ok ? T(-0.5) * e + (a.wu_scalar ? a.wu * sg : T(0)) : T(0);
+      if (idx < NB * LDU) sV[idx] = a.wu_scalar ? vv[q] : sg;
     }
     __syncthreads();
     if (!a.wu_scalar) {  // v += W_u sigma
@@ -380,15 +489,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
       __syncthreads();
     }
     // j = kappa + Fbar_s v   (register-resident Fbar_s)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (b < nb) {
-        T acc = T(0);
-#pragma unroll
-        for (int j = 0; j < kKC; ++j) acc += mreg[j] * sV[b * kLDU + kb + j];
-        red[(ks * NB + b) * kRT + r] = acc;
-      }
-    }
+    gemv_cols<T, NB, (NB >= 2 && sizeof(T) == 4 ? 2 : 1)>(mreg, sV, kb, ks, r, nb, red);
     if (s > a.s_begin) {
       const int fn = __builtin_amdgcn_readfirstlane(sFid[s - 1 - a.s_begin]);
       if (fn != f_cur) {
@@ -417,7 +518,10 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
         if (idx < NB * LDX && b < nb && i < nx) a.lam[(size_t)(lo + b) * LDX + i] = sLn[idx];
       }
     }
-    __syncthreads();
+    // No closing barrier: the next stage writes sLn (this stage's sLc, read
+    // before this stage's first barrier), sV and red only after barriers of
+    // its own that every wave reaches after finishing this stage, and reads
+    // this stage's sJ only after its first barrier.
     T* t = sLc;
     sLc = sLn;
     sLn = t;
@@ -433,6 +537,65 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Closing protocol of the last forward launch of an iteration: every workgroup
+// (those of trees that have stopped too) checks in, and the last one to do so
+// ends the iteration of every tree still running: residual max into the
+// history, stop tests, theta / beta (or, in the power iteration of one tree,
+// the norm of the new iterate).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void seg_iteration_end(const SegArgs<T>& a, double* sred, int* s_last) {
+  const int tid = threadIdx.x;
+  __threadfence();
+  if (tid == 0) {
+    const unsigned prev = atomicAdd(a.counter, 1u);
+    *s_last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!*s_last) return;
+  __threadfence();
+  if (a.mode == 1) {
+    double acc = 0.0;
+    for (int i = tid; i < a.part_total; i += kSegThreads) acc += a.part[i];
+    const double tot = block_sum512(acc, sred);
+    if (tid == 0) {
+      DevCtl* c = a.ctl;
+      const double L = sqrt(tot);
+      c->L = L;
+      c->pw_scale = L > 0.0 ? 1.0 / L : 0.0;
+      c->iter = c->iter + 1;
+      *a.counter = 0u;
+    }
+    return;
+  }
+  for (int k = tid; k < a.ntrees; k += kSegThreads) {
+    DevCtl* c = a.ctl + k;
+    if (c->done) continue;
+    const int it = c->iter;
+    const double res = __longlong_as_double((long long)atomicExch(&c->res_bits, 0ull));
+    a.hist[(size_t)k * a.hist_stride + it] = res;
+    c->last_res = res;
+    c->iter = it + 1;
+    if (!(res < INFINITY)) {
+      c->numeric = 1;
+      c->done = 1;
+    } else if (c->tol > 0.0 && res <= c->tol) {
+      c->converged = 1;
+      c->done = 1;
+    } else if (it + 1 >= c->max_iter) {
+      c->done = 1;
+    }
+    const double th = c->theta;
+    const double t2 = th * th;
+    const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
+    c->theta_prev = th;
+    c->theta = thn;
+    c->beta = thn * (1.0 / th - 1.0);
+  }
+  if (tid == 0) *a.counter = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // Forward sweep over one level, stages s_begin up to s_end, with the fused
 // prox / dual update.  Per node:
 //   u_n = Fbar_s (W_u u_anc) + j_n / p_n       (= Kbar_s u_anc + k_n)
@@ -444,8 +607,14 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
 // ---------------------------------------------------------------------------
 template <typename T, int NB>
 __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
-  DevCtl* ctl = a.ctl;
-  if (ctl->done) return;
+  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
+  DevCtl* ctl = a.ctl + tree;
+  __shared__ double sred[kSegThreads];
+  __shared__ int s_last;
+  if (ctl->done) {  // this tree has stopped; the closing launch still counts it
+    if (a.last_level) seg_iteration_end(a, sred, &s_last);
+    return;
+  }
   constexpr int QX = NB * 128 / kSegThreads > 0 ? NB * 128 / kSegThreads : 1;
   const int tid = threadIdx.x;
   const int it = ctl->iter;
@@ -468,8 +637,6 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
   int* sRow = sFid + a.nst + (a.nst & 1);            // CSR of B (nx rows), 8-byte aligned
   int* sCol = sRow + nx + 1;
   T* sVal = reinterpret_cast<T*>(sCol + a.nnzB + ((nx + 1 + a.nnzB) & 1));  // 8-byte aligned
-  __shared__ double sred[kSegThreads];
-  __shared__ int s_last;
   {
     const int2* rg = a.ranges + (size_t)blockIdx.x * a.nst;
     for (int i = tid; i < a.nst; i += kSegThreads) {
@@ -482,16 +649,18 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
   const int r = tid % kRT;
   const int ks = __builtin_amdgcn_readfirstlane(tid / kRT);
   const int kb = ks * kKC;
-  // stage-invariant bounds of this thread's slots
-  T bxlo[QX], bxhi[QX], bxs[QX], bulo[QX], buhi[QX];
-#pragma unroll
-  for (int q = 0; q < QX; ++q) {
-    const int ix = (tid + q * kSegThreads) % LDX, iu = (tid + q * kSegThreads) % LDU;
-    bxlo[q] = ldm(a.xmin, ix, ix < nx);
-    bxhi[q] = ldm(a.xmax, ix, ix < nx);
-    bxs[q] = ldm(a.xs, ix, ix < nx);
-    bulo[q] = ldm(a.umin, iu, iu < nu);
-    buhi[q] = ldm(a.umax, iu, iu < nu);
+  // Stage-invariant bounds of this thread's slots, scaled by gamma: for a box
+  // C, gamma P_C(v / gamma) = P_{gamma C}(v), so the prox needs no division
+  // (and a component inside the box leaves r = v - v = 0 exactly).
+  // Kept in LDS (registers are scarce here): [xmin | xmax | xs] by x-slot,
+  // [umin | umax] by u-slot, 128 entries each (nx, nu <= 128 on this path).
+  __shared__ T sBnd[5 * kRT];
+  for (int i = tid; i < kRT; i += kSegThreads) {
+    sBnd[i] = gam * ldm(a.xmin, i, i < nx);
+    sBnd[kRT + i] = gam * ldm(a.xmax, i, i < nx);
+    sBnd[2 * kRT + i] = gam * ldm(a.xs, i, i < nx);
+    sBnd[3 * kRT + i] = gam * ldm(a.umin, i, i < nu);
+    sBnd[4 * kRT + i] = gam * ldm(a.umax, i, i < nu);
   }
   // Per-node inputs of a stage: u-slots (j, 1/p, parent, y3, y3o), x-slots
   // (g, parent, y1, y1o, y2, y2o).  Two sets alternate between stages, so the
@@ -534,7 +703,14 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
   };
 
   int s = a.s_begin;
-  __syncthreads();  // sRg, sFid ready
+  __syncthreads();  // sRg, sFid, CSR ready
+  // this thread's rows of B (one per x-slot)
+  RegRow<T, 3> brow[QX];
+#pragma unroll
+  for (int q = 0; q < QX; ++q) {
+    const int i = (tid + q * kSegThreads) % LDX;
+    brow[q].load(sRow, sCol, sVal, i, i < nx);
+  }
   int f_cur = __builtin_amdgcn_readfirstlane(sFid[0]);
   load_factor<T>(a.F + (size_t)f_cur * kLDU * kLDU, r, kb, mreg);
   load_stage(s, PA);
@@ -552,17 +728,20 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
       const int b = idx / LDU, i = idx - b * LDU;
       T v = T(0);
       if (b < np && i < nu)
-        v = par0 >= 0 ? a.u[(size_t)(lo_p + b) * LDU + i] : (power ? T(0) : a.pq[LDX + i]);
+        v = par0 >= 0 ? a.u[(size_t)(lo_p + b) * LDU + i]
+                      : (power ? T(0) : a.pq[(size_t)tree * a.pq_stride + LDX + i]);
       sUp[idx] = v;
     }
     for (int idx = tid; idx < NB * LDX; idx += kSegThreads) {
       const int b = idx / LDX, i = idx - b * LDX;
       T v = T(0);
       if (b < np && i < nx)
-        v = par0 >= 0 ? a.x[(size_t)(lo_p + b) * LDX + i] : (power ? T(0) : a.pq[i]);
+        v = par0 >= 0 ? a.x[(size_t)(lo_p + b) * LDX + i]
+                      : (power ? T(0) : a.pq[(size_t)tree * a.pq_stride + i]);
       sXp[idx] = v;
     }
   }
+  __syncthreads();  // the first stage's parents are in LDS
   double rmax = 0.0, zsq = 0.0;
   const bool wave_norm = LDX == 64;  // one node's x-block is exactly one wave
 
@@ -603,7 +782,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
     }
     flush();
     load_stage(s < a.s_end ? s + 1 : s, Nx);  // unconditional, as in the backward sweep
-    __syncthreads();
+    // (the parents in sUp / sXp were written before the previous barrier)
     const T* V = sUp;
     if (!a.wu_scalar) {  // W_u u_anc per parent, into sUn
       stream_partials<T, NB>(a.Wu, LDU, nu, nu, sUp, LDU, np, red);
@@ -616,15 +795,8 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
       V = sUn;
     }
     // Fbar_s (W_u u_anc), one column per parent
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (b < np) {
-        T acc = T(0);
-#pragma unroll
-        for (int j = 0; j < kKC; ++j) acc += mreg[j] * V[b * kLDU + kb + j];
-        red[(ks * NB + b) * kRT + r] = acc;
-      }
-    }
+    // (one column at a time in FP64: the forward kernel's registers are scarce)
+    gemv_cols<T, NB, (NB >= 2 && NB <= 4 && sizeof(T) == 4 ? 2 : 1)>(mreg, V, kb, ks, r, np, red);
     // this stage's factor is consumed: load the next stage's into the same
     // registers if it is another block
     if (s < a.s_end) {
@@ -668,8 +840,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
       if (idx < NB * LDX && b < nb && i < nx) {
         const int pb = C.pax[q] >= 0 ? C.pax[q] - lo_p : 0;
         xn = a.a_ident ? sXp[pb * LDX + i] : sum_partials<T, NB>(red, pb, i);
-        const int pe = sRow[i + 1];
-        for (int p = sRow[i]; p < pe; ++p) xn += sVal[p] * sUn[b * LDU + sCol[p]];
+        xn = brow[q].apply(xn, sUn + b * LDU, sCol, sVal);
         if (!power) xn += C.pg[q];
         dnx[q] = lo + b;
       }
@@ -704,9 +875,9 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
         if (idx < NB * LDU && b < nb && i < nu) {
           const T w = w3c[q];
           const T v = w + gam * uv[q];
-          const T y = v - gam * fmin(fmax(v / gam, bulo[q]), buhi[q]);
+          const T y = v - fmin(fmax(v, sBnd[3 * kRT + i]), sBnd[4 * kRT + i]);
           dy3[q] = y;
-          double d = fabs((double)y - (double)w) / gam64;
+          double d = fabs((double)y - (double)w);
           if (!(d <= 1.0e308)) d = INFINITY;
           rmax = fmax(rmax, d);
         }
@@ -722,8 +893,8 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
         const T w1 = w1c[q];
         const T w2 = w2c[q];
         const T v1 = w1 + gam * xv[q], v2 = w2 + gam * xv[q];
-        const T rr1 = v1 - gam * fmin(fmax(v1 / gam, bxlo[q]), bxhi[q]);
-        const T rr2 = v2 - gam * fmax(v2 / gam, bxs[q]);
+        const T rr1 = v1 - fmin(fmax(v1, sBnd[i]), sBnd[kRT + i]);
+        const T rr2 = v2 - fmax(v2, sBnd[2 * kRT + i]);
         r1v[q] = ok ? rr1 : T(0);
         r2v[q] = ok ? rr2 : T(0);
         w1v[q] = w1;
@@ -778,15 +949,19 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
           const T y1 = r1v[q] * sc1, y2 = r2v[q] * sc2;
           dy1[q] = y1;
           dy2[q] = y2;
-          double d1 = fabs((double)y1 - (double)w1v[q]) / gam64;
-          double d2 = fabs((double)y2 - (double)w2v[q]) / gam64;
+          double d1 = fabs((double)y1 - (double)w1v[q]);
+          double d2 = fabs((double)y2 - (double)w2v[q]);
           if (!(d1 <= 1.0e308)) d1 = INFINITY;
           if (!(d2 <= 1.0e308)) d2 = INFINITY;
           rmax = fmax(rmax, fmax(d1, d2));
         }
       }
     }
-    __syncthreads();
+    // Closing barrier only for the LDS norm reduction, which used red as
+    // scratch; otherwise the next stage reads sUn / sXn (written before the
+    // barrier after u) and writes sUp, sXp and red only after barriers every
+    // wave reaches after finishing this stage.
+    if (!wave_norm) __syncthreads();
     // this stage's nodes are the next stage's parents
     T* t = sUp;
     sUp = sUn;
@@ -810,54 +985,12 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
     const double tot = block_sum512(zsq, sred);
     if (tid == 0) a.part[a.part_base + blockIdx.x] = tot;
   } else {
-    const double m = block_max512(rmax, sred);
+    // max |y+ - w| / gamma: the division by gamma > 0 is monotone, so dividing
+    // the workgroup's max once gives the max of the quotients exactly
+    const double m = block_max512(rmax, sred) / gam64;
     if (tid == 0) atomicMax(&ctl->res_bits, (unsigned long long)__double_as_longlong(m));
   }
-  if (!a.last_level) return;
-  __threadfence();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(&ctl->wg_done, 1u);
-    s_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  if (power) {
-    double acc = 0.0;
-    for (int i = tid; i < a.part_total; i += kSegThreads) acc += a.part[i];
-    const double tot = block_sum512(acc, sred);
-    if (tid == 0) {
-      const double L = sqrt(tot);
-      ctl->L = L;
-      ctl->pw_scale = L > 0.0 ? 1.0 / L : 0.0;
-      ctl->iter = it + 1;
-      ctl->wg_done = 0u;
-    }
-    return;
-  }
-  if (tid == 0) {
-    DevCtl* c = ctl;
-    const double res = __longlong_as_double((long long)atomicExch(&c->res_bits, 0ull));
-    a.hist[it] = res;
-    c->last_res = res;
-    c->iter = it + 1;
-    if (!(res < INFINITY)) {
-      c->numeric = 1;
-      c->done = 1;
-    } else if (c->tol > 0.0 && res <= c->tol) {
-      c->converged = 1;
-      c->done = 1;
-    } else if (it + 1 >= c->max_iter) {
-      c->done = 1;
-    }
-    const double th = c->theta;
-    const double t2 = th * th;
-    const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
-    c->theta_prev = th;
-    c->theta = thn;
-    c->beta = thn * (1.0 / th - 1.0);
-    c->wg_done = 0u;
-  }
+  if (a.last_level) seg_iteration_end(a, sred, &s_last);
 }
 
 // ---------------------------------------------------------------------------
@@ -873,7 +1006,6 @@ void launch_seg_nb(bool fwd, const SegArgs<T>& a, int n_wg, hipStream_t st) {
 template <typename T>
 void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st) {
   switch (nbm) {
-    case 8: launch_seg_nb<T, 8>(fwd, a, n_wg, st); break;
     case 4: launch_seg_nb<T, 4>(fwd, a, n_wg, st); break;
     case 2: launch_seg_nb<T, 2>(fwd, a, n_wg, st); break;
     default: launch_seg_nb<T, 1>(fwd, a, n_wg, st); break;
@@ -883,7 +1015,6 @@ void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st
 template <typename T>
 size_t seg_lds(int nbm, const SegArgs<T>& a) {
   switch (nbm) {
-    case 8: return seg_lds_bytes<T, 8>(a);
     case 4: return seg_lds_bytes<T, 4>(a);
     case 2: return seg_lds_bytes<T, 2>(a);
     default: return seg_lds_bytes<T, 1>(a);

@@ -19,6 +19,17 @@ struct NetDev {
   T *Bval = nullptr, *Btval = nullptr, *Wu = nullptr;
 };
 
+// A cached batch: the forest of its trees (keyed by their ids) and the
+// device tables that map every tree's rows into the forest.
+struct Batch {
+  std::vector<uint64_t> versions;  // member data versions held by the forest
+  TreeHost forest;
+  std::vector<int> map, map_off;   // forest index of node n of tree k: map[map_off[k] + n]
+  int* d_map = nullptr;
+  int* d_tstart = nullptr;
+  double* d_red = nullptr;         // per tree: cost, box and equality violations
+};
+
 struct DevExtra {
   // FP64 operands of the data step and of the cost evaluation.
   double *Gd = nullptr;    // nx x nd, col-major ld LDX
@@ -54,6 +65,7 @@ struct tapg_solver_s {
   tapg::NetDev<float> d32;
   tapg::DevExtra dx;
   std::map<uint64_t, tapg::Slot> slots;
+  std::map<std::vector<uint64_t>, tapg::Batch> batches;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool use_graph = true;
   // structure of the network and weights (detected at creation)
@@ -72,7 +84,10 @@ struct tapg_solver_s {
 
 namespace tapg {
 
-// Segment schedule (schedule.cpp).
+// Segment schedule (schedule.cpp).  A workgroup holds at most kSegNbMax nodes
+// of one stage (kernel templates NB = 1, 2, 4; wider groups would spill
+// registers).
+constexpr int kSegNbMax = 4;
 struct LevelPlan {
   int s_begin, s_end, group, nbm, n_wg;
   double cost;
@@ -89,6 +104,12 @@ void dev_upload_factors(tapg_solver_s* S);   // Fbar/Kbar/Gbar to the device
 Slot& dev_slot(tapg_solver_s* S, const TreeHost& t);  // allocate/upload as needed
 void dev_solve(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
                const double* q, bool warm, double gamma, tapg_result& res);
+// Solve several trees in one set of launches (a forest); results go to each
+// tree's own slot as after tapg_solve.
+void dev_batch_solve(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
+                     const std::vector<Slot*>& own, const double* const* p,
+                     const double* const* q, const int* warm, const std::vector<double>& gamma,
+                     tapg_result* res);
 double dev_power(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters);
 void dev_get_primal(tapg_solver_s* S, Slot& sl, double* u, double* x);
 void dev_get_dual(tapg_solver_s* S, Slot& sl, double* y);

@@ -226,6 +226,11 @@ SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mod
   a.ctl = sl.d_ctl;
   a.part = sl.d_part;
   a.hist = sl.d_hist;
+  a.ntrees = sl.ntrees;
+  a.hist_stride = sl.hist_cap;
+  a.pq_stride = S->LDX + S->LDU;
+  a.counter = sl.d_counter;
+  a.wgtree = nullptr;
   return a;
 }
 
@@ -256,6 +261,7 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
         a.s_end = L.s_end;
         a.nst = L.s_end - L.s_begin + 1;
         a.ranges = L.d_ranges;
+        a.wgtree = L.d_wgtree;
         a.part_base = bases[l];
         a.nch = L.nch;
         a.last_level = (pass == 1 && l == nl - 1) ? 1 : 0;
@@ -559,8 +565,11 @@ void dev_free_slot(Slot& sl) {
   dfree(sl.d_kappa); dfree(sl.d_g); dfree(sl.d_pq); dfree(sl.d_pq64);
   dfree(sl.d_P0); dfree(sl.d_P1);
   dfree(sl.d_Y0); dfree(sl.d_Y1); dfree(sl.d_lam); dfree(sl.d_j); dfree(sl.d_u); dfree(sl.d_x);
-  dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part);
-  for (auto& L : sl.levels) dfree(L.d_ranges);
+  dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part); dfree(sl.d_counter);
+  for (auto& L : sl.levels) {
+    dfree(L.d_ranges);
+    dfree(L.d_wgtree);
+  }
   sl.levels.clear();
 }
 
@@ -569,6 +578,12 @@ void dev_release(tapg_solver_s* S) {
   if (S->stream) (void)hipStreamSynchronize(S->stream);
   for (auto& kv : S->slots) dev_free_slot(kv.second);
   S->slots.clear();
+  for (auto& kv : S->batches) {
+    dfree(kv.second.d_map);
+    dfree(kv.second.d_tstart);
+    dfree(kv.second.d_red);
+  }
+  S->batches.clear();
   free_net(S->d64);
   free_net(S->d32);
   dfree(S->dx.Gd); dfree(S->dx.Pd); dfree(S->dx.Gbar); dfree(S->dx.E); dfree(S->dx.Ed);
@@ -678,17 +693,20 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       sl.d_price = dmalloc<double>(K);
       sl.d_kappa = dalloc((size_t)K * LDU);
       sl.d_g = dalloc((size_t)K * LDX);
-      sl.d_pq = dalloc(LDX + LDU);
-      sl.d_pq64 = dmalloc<double>(LDX + LDU);
+      sl.ntrees = t.ntrees;
+      sl.d_pq = dalloc((size_t)t.ntrees * (LDX + LDU));
+      sl.d_pq64 = dmalloc<double>((size_t)t.ntrees * (LDX + LDU));
+      sl.d_counter = dmalloc<unsigned>(1);
+      TAPG_HIP(hipMemsetAsync(sl.d_counter, 0, sizeof(unsigned), st));
       sl.d_Y0 = dalloc((size_t)K * LDY);
       sl.d_Y1 = dalloc((size_t)K * LDY);
       sl.d_lam = dalloc((size_t)K * LDX);
       sl.d_j = dalloc((size_t)K * LDU);
       sl.d_u = dalloc((size_t)K * LDU);
       sl.d_x = dalloc((size_t)K * LDX);
-      sl.d_ctl = dmalloc<DevCtl>(1);
+      sl.d_ctl = dmalloc<DevCtl>(t.ntrees);
       sl.hist_cap = std::max(1, S->cfg.max_iter);
-      sl.d_hist = dmalloc<double>(sl.hist_cap);
+      sl.d_hist = dmalloc<double>((size_t)sl.hist_cap * t.ntrees);
       sl.node_offset = t.offset;
       sl.nb_of_stage.resize(t.N);
       sl.tiles_of_stage.resize(t.N);
@@ -705,7 +723,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       sl.tile_offset[t.N] = tot;
       sl.total_tiles = tot;
       if (S->seg_ok) {
-        const int nbmax = S->fp32 ? 8 : 4;
+        const int nbmax = kSegNbMax;
         const double node_us = (double)S->net.nu * S->net.nu / 64.0 / 2400.0 * (S->fp32 ? 0.5 : 1.0);
         const char* spec = std::getenv("TAPG_LEVELS");
         std::vector<LevelPlan> plans =
@@ -727,17 +745,28 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
               nch = std::max(nch, t.cend[q.second - 1] - t.cbeg[q.first]);
             }
           }
-          Slot::Level L{P.s_begin, P.s_end, P.n_wg, nb_template(wmax), nch, nullptr};
+          Slot::Level L{P.s_begin, P.s_end, P.n_wg, nb_template(wmax), nch, nullptr, nullptr};
           {
             const int nst = P.s_end - P.s_begin + 1;
             const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, nst, nch)
                                        : seg_lds_probe<double>(S, L.nbm, nst, nch);
-            if (lds > S->lds_limit)
+            if (lds + kSegStaticLds > S->lds_limit)
               throw Fail{TAPG_EINVAL, "segment schedule needs " + std::to_string(lds) +
                                           " bytes of LDS per workgroup (limit " +
                                           std::to_string(S->lds_limit) + ")"};
           }
           L.d_ranges = upload(rg, st);
+          if (t.ntrees > 1) {  // the tree of each workgroup, from its first node
+            const int nst = P.s_end - P.s_begin + 1;
+            std::vector<int> wt(P.n_wg, 0);
+            for (int w = 0; w < P.n_wg; ++w) {
+              const int n0 = rp[(size_t)w * nst].first;
+              int k = 0;
+              while (k + 1 < t.ntrees && t.seg_begin(P.s_begin, k + 1) <= n0) ++k;
+              wt[w] = k;
+            }
+            L.d_wgtree = upload(wt, st);
+          }
           sl.levels.push_back(L);
           ptot += P.n_wg;
         }
@@ -756,7 +785,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
   if (sl.hist_cap < S->cfg.max_iter) {
     dfree(sl.d_hist);
     sl.hist_cap = S->cfg.max_iter;
-    sl.d_hist = dmalloc<double>(sl.hist_cap);
+    sl.d_hist = dmalloc<double>((size_t)sl.hist_cap * sl.ntrees);
     if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
     sl.graph = nullptr;
   }
@@ -778,6 +807,182 @@ void dev_solve(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p, c
     solve_impl<float>(S, t, sl, p, q, warm, gamma, res);
   else
     solve_impl<double>(S, t, sl, p, q, warm, gamma, res);
+}
+
+namespace {
+template <typename T>
+void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
+                const std::vector<Slot*>& own, const double* const* p, const double* const* q,
+                const int* warm, const std::vector<double>& gam, tapg_result* res) {
+  const NetworkHost& h = S->net;
+  hipStream_t st = S->stream;
+  const int LDX = S->LDX, LDU = S->LDU, LDY = S->LDY, PQ = LDX + LDU;
+  const int nt = (int)trees.size();
+  // the forest of this batch, cached by the member ids
+  std::vector<uint64_t> key(nt);
+  for (int k = 0; k < nt; ++k) key[k] = trees[k]->uid;
+  auto bit = S->batches.find(key);
+  if (bit == S->batches.end()) {
+    Batch b;
+    b.forest = build_forest(trees, b.map, b.map_off);
+    for (const TreeHost* t : trees) b.versions.push_back(t->version);
+    try {
+      b.d_map = upload(b.map, st);
+      b.d_tstart = upload(b.forest.tstart, st);
+      b.d_red = dmalloc<double>((size_t)3 * nt);
+    } catch (...) {
+      dfree(b.d_map); dfree(b.d_tstart); dfree(b.d_red);
+      throw;
+    }
+    bit = S->batches.emplace(key, std::move(b)).first;
+  } else {
+    bool stale = false;
+    for (int k = 0; k < nt; ++k) stale = stale || bit->second.versions[k] != trees[k]->version;
+    if (stale) {
+      refresh_forest_data(trees, bit->second.map, bit->second.map_off, bit->second.forest);
+      for (int k = 0; k < nt; ++k) bit->second.versions[k] = trees[k]->version;
+    }
+  }
+  Batch& B = bit->second;
+  const TreeHost& f = B.forest;
+  Slot& sl = dev_slot(S, f);
+  if (!sl.segmented)
+    throw Fail{TAPG_EINVAL, "batched solves need the segment kernels (nx, nu <= 128, sparse B)"};
+  // (p, q) and control block of every tree
+  std::vector<double> pq64((size_t)nt * PQ, 0.0);
+  std::vector<DevCtl> c(nt);
+  for (int k = 0; k < nt; ++k) {
+    for (int i = 0; i < h.nx; ++i) pq64[(size_t)k * PQ + i] = p[k][i];
+    for (int i = 0; i < h.nu; ++i) pq64[(size_t)k * PQ + LDX + i] = q[k][i];
+    c[k] = DevCtl{};
+    c[k].max_iter = S->cfg.max_iter;
+    c[k].tol = S->cfg.tol;
+    c[k].gamma = gam[k];
+    c[k].theta = 1.0;
+    c[k].theta_prev = 1.0;
+    c[k].beta = 0.0;
+  }
+  std::vector<T> pqT(pq64.begin(), pq64.end());
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemcpyAsync(sl.d_ctl, c.data(), c.size() * sizeof(DevCtl), hipMemcpyHostToDevice, st));
+  // dual start: zero, then the warm trees' latest duals into both buffers
+  const size_t ybytes = (size_t)f.K * LDY * sizeof(T);
+  TAPG_HIP(hipMemsetAsync(sl.d_Y0, 0, ybytes, st));
+  TAPG_HIP(hipMemsetAsync(sl.d_Y1, 0, ybytes, st));
+  for (int k = 0; k < nt; ++k) {
+    if (!(warm && warm[k] && own[k]->has_dual)) continue;
+    const T* src = static_cast<const T*>(own[k]->last_iter_parity ? own[k]->d_Y1 : own[k]->d_Y0);
+    const int* idx = B.d_map + B.map_off[k];
+    launch_copy_rows<T>(src, LDY, static_cast<T*>(sl.d_Y0), LDY, idx, trees[k]->K, LDY, true, st);
+    launch_copy_rows<T>(src, LDY, static_cast<T*>(sl.d_Y1), LDY, idx, trees[k]->K, LDY, true, st);
+  }
+  TAPG_HIP(hipGetLastError());
+  TAPG_HIP(hipEventRecord(S->ev0, st));
+  launch_data_step<T>(f.K, h.nx, h.nu, h.nd, LDX, LDU, (const int*)sl.d_stage,
+                      (const double*)sl.d_prob64, (const double*)sl.d_demand,
+                      (const double*)sl.d_price, (const double*)S->dx.Pd,
+                      (const double*)S->dx.Gd, (const double*)S->dx.Gbar,
+                      (const double*)S->d64.F, (const double*)S->dx.alpha0,
+                      (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
+                      static_cast<T*>(sl.d_g), st);
+  TAPG_HIP(hipGetLastError());
+  // iterations in graph chunks until every tree has stopped
+  const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
+  const NetDev<T>& d = net_of<T>(S);
+  if (S->use_graph && (sl.graph == nullptr || sl.graph_iters != chunk)) {
+    if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+    sl.graph = nullptr;
+    hipGraph_t g = nullptr;
+    TAPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    TAPG_HIP(hipStreamEndCapture(st, &g));
+    hipError_t e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw Fail{TAPG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    sl.graph_iters = chunk;
+  }
+  int launched = 0;
+  while (true) {
+    if (S->use_graph) {
+      TAPG_HIP(hipGraphLaunch(sl.graph, st));
+    } else {
+      for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+      TAPG_HIP(hipGetLastError());
+    }
+    launched += chunk;
+    TAPG_HIP(hipMemcpyAsync(c.data(), sl.d_ctl, c.size() * sizeof(DevCtl), hipMemcpyDeviceToHost, st));
+    TAPG_HIP(hipStreamSynchronize(st));
+    bool all = true;
+    for (int k = 0; k < nt; ++k) all = all && c[k].done;
+    if (all || launched >= S->cfg.max_iter) break;
+  }
+  TAPG_HIP(hipEventRecord(S->ev1, st));
+  // cost and violations of every tree's final primal iterate
+  launch_cost<T>(f.K, h.nx, h.nu, h.nd, h.ns, LDX, LDU, (const int*)sl.d_anc,
+                 (const double*)sl.d_prob64, (const double*)sl.d_demand,
+                 (const double*)sl.d_price, (const T*)sl.d_u, (const T*)sl.d_x,
+                 (const double*)sl.d_pq64, (const double*)S->d64.A, (const double*)S->d64.B,
+                 (const double*)S->dx.Gd, (const double*)S->dx.E, (const double*)S->dx.Ed,
+                 (const double*)S->dx.Wu, (const double*)S->dx.alpha0, (const double*)S->dx.cE,
+                 (const double*)S->d64.xmin, (const double*)S->d64.xmax,
+                 (const double*)S->d64.xs, (const double*)S->d64.umin,
+                 (const double*)S->d64.umax, S->cfg.W_alpha, S->cfg.W_x, S->cfg.W_s, sl.d_part,
+                 S->dx.red, st);
+  launch_cost_reduce_forest(sl.d_part, B.d_tstart, f.N, nt, B.d_red, st);
+  TAPG_HIP(hipGetLastError());
+  std::vector<double> red((size_t)3 * nt);
+  TAPG_HIP(hipMemcpyAsync(red.data(), B.d_red, red.size() * 8, hipMemcpyDeviceToHost, st));
+  // every tree's rows, latest dual and history back into its own slot
+  for (int k = 0; k < nt; ++k) {
+    Slot& o = *own[k];
+    const int* idx = B.d_map + B.map_off[k];
+    const int Kk = trees[k]->K;
+    launch_copy_rows<T>(static_cast<const T*>(sl.d_u), LDU, static_cast<T*>(o.d_u), LDU, idx, Kk,
+                        LDU, false, st);
+    launch_copy_rows<T>(static_cast<const T*>(sl.d_x), LDX, static_cast<T*>(o.d_x), LDX, idx, Kk,
+                        LDX, false, st);
+    const T* ysrc = static_cast<const T*>((c[k].iter & 1) ? sl.d_Y1 : sl.d_Y0);
+    launch_copy_rows<T>(ysrc, LDY, static_cast<T*>(o.d_Y0), LDY, idx, Kk, LDY, false, st);
+    const int m = std::min(c[k].iter, o.hist_cap);
+    if (m > 0)
+      TAPG_HIP(hipMemcpyAsync(o.d_hist, sl.d_hist + (size_t)k * sl.hist_cap, (size_t)m * 8,
+                              hipMemcpyDeviceToDevice, st));
+  }
+  TAPG_HIP(hipGetLastError());
+  TAPG_HIP(hipStreamSynchronize(st));
+  float ms = 0.f;
+  TAPG_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+  for (int k = 0; k < nt; ++k) {
+    tapg_result r{};
+    r.iters = c[k].iter;
+    r.converged = c[k].converged;
+    r.primal_res = c[k].last_res;
+    r.cost = red[3 * k + 0];
+    r.viol_box = red[3 * k + 1];
+    r.viol_eq = red[3 * k + 2];
+    r.gamma = gam[k];
+    r.solve_ms = ms;
+    res[k] = r;
+    Slot& o = *own[k];
+    o.has_dual = true;
+    o.last_iter_parity = 0;
+    o.last = r;
+    o.has_result = true;
+    o.numeric = c[k].numeric != 0;
+  }
+}
+}  // namespace
+
+void dev_batch_solve(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
+                     const std::vector<Slot*>& own, const double* const* p,
+                     const double* const* q, const int* warm, const std::vector<double>& gamma,
+                     tapg_result* res) {
+  TAPG_HIP(hipSetDevice(S->device));
+  if (S->fp32)
+    batch_impl<float>(S, trees, own, p, q, warm, gamma, res);
+  else
+    batch_impl<double>(S, trees, own, p, q, warm, gamma, res);
 }
 
 double dev_power(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {

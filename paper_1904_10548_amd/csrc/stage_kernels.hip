@@ -507,14 +507,16 @@ __global__ __launch_bounds__(kThreads) void cost_kernel(
   __shared__ double red[kThreads];
   const int n = blockIdx.x;
   const int par = anc[n];
+  // the root of tree k (ancestor -1 - k) starts from that tree's (p, q)
+  const double* pqn = pq + (par < 0 ? (size_t)(-par - 1) * (LDX + LDU) : 0);
   for (int i = threadIdx.x; i < nu; i += kThreads) {
     const double un = (double)u[(size_t)n * LDU + i];
-    const double up = par >= 0 ? (double)u[(size_t)par * LDU + i] : pq[LDX + i];
+    const double up = par >= 0 ? (double)u[(size_t)par * LDU + i] : pqn[LDX + i];
     sU[i] = un;
     sDu[i] = un - up;
   }
   for (int i = threadIdx.x; i < nx; i += kThreads)
-    sXp[i] = par >= 0 ? (double)x[(size_t)par * LDX + i] : pq[i];
+    sXp[i] = par >= 0 ? (double)x[(size_t)par * LDX + i] : pqn[i];
   for (int k = threadIdx.x; k < nd; k += kThreads) sD[k] = demand[(size_t)n * nd + k];
   __syncthreads();
   double lin = 0.0, quad = 0.0, vbox = 0.0;
@@ -582,6 +584,47 @@ __global__ __launch_bounds__(kThreads) void cost_reduce_kernel(const double* par
   }
 }
 
+
+// Per-tree sums of the per-node cost terms of a forest: block k walks tree
+// k's node range of every stage (tstart[s * (ntrees + 1) + k ..]).
+__global__ __launch_bounds__(kThreads) void cost_reduce_forest_kernel(const double* part,
+                                                                      const int* tstart, int N,
+                                                                      int ntrees, double* out) {
+  __shared__ double red[kThreads];
+  const int k = blockIdx.x;
+  double c = 0.0, vb = 0.0, ms = 0.0, dy = 0.0;
+  for (int s = 0; s < N; ++s) {
+    const int b = tstart[(size_t)s * (ntrees + 1) + k], e = tstart[(size_t)s * (ntrees + 1) + k + 1];
+    for (int n = b + threadIdx.x; n < e; n += kThreads) {
+      c += part[(size_t)n * 4 + 0];
+      vb = fmax(vb, part[(size_t)n * 4 + 1]);
+      ms = fmax(ms, part[(size_t)n * 4 + 2]);
+      dy = fmax(dy, part[(size_t)n * 4 + 3]);
+    }
+  }
+  c = block_sum(c, red);
+  vb = block_max(vb, red);
+  ms = block_max(ms, red);
+  dy = block_max(dy, red);
+  if (threadIdx.x == 0) {
+    out[3 * k + 0] = c;
+    out[3 * k + 1] = vb;
+    out[3 * k + 2] = fmax(ms, dy);
+  }
+}
+
+// Rows between a tree's own buffers and a forest's: gather (dst row r = src
+// row idx[r]) or scatter (dst row idx[r] = src row r), `width` elements a row.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void copy_rows_kernel(const T* src, int ld_src, T* dst,
+                                                             int ld_dst, const int* idx, int rows,
+                                                             int width, int scatter) {
+  const int r = blockIdx.x;
+  if (r >= rows) return;
+  const size_t rs = scatter ? (size_t)r : (size_t)idx[r];
+  const size_t rd = scatter ? (size_t)idx[r] : (size_t)r;
+  for (int i = threadIdx.x; i < width; i += kThreads) dst[rd * ld_dst + i] = src[rs * ld_src + i];
+}
 
 // ---------------------------------------------------------------------------
 // Launch wrappers
@@ -655,6 +698,24 @@ void launch_cost(int K, int nx, int nu, int nd, int ns, int LDX, int LDU, const 
   hipLaunchKernelGGL(cost_reduce_kernel, dim3(1), dim3(kThreads), 0, st, (const double*)part, K,
                      out);
 }
+
+void launch_cost_reduce_forest(const double* part, const int* tstart, int N, int ntrees,
+                               double* out, hipStream_t st) {
+  hipLaunchKernelGGL(cost_reduce_forest_kernel, dim3(ntrees), dim3(kThreads), 0, st, part, tstart,
+                     N, ntrees, out);
+}
+
+template <typename T>
+void launch_copy_rows(const T* src, int ld_src, T* dst, int ld_dst, const int* idx, int rows,
+                      int width, bool scatter, hipStream_t st) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL((copy_rows_kernel<T>), dim3(rows), dim3(kThreads), 0, st, src, ld_src, dst,
+                     ld_dst, idx, rows, width, scatter ? 1 : 0);
+}
+template void launch_copy_rows<double>(const double*, int, double*, int, const int*, int, int,
+                                       bool, hipStream_t);
+template void launch_copy_rows<float>(const float*, int, float*, int, const int*, int, int, bool,
+                                      hipStream_t);
 
 #define TAPG_INST(T)                                                                         \
   template void launch_bwd_stage<T>(int, const SweepArgs<T>&, int, hipStream_t);            \

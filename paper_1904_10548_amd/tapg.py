@@ -35,7 +35,7 @@ TAPG_FP32 = 1
 EXPORTED = [
     "tapg_network_create", "tapg_network_destroy", "tapg_tree_create", "tapg_tree_set_data",
     "tapg_tree_num_nodes", "tapg_tree_destroy", "tapg_solver_create", "tapg_solver_destroy",
-    "tapg_factor_step", "tapg_get_factors", "tapg_factor_blocks", "tapg_solve", "tapg_get_primal", "tapg_get_dual",
+    "tapg_factor_step", "tapg_get_factors", "tapg_factor_blocks", "tapg_solve", "tapg_batch_solve", "tapg_get_primal", "tapg_get_dual",
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
     "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_last_error",
     "tapg_version",
@@ -112,6 +112,9 @@ def lib() -> ctypes.CDLL:
         "tapg_get_factors": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
         "tapg_factor_blocks": ([_P, _I, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_solve": ([_P, _P, _D, _D, ctypes.c_int, _D, ctypes.POINTER(TapgResult)], ctypes.c_int),
+        "tapg_batch_solve": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_D),
+                              ctypes.POINTER(_D), _I, ctypes.POINTER(_D),
+                              ctypes.POINTER(TapgResult)], ctypes.c_int),
         "tapg_get_primal": ([_P, _P, _D, _D], ctypes.c_int),
         "tapg_get_dual": ([_P, _P, _D], ctypes.c_int),
         "tapg_set_dual": ([_P, _P, _D], ctypes.c_int),
@@ -260,6 +263,28 @@ def tapg_solve(solver, tree, p, q, warm_start=False, nu=None):
     return st, u0, res
 
 
+def tapg_batch_solve(solver, trees, ps, qs, warm_start=None, nu=None):
+    """Solve ``trees`` together.  Returns ``(status, [u0], [result])``; status
+    is TAPG_OK or TAPG_ENOTCONV (TAPG_ENUMERIC raises)."""
+    n = len(trees)
+    keep = [_f64(v) for v in ps] + [_f64(v) for v in qs]
+    tarr = (_P * n)(*trees)
+    parr = (_D * n)(*[_ptr(v) for v in keep[:n]])
+    qarr = (_D * n)(*[_ptr(v) for v in keep[n:]])
+    width = (keep[n].size if n else 0) if nu is None else nu
+    u0 = [np.zeros(width) for _ in range(n)]
+    uarr = (_D * n)(*[_ptr(v) for v in u0])
+    warr = None
+    if warm_start is not None:
+        w = np.ascontiguousarray([int(bool(v)) for v in warm_start], dtype=np.int32)
+        keep.append(w)
+        warr = w.ctypes.data_as(_I)
+    res = (TapgResult * n)()
+    st = _check(lib().tapg_batch_solve(solver, n, tarr, parr, qarr, warr, uarr, res),
+                allow=(TAPG_OK, TAPG_ENOTCONV))
+    return st, u0, list(res)
+
+
 def tapg_get_primal(solver, tree, K, nx, nu):
     u = np.zeros((K, nu))
     x = np.zeros((K, nx))
@@ -345,6 +370,9 @@ class Solver:
 
     def solve(self, tree, p, q, warm_start=False):
         return tapg_solve(self.h, tree, p, q, warm_start, nu=self.nu)
+
+    def batch_solve(self, trees, ps, qs, warm_start=None):
+        return tapg_batch_solve(self.h, trees, ps, qs, warm_start, nu=self.nu)
 
     def primal(self, tree):
         return tapg_get_primal(self.h, tree, tapg_tree_num_nodes(tree), self.nx, self.nu)

@@ -120,15 +120,15 @@ def test_null_handles_are_errors():
 @pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
 def test_schedule_plan_covers_stages(name, precision):
     """The planner's levels cover stages 0..N-1 in order, every workgroup
-    holds at most 4 (FP64) / 8 (FP32) nodes per stage, and the groups of a
-    level cover its first stage."""
+    holds at most 4 nodes per stage, and the groups of a level cover its
+    first stage."""
     P = ds.config_problem(name)
     h = tapg.tapg_tree_create(*_tree_args(P))
     try:
         plan = tapg.tapg_plan_schedule(h, precision)
     finally:
         tapg.tapg_tree_destroy(h)
-    cap = 4 if precision == tapg.TAPG_FP64 else 8
+    cap = 4
     assert plan[0][0] == 0 and plan[-1][1] == P.tree.N - 1
     for a, b in zip(plan, plan[1:]):
         assert b[0] == a[1] + 1
@@ -146,11 +146,12 @@ def test_schedule_override_and_rejection():
         assert max(p[4] for p in plan) == 4
         with pytest.raises(tapg.TapgError):
             tapg.tapg_plan_schedule(h, tapg.TAPG_FP64, "1:1,4:1")  # must start at stage 0
-        # one workgroup from stage 2 (8 nodes) down to stage 5 holds 8 nodes of
-        # stage 5: within the FP32 limit, beyond the FP64 one
-        plan = tapg.tapg_plan_schedule(h, tapg.TAPG_FP32, "0:1,2:1,6:1")
-        assert max(p[4] for p in plan) == 8
-        with pytest.raises(tapg.TapgError):
-            tapg.tapg_plan_schedule(h, tapg.TAPG_FP64, "0:1,2:1,6:1")
+        # one workgroup from stage 2 (8 nodes) down to stage 5 would hold 8
+        # nodes of stage 5: beyond the limit of 4 in either precision
+        plan = tapg.tapg_plan_schedule(h, tapg.TAPG_FP32, "0:1,2:1,5:1")
+        assert max(p[4] for p in plan) == 4
+        for prec in (tapg.TAPG_FP64, tapg.TAPG_FP32):
+            with pytest.raises(tapg.TapgError):
+                tapg.tapg_plan_schedule(h, prec, "0:1,2:1,6:1")
     finally:
         tapg.tapg_tree_destroy(h)

@@ -1,0 +1,155 @@
+"""GPU: batched solves (several trees swept together as one forest) against
+the FP64 oracle per tree and against single-tree solves of the same trees.
+
+Bars as for single trees (FP64): iterates to 1e-9 of their scale, cost to 1e-6
+relative; against a single-tree GPU solve the same arithmetic runs per node,
+so iteration counts are equal and iterates agree to 1e-12.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import dwn_synth as ds
+import oracle as O
+from paper_1904_10548_amd import tapg
+
+from gpu_helpers import add_tree, make_solver
+from helpers import tiny_batch
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(2, 4), (3, 3), ("irregular", 3, 20), (1, 1), (2, 8)]
+
+
+@pytest.fixture(autouse=True)
+def _default_schedule():
+    for k in ("TAPG_LEVELS",):
+        os.environ.pop(k, None)
+    os.environ["TAPG_USE_GRAPH"] = "1"
+    os.environ["TAPG_SEGMENTS"] = "1"
+    yield
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _gamma_for(batch):
+    """One step size valid for every tree of the batch (0.9 / max L)."""
+    Ls = []
+    for P in batch:
+        Ls.append(O.lipschitz_power(P, O.StageFactors(P.net, P.weights.W_u, P.tree), 300))
+    return 0.9 / max(Ls)
+
+
+def test_batch_fixed_iterations_matches_oracle_per_tree():
+    batch = tiny_batch(SHAPES)
+    gamma = _gamma_for(batch)
+    iters = 300
+    say("batch fixed", [P.tree.K for P in batch], "iters", iters)
+    with make_solver(batch[0], gamma=gamma, tol=0.0, max_iter=iters, check_every=64) as S:
+        trees = [add_tree(S, P) for P in batch]
+        st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
+        out = [(S.primal(t), S.dual(t), tapg.tapg_residual_history(S.h, t, iters)) for t in trees]
+    assert st == tapg.TAPG_OK
+    for P, r, u0, ((u, x), y, hist) in zip(batch, res, u0s, out):
+        ref = O.apg(P, gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
+        assert r.iters == iters
+        su, sx, sy = (max(1.0, np.abs(v).max()) for v in (ref.u, ref.x, ref.y))
+        assert np.abs(u - ref.u).max() <= 1e-9 * su
+        assert np.abs(x - ref.x).max() <= 1e-9 * sx
+        assert np.abs(y - ref.y).max() <= 1e-9 * sy
+        assert np.abs(u0 - ref.u[0]).max() <= 1e-9 * su
+        J = O.primal_cost(P, ref.u, ref.x)
+        assert abs(r.cost - J) <= 1e-6 * max(1.0, abs(J))
+        vb, ve = O.violations(P, ref.u, ref.x)
+        assert abs(r.viol_box - vb) <= 1e-6 and r.viol_eq <= 1e-9
+        assert np.allclose(hist, ref.res_hist, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
+def test_batch_equals_single_tree_solves_to_tolerance(precision):
+    """Auto step size per tree and a tolerance: every tree stops at the same
+    iteration as its own tapg_solve, with the same iterate; trees stop at
+    different iterations inside the batch."""
+    batch = tiny_batch(SHAPES, seed=23)
+    kw = dict(gamma=0.0, tol=1e-6, max_iter=20000, check_every=50, precision=precision)
+    say("batch vs single", [P.tree.K for P in batch], "prec", precision)
+    with make_solver(batch[0], **kw) as S:
+        trees = [add_tree(S, P) for P in batch]
+        st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
+        got = [S.primal(t) for t in trees]
+    with make_solver(batch[0], **kw) as S:
+        single = []
+        for P in batch:
+            t = add_tree(S, P)
+            st1, u01, r1 = S.solve(t, P.p, P.q)
+            single.append((r1, S.primal(t), u01))
+    assert st == tapg.TAPG_OK
+    assert len({r.iters for r in res}) > 1  # the trees stop at different iterations
+    tol = 1e-12 if precision == tapg.TAPG_FP64 else 1e-5
+    for r, (u, x), u0, (r1, (u1, x1), u01) in zip(res, got, u0s, single):
+        assert r.converged and r1.converged
+        assert r.iters == r1.iters
+        assert abs(r.gamma - r1.gamma) <= 1e-15 * r1.gamma
+        assert np.abs(u - u1).max() <= tol * max(1.0, np.abs(u1).max())
+        assert np.abs(x - x1).max() <= tol * max(1.0, np.abs(x1).max())
+        assert np.abs(u0 - u01).max() <= tol * max(1.0, np.abs(u01).max())
+        assert abs(r.cost - r1.cost) <= 1e-9 * max(1.0, abs(r1.cost))
+
+
+def test_batch_warm_start_and_resolve():
+    """A second batch solve warm-starts the chosen trees from their last dual:
+    the same iterations as a warm single-tree solve; cold trees repeat their
+    first solve exactly."""
+    batch = tiny_batch(SHAPES[:3], seed=5)
+    kw = dict(gamma=0.0, tol=1e-6, max_iter=20000, check_every=50)
+    with make_solver(batch[0], **kw) as S:
+        trees = [add_tree(S, P) for P in batch]
+        ps, qs = [P.p for P in batch], [P.q for P in batch]
+        _, _, r0 = S.batch_solve(trees, ps, qs)
+        ps2 = [p + 0.1 for p in ps]
+        _, _, r1 = S.batch_solve(trees, ps2, qs, warm_start=[1, 0, 1])
+    with make_solver(batch[0], **kw) as S:
+        single = []
+        for P, p2 in zip(batch, ps2):
+            t = add_tree(S, P)
+            S.solve(t, P.p, P.q)
+            single.append(S.solve(t, p2, P.q, warm_start=True)[2])
+    assert r1[1].iters != 0
+    for k in (0, 2):
+        assert r1[k].iters == single[k].iters
+        assert abs(r1[k].cost - single[k].cost) <= 1e-9 * max(1.0, abs(single[k].cost))
+
+
+def test_batch_of_full_size_trees_fp32():
+    """Three Barcelona-sized trees of the 64-tree configuration, FP32 sweeps:
+    each tree's cost after a fixed number of iterations within 1e-4 of the FP64
+    oracle's."""
+    batch = [ds.config_problem("batch64", i) for i in range(3)]
+    iters = 30
+    gamma = 0.0
+    say("batch64 x3", [P.tree.K for P in batch])
+    with make_solver(batch[0], gamma=gamma, tol=0.0, max_iter=iters, check_every=iters,
+                     precision=tapg.TAPG_FP32) as S:
+        trees = [add_tree(S, P) for P in batch]
+        st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
+    for P, r in zip(batch, res):
+        ref = O.apg(P, r.gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
+        J = O.primal_cost(P, ref.u, ref.x)
+        assert r.iters == iters
+        assert abs(r.cost - J) <= 1e-4 * max(1.0, abs(J))
+
+
+def test_batch_argument_errors():
+    batch = tiny_batch(SHAPES[:2])
+    with make_solver(batch[0], gamma=1e-3, tol=0.0, max_iter=5) as S:
+        trees = [add_tree(S, P) for P in batch]
+        with pytest.raises(tapg.TapgError):
+            S.batch_solve([trees[0], trees[0]], [batch[0].p] * 2, [batch[0].q] * 2)
+        with pytest.raises(tapg.TapgError):
+            S.batch_solve([], [], [])

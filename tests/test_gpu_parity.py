@@ -127,16 +127,14 @@ def test_wide_ragged_tree_fp64_and_fp32():
 
 
 @pytest.mark.parametrize("levels,fp32", [(None, False), ("0:1,2:2,4:1", False),
-                                         ("0:1,1:1,3:2,5:4", True)])
+                                         ("0:1,1:1,3:2,5:2", True)])
 def test_dwn128_fixed_iterations(levels, fp32):
     """Full-size network and tree (K = 2429): 40 iterations, every element;
     planned schedule and forced multi-level / grouped schedules."""
     P = ds.config_problem("dwn128")
     sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
     gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 60))
-    if fp32:
-        # a group of 4 at stage 5 is 8 nodes wide from stage 6 on: FP32 only
-        # (an FP64 workgroup holds at most 4 nodes of a stage)
+    if fp32:  # FP32 sweeps on a five-level schedule with groups of two
         st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40,
                                                          precision=tapg.TAPG_FP32, levels=levels)
         J = O.primal_cost(P, ref.u, ref.x)
