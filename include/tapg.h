@@ -43,6 +43,7 @@ extern "C" {
 typedef struct tapg_network_s* tapg_network;
 typedef struct tapg_tree_s* tapg_tree;
 typedef struct tapg_solver_s* tapg_solver;
+typedef struct tapg_server_s* tapg_server;
 
 typedef enum {
   TAPG_OK = 0,
@@ -212,6 +213,39 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
  * end-of-iteration kernel. */
 tapg_status tapg_kernel_timing(tapg_solver solver, int enable);
 tapg_status tapg_kernel_times(tapg_solver solver, double* ms, long long* launches);
+
+/* Request server (the solve loop of a controller serving many requests,
+ * Sec. 5's SmpcController::controlAction per request): a worker thread owns the
+ * solver; each round it takes the pending requests, first come first served,
+ * whose estimated device memory fits hbm_budget_bytes (at most max_batch, one
+ * request per tree) and solves them with one batched solve (tapg_batch_solve);
+ * requests arriving meanwhile join the next round.  A request is warm started
+ * when the previous request of its session solved the same tree.  While a
+ * server exists, other calls on its solver return TAPG_ESTATE; destroy the
+ * server before the solver.  A submitted tree must not be modified or destroyed
+ * before its ticket completes. */
+tapg_status tapg_server_create(tapg_solver solver, size_t hbm_budget_bytes, int max_batch,
+                               tapg_server* out);
+/* Queue one request (p: nx, q: nu, copied); *ticket identifies it. */
+tapg_status tapg_server_submit(tapg_server srv, tapg_tree tree, const double* p, const double* q,
+                               int session, long long* ticket);
+/* Result of a request: waits up to wait_ms (0: do not wait, < 0: until done).
+ * TAPG_ESTATE while pending (nothing written); otherwise the request's status
+ * (TAPG_OK, TAPG_ENOTCONV, TAPG_ENUMERIC, or TAPG_ENOMEM if it alone exceeds
+ * the budget), with u0_out (nu), res and latency_ms (submit to completion;
+ * each may be NULL) written; the ticket is then released. */
+tapg_status tapg_server_poll(tapg_server srv, long long ticket, int wait_ms, double* u0_out,
+                             tapg_result* res, double* latency_ms);
+/* Counters: batches run, requests solved, worker busy time, queue length. */
+tapg_status tapg_server_stats(tapg_server srv, long long* batches, long long* solved,
+                              double* busy_ms, int* pending);
+/* Stops the worker (queued requests complete with TAPG_ESTATE) and frees it. */
+void tapg_server_destroy(tapg_server srv);
+
+/* Release the device memory a solver holds for a tree (its slot and every
+ * cached batch containing it).  The tree stays valid; a later solve allocates
+ * again. */
+tapg_status tapg_solver_forget(tapg_solver solver, tapg_tree tree);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* tapg_last_error(void);

@@ -364,6 +364,7 @@ void tapg_solver_destroy(tapg_solver solver) {
 tapg_status tapg_factor_step(tapg_solver solver, int N) {
   return guarded([&]() -> tapg_status {
     need(solver, "solver");
+    if (solver->server_active) fail(TAPG_ESTATE, "the solver is driven by a server");
     if (N < 1 || N > 100000) fail(TAPG_EDIM, "N must be in [1, 100000]");
     factor_step(solver, N);
     dev_upload_factors(solver);
@@ -398,8 +399,19 @@ tapg_status tapg_factor_blocks(tapg_solver solver, int* fid, int n, int* n_block
   });
 }
 
+static void check_pair_unserved(tapg_solver solver, tapg_tree tree) {
+  need(solver, "solver");
+  need(tree, "tree");
+  if (solver->N == 0) fail(TAPG_ESTATE, "factor step not run");
+  if (tree->h.N != solver->N)
+    fail(TAPG_EDIM, "tree horizon " + std::to_string(tree->h.N) + " != factored horizon " +
+                        std::to_string(solver->N));
+  if (tree->h.nd != solver->net.nd) fail(TAPG_EDIM, "tree nd does not match the network");
+}
+
 static void check_pair(tapg_solver solver, tapg_tree tree) {
   need(solver, "solver");
+  if (solver->server_active) fail(TAPG_ESTATE, "the solver is driven by a server");
   need(tree, "tree");
   if (solver->N == 0) fail(TAPG_ESTATE, "factor step not run");
   if (tree->h.N != solver->N)
@@ -438,43 +450,81 @@ tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, cons
   });
 }
 
+}  // extern "C"
+
+namespace tapg {
+// Batched solve shared by tapg_batch_solve and the server: validation, the
+// step size of every tree, the forest solve and the root inputs.  st_out[k]
+// is tree k's status (OK, ENOTCONV or ENUMERIC).
+void batch_core(tapg_solver_s* solver, int ntrees, const tapg_tree* trees, const double* const* p,
+                const double* const* q, const int* warm_start, double* const* u0_out,
+                tapg_result* res, tapg_status* st_out) {
+  need(solver, "solver");
+  need(trees, "trees");
+  need(p, "p");
+  need(q, "q");
+  if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
+  std::vector<const TreeHost*> th(ntrees);
+  std::vector<Slot*> own(ntrees);
+  std::vector<double> gamma(ntrees);
+  std::vector<uint64_t> ids;
+  for (int k = 0; k < ntrees; ++k) {
+    check_pair_unserved(solver, trees[k]);
+    need(p[k], "p[k]");
+    need(q[k], "q[k]");
+    if (!finite_all(p[k], solver->net.nx) || !finite_all(q[k], solver->net.nu))
+      fail(TAPG_ENUMERIC, "non-finite p or q of tree " + std::to_string(k));
+    th[k] = &trees[k]->h;
+    ids.push_back(th[k]->uid);
+  }
+  std::sort(ids.begin(), ids.end());
+  if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+    fail(TAPG_EINVAL, "a tree appears twice in the batch");
+  for (int k = 0; k < ntrees; ++k) {
+    own[k] = &dev_slot(solver, *th[k]);
+    gamma[k] = solver_gamma(solver, *th[k], *own[k]);
+  }
+  std::vector<tapg_result> r(ntrees);
+  dev_batch_solve(solver, th, own, p, q, warm_start, gamma, r.data());
+  for (int k = 0; k < ntrees; ++k) {
+    if (u0_out && u0_out[k]) dev_get_root_input(solver, *own[k], u0_out[k]);
+    if (res) res[k] = r[k];
+    tapg_status sk = TAPG_OK;
+    if (own[k]->numeric) sk = TAPG_ENUMERIC;
+    else if (!r[k].converged && solver->cfg.tol > 0) sk = TAPG_ENOTCONV;
+    if (st_out) st_out[k] = sk;
+  }
+}
+}  // namespace tapg
+
+extern "C" {
+
+tapg_status tapg_solver_forget(tapg_solver solver, tapg_tree tree) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    need(tree, "tree");
+    if (solver->server_active) fail(TAPG_ESTATE, "the solver is driven by a server");
+    const uint64_t uid = tree->h.uid;
+    std::vector<std::vector<uint64_t>> keys;
+    for (const auto& kv : solver->batches)
+      if (std::find(kv.first.begin(), kv.first.end(), uid) != kv.first.end()) keys.push_back(kv.first);
+    for (const auto& k : keys) dev_drop_batch(solver, k);
+    dev_drop_tree(solver, uid);
+    return TAPG_OK;
+  });
+}
+
 tapg_status tapg_batch_solve(tapg_solver solver, int ntrees, const tapg_tree* trees,
                              const double* const* p, const double* const* q, const int* warm_start,
                              double* const* u0_out, tapg_result* res) {
   return guarded([&]() -> tapg_status {
-    need(solver, "solver");
-    need(trees, "trees");
-    need(p, "p");
-    need(q, "q");
-    if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
-    std::vector<const TreeHost*> th(ntrees);
-    std::vector<Slot*> own(ntrees);
-    std::vector<double> gamma(ntrees);
-    std::vector<uint64_t> ids;
-    for (int k = 0; k < ntrees; ++k) {
-      check_pair(solver, trees[k]);
-      need(p[k], "p[k]");
-      need(q[k], "q[k]");
-      if (!finite_all(p[k], solver->net.nx) || !finite_all(q[k], solver->net.nu))
-        fail(TAPG_ENUMERIC, "non-finite p or q of tree " + std::to_string(k));
-      th[k] = &trees[k]->h;
-      ids.push_back(th[k]->uid);
-    }
-    std::sort(ids.begin(), ids.end());
-    if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
-      fail(TAPG_EINVAL, "a tree appears twice in the batch");
-    for (int k = 0; k < ntrees; ++k) {
-      own[k] = &dev_slot(solver, *th[k]);
-      gamma[k] = solver_gamma(solver, *th[k], *own[k]);
-    }
-    std::vector<tapg_result> r(ntrees);
-    dev_batch_solve(solver, th, own, p, q, warm_start, gamma, r.data());
+    if (solver && solver->server_active) fail(TAPG_ESTATE, "the solver is driven by a server");
+    std::vector<tapg_status> sk(std::max(ntrees, 1), TAPG_OK);
+    batch_core(solver, ntrees, trees, p, q, warm_start, u0_out, res, sk.data());
     tapg_status worst = TAPG_OK;
     for (int k = 0; k < ntrees; ++k) {
-      if (u0_out && u0_out[k]) dev_get_root_input(solver, *own[k], u0_out[k]);
-      if (res) res[k] = r[k];
-      if (own[k]->numeric) worst = TAPG_ENUMERIC;
-      else if (worst == TAPG_OK && !r[k].converged && solver->cfg.tol > 0) worst = TAPG_ENOTCONV;
+      if (sk[k] == TAPG_ENUMERIC) worst = TAPG_ENUMERIC;
+      else if (worst == TAPG_OK && sk[k] == TAPG_ENOTCONV) worst = TAPG_ENOTCONV;
     }
     if (worst == TAPG_ENUMERIC) set_error("a tree of the batch has a non-finite dual residual");
     return worst;
@@ -588,6 +638,7 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
 tapg_status tapg_kernel_timing(tapg_solver solver, int enable) {
   return guarded([&]() -> tapg_status {
     need(solver, "solver");
+    if (solver->server_active) fail(TAPG_ESTATE, "the solver is driven by a server");
     dev_set_kernel_timing(solver, enable != 0);
     return TAPG_OK;
   });

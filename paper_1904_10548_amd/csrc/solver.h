@@ -77,6 +77,7 @@ struct tapg_solver_s {
   // optional per-launch timing of the sweep kernels (HIP events around each
   // launch; graphs are bypassed while it is on)
   bool time_kernels = false;
+  bool server_active = false;  // a tapg_server drives this solver (other calls refused)
   std::vector<hipEvent_t> tev;      // pairs, reused per chunk
   double kt_ms[3] = {0, 0, 0};      // backward stages, forward stages, iteration end
   long long kt_n[3] = {0, 0, 0};
@@ -96,6 +97,11 @@ int nb_template(int w);
 std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us);
 std::vector<LevelPlan> levels_from_env(const TreeHost& t, const char* spec);
 std::vector<std::pair<int, int>> level_ranges(const TreeHost& t, const LevelPlan& L, int& wmax);
+
+// Batched solve shared by tapg_batch_solve and the server (api.cpp).
+void batch_core(tapg_solver_s* solver, int ntrees, const tapg_tree* trees, const double* const* p,
+                const double* const* q, const int* warm_start, double* const* u0_out,
+                tapg_result* res, tapg_status* st_out);
 
 // Device layer (solver.hip).
 void dev_init(tapg_solver_s* S);             // streams, events, network buffers
@@ -118,5 +124,9 @@ void dev_set_dual(tapg_solver_s* S, Slot& sl, const double* y);
 int dev_get_history(tapg_solver_s* S, Slot& sl, double* h, int n);
 void dev_set_kernel_timing(tapg_solver_s* S, bool on);
 void dev_free_slot(Slot& sl);
+// Free the forest (slot, graph and maps) cached for this exact batch, if any.
+void dev_drop_batch(tapg_solver_s* S, const std::vector<uint64_t>& key);
+// Free the device slot of one tree (its buffers, graph and results), if any.
+void dev_drop_tree(tapg_solver_s* S, uint64_t uid);
 
 }  // namespace tapg

@@ -974,6 +974,27 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
 }
 }  // namespace
 
+void dev_drop_batch(tapg_solver_s* S, const std::vector<uint64_t>& key) {
+  auto it = S->batches.find(key);
+  if (it == S->batches.end()) return;
+  TAPG_HIP(hipSetDevice(S->device));
+  TAPG_HIP(hipStreamSynchronize(S->stream));
+  dev_drop_tree(S, it->second.forest.uid);
+  dfree(it->second.d_map);
+  dfree(it->second.d_tstart);
+  dfree(it->second.d_red);
+  S->batches.erase(it);
+}
+
+void dev_drop_tree(tapg_solver_s* S, uint64_t uid) {
+  auto it = S->slots.find(uid);
+  if (it == S->slots.end()) return;
+  TAPG_HIP(hipSetDevice(S->device));
+  TAPG_HIP(hipStreamSynchronize(S->stream));
+  dev_free_slot(it->second);
+  S->slots.erase(it);
+}
+
 void dev_batch_solve(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
                      const std::vector<Slot*>& own, const double* const* p,
                      const double* const* q, const int* warm, const std::vector<double>& gamma,

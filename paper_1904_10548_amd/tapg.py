@@ -37,8 +37,9 @@ EXPORTED = [
     "tapg_tree_num_nodes", "tapg_tree_destroy", "tapg_solver_create", "tapg_solver_destroy",
     "tapg_factor_step", "tapg_get_factors", "tapg_factor_blocks", "tapg_solve", "tapg_batch_solve", "tapg_get_primal", "tapg_get_dual",
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
-    "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_last_error",
-    "tapg_version",
+    "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_solver_forget",
+    "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats",
+    "tapg_server_destroy", "tapg_last_error", "tapg_version",
 ]
 
 
@@ -111,6 +112,16 @@ def lib() -> ctypes.CDLL:
         "tapg_factor_step": ([_P, ctypes.c_int], ctypes.c_int),
         "tapg_get_factors": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
         "tapg_factor_blocks": ([_P, _I, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "tapg_solver_forget": ([_P, _P], ctypes.c_int),
+        "tapg_server_create": ([_P, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
+        "tapg_server_submit": ([_P, _P, _D, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)],
+                               ctypes.c_int),
+        "tapg_server_poll": ([_P, ctypes.c_longlong, ctypes.c_int, _D, ctypes.POINTER(TapgResult),
+                             _D], ctypes.c_int),
+        "tapg_server_stats": ([_P, ctypes.POINTER(ctypes.c_longlong),
+                              ctypes.POINTER(ctypes.c_longlong), _D, ctypes.POINTER(ctypes.c_int)],
+                             ctypes.c_int),
+        "tapg_server_destroy": ([_P], None),
         "tapg_solve": ([_P, _P, _D, _D, ctypes.c_int, _D, ctypes.POINTER(TapgResult)], ctypes.c_int),
         "tapg_batch_solve": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_D),
                               ctypes.POINTER(_D), _I, ctypes.POINTER(_D),
@@ -283,6 +294,50 @@ def tapg_batch_solve(solver, trees, ps, qs, warm_start=None, nu=None):
     st = _check(lib().tapg_batch_solve(solver, n, tarr, parr, qarr, warr, uarr, res),
                 allow=(TAPG_OK, TAPG_ENOTCONV))
     return st, u0, list(res)
+
+
+def tapg_solver_forget(solver, tree):
+    _check(lib().tapg_solver_forget(solver, tree))
+
+
+def tapg_server_create(solver, hbm_budget_bytes, max_batch=64):
+    out = _P()
+    _check(lib().tapg_server_create(solver, int(hbm_budget_bytes), int(max_batch),
+                                    ctypes.byref(out)))
+    return out
+
+
+def tapg_server_submit(srv, tree, p, q, session=0):
+    t = ctypes.c_longlong(0)
+    _check(lib().tapg_server_submit(srv, tree, _ptr(_f64(p)), _ptr(_f64(q)), int(session),
+                                    ctypes.byref(t)))
+    return t.value
+
+
+def tapg_server_poll(srv, ticket, nu, wait_ms=-1):
+    """``(status, u0, result, latency_ms)``; status TAPG_ESTATE while pending."""
+    u0 = np.zeros(nu)
+    res = TapgResult()
+    lat = np.zeros(1)
+    st = lib().tapg_server_poll(srv, int(ticket), int(wait_ms), _ptr(u0), ctypes.byref(res),
+                                _ptr(lat))
+    if st not in (TAPG_OK, TAPG_ENOTCONV, TAPG_ESTATE, TAPG_ENOMEM, TAPG_ENUMERIC):
+        _check(st)
+    return st, u0, res, float(lat[0])
+
+
+def tapg_server_stats(srv):
+    b, s = ctypes.c_longlong(0), ctypes.c_longlong(0)
+    busy = np.zeros(1)
+    pend = ctypes.c_int(0)
+    _check(lib().tapg_server_stats(srv, ctypes.byref(b), ctypes.byref(s), _ptr(busy),
+                                   ctypes.byref(pend)))
+    return {"batches": b.value, "solved": s.value, "busy_ms": float(busy[0]),
+            "pending": pend.value}
+
+
+def tapg_server_destroy(srv):
+    lib().tapg_server_destroy(srv)
 
 
 def tapg_get_primal(solver, tree, K, nx, nu):

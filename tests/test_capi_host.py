@@ -155,3 +155,16 @@ def test_schedule_override_and_rejection():
                 tapg.tapg_plan_schedule(h, prec, "0:1,2:1,6:1")
     finally:
         tapg.tapg_tree_destroy(h)
+
+
+def test_server_argument_errors_on_host():
+    """Server entry points validate their arguments before touching a device."""
+    import ctypes
+    L = tapg.lib()
+    out = ctypes.c_void_p()
+    assert L.tapg_server_create(None, 1 << 30, 8, ctypes.byref(out)) == tapg.TAPG_EINVAL
+    assert L.tapg_server_poll(None, 1, 0, None, None, None) == tapg.TAPG_EINVAL
+    assert L.tapg_server_stats(None, None, None, None, None) == tapg.TAPG_EINVAL
+    t = ctypes.c_longlong(0)
+    assert L.tapg_server_submit(None, None, None, None, 0, ctypes.byref(t)) == tapg.TAPG_EINVAL
+    L.tapg_server_destroy(None)  # no-op

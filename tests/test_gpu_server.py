@@ -1,0 +1,97 @@
+"""GPU: the request server (worker thread, batched rounds, session warm
+starts, HBM admission) against single-tree solves of the same requests."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1904_10548_amd import tapg
+
+from gpu_helpers import add_tree, make_solver
+from helpers import tiny_batch
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(2, 4), (3, 3), ("irregular", 3, 20), (1, 1), (2, 8)]
+
+
+@pytest.fixture(autouse=True)
+def _default_schedule():
+    os.environ.pop("TAPG_LEVELS", None)
+    os.environ["TAPG_USE_GRAPH"] = "1"
+    os.environ["TAPG_SEGMENTS"] = "1"
+    yield
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def test_server_matches_single_solves_with_session_warm_start():
+    """Every tree is requested twice by its own session; the second request
+    (new initial state) is warm started from the first, as a warm tapg_solve."""
+    batch = tiny_batch(SHAPES, seed=31)
+    kw = dict(gamma=0.0, tol=1e-6, max_iter=20000, check_every=50)
+    nu = batch[0].net.nu
+    p2 = [P.p + 0.2 for P in batch]
+    say("server", [P.tree.K for P in batch])
+    with make_solver(batch[0], **kw) as S:
+        trees = [add_tree(S, P) for P in batch]
+        srv = tapg.tapg_server_create(S.h, 1 << 34, 64)
+        try:
+            t1 = [tapg.tapg_server_submit(srv, t, P.p, P.q, session=k)
+                  for k, (t, P) in enumerate(zip(trees, batch))]
+            t2 = [tapg.tapg_server_submit(srv, t, p, P.q, session=k)
+                  for k, (t, P, p) in enumerate(zip(trees, batch, p2))]
+            with pytest.raises(tapg.TapgError):  # the server owns the solver
+                S.solve(trees[0], batch[0].p, batch[0].q)
+            first = [tapg.tapg_server_poll(srv, t, nu) for t in t1]
+            second = [tapg.tapg_server_poll(srv, t, nu) for t in t2]
+            stats = tapg.tapg_server_stats(srv)
+        finally:
+            tapg.tapg_server_destroy(srv)
+        S.solve(trees[0], batch[0].p, batch[0].q)  # usable again
+    assert stats["solved"] == 2 * len(batch) and stats["batches"] >= 2
+    with make_solver(batch[0], **kw) as S:
+        ref = []
+        for P, p in zip(batch, p2):
+            t = add_tree(S, P)
+            _, u0a, ra = S.solve(t, P.p, P.q)
+            _, u0b, rb = S.solve(t, p, P.q, warm_start=True)
+            ref.append(((u0a, ra), (u0b, rb)))
+    for (st1, u1, r1, l1), (st2, u2, r2, l2), ((u0a, ra), (u0b, rb)) in zip(first, second, ref):
+        assert st1 == tapg.TAPG_OK and st2 == tapg.TAPG_OK
+        assert l1 > 0 and l2 > 0
+        assert r1.iters == ra.iters and r2.iters == rb.iters
+        assert np.abs(u1 - u0a).max() <= 1e-12 * max(1.0, np.abs(u0a).max())
+        assert np.abs(u2 - u0b).max() <= 1e-12 * max(1.0, np.abs(u0b).max())
+        assert abs(r2.cost - rb.cost) <= 1e-9 * max(1.0, abs(rb.cost))
+
+
+def test_server_rejects_requests_over_the_budget():
+    batch = tiny_batch(SHAPES[:2], seed=3)
+    nu = batch[0].net.nu
+    with make_solver(batch[0], gamma=1e-3, tol=0.0, max_iter=10) as S:
+        trees = [add_tree(S, P) for P in batch]
+        srv = tapg.tapg_server_create(S.h, 1024, 8)  # 1 KiB: nothing fits
+        try:
+            tk = [tapg.tapg_server_submit(srv, t, P.p, P.q) for t, P in zip(trees, batch)]
+            out = [tapg.tapg_server_poll(srv, t, nu) for t in tk]
+        finally:
+            tapg.tapg_server_destroy(srv)
+    assert all(o[0] == tapg.TAPG_ENOMEM for o in out)
+
+
+def test_solver_forget_releases_and_resolves():
+    batch = tiny_batch(SHAPES[:2], seed=9)
+    with make_solver(batch[0], gamma=0.0, tol=1e-6, max_iter=20000) as S:
+        t = add_tree(S, batch[0])
+        _, u0a, ra = S.solve(t, batch[0].p, batch[0].q)
+        tapg.tapg_solver_forget(S.h, t)
+        with pytest.raises(tapg.TapgError):
+            S.primal(t)  # nothing held for the tree any more
+        _, u0b, rb = S.solve(t, batch[0].p, batch[0].q)
+    assert ra.iters == rb.iters and np.array_equal(u0a, u0b)
