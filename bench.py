@@ -82,6 +82,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests/s")
+    ap.add_argument("--requests", type=int, default=400, help="serve: timed requests")
+    ap.add_argument("--sessions", type=int, default=32, help="serve: sessions (one tree each)")
+    ap.add_argument("--max-batch", type=int, default=64, help="serve: trees in flight")
+    ap.add_argument("--hbm-gb", type=float, default=64.0, help="serve: admission budget")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -98,8 +103,12 @@ def main():
     except Exception:  # torch is optional plumbing here
         have_torch = False
 
+    # long solves print their own progress (iterations, trees running) to stderr
+    os.environ.setdefault("TAPG_PROGRESS", "30")
     if args.config == "batch64":
         return main_batch(args, ds, tapg)
+    if args.config == "serve":
+        return main_serve(args, ds, tapg)
     P = ds.config_problem(args.config)
     net, w = P.net, P.weights
     prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
@@ -287,6 +296,114 @@ def main_batch(args, ds, tapg):
         "lipschitz_s": round(lipschitz_s, 4),
         "roofline": None,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    S.close()
+
+
+def main_serve(args, ds, tapg):
+    """Serving loop: Poisson arrivals of receding-horizon re-solves over
+    `sessions` trees of 32..512 scenarios (K 669..8,701); each request starts
+    from its session's previous root input (q) and a drifted state (p), is warm
+    started when its session's previous request solved the same tree, and is
+    admitted into the running set by HBM budget (continuous batching).
+    Value: requests completed per second over the timed requests; latency is
+    submit to completion."""
+    import threading
+    n_sess = args.sessions
+    sess = [ds.config_problem("serve", i) for i in range(n_sess)]
+    P0 = sess[0]
+    net, w = P0.net, P0.weights
+    prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
+    S = tapg.Solver(dict(A=net.A, B=net.B, Gd=net.Gd, E=net.E, Ed=net.Ed, xmin=net.xmin,
+                         xmax=net.xmax, xs=net.xs, umin=net.umin, umax=net.umax),
+                    dict(W_alpha=w.W_alpha, W_s=w.W_s, W_x=w.W_x, alpha0=w.alpha0,
+                         c_energy=w.c_energy, W_u=w.W_u),
+                    P0.tree.N, gamma=0.0, tol=args.tol, max_iter=args.max_iter,
+                    check_every=args.check_every, precision=prec)
+    trees = [S.add_tree(P.tree.nodes_per_stage, P.tree.anc, P.tree.prob, P.data.demand,
+                        P.data.price) for P in sess]
+    t0 = time.perf_counter()
+    for t in trees:
+        tapg.tapg_estimate_lipschitz(S.h, t, 100)
+    print(f"[bench] serve: {n_sess} sessions, K {min(P.tree.K for P in sess)}.."
+          f"{max(P.tree.K for P in sess)}, power {time.perf_counter() - t0:.2f}s",
+          file=sys.stderr, flush=True)
+    srv = tapg.tapg_server_create(S.h, int(args.hbm_gb * 2**30), args.max_batch)
+    rng = np.random.default_rng(np.random.SeedSequence([1004, 17]))
+    n_warm = n_sess  # one request per session before the timed ones
+    total = n_warm + args.requests
+    gaps = rng.exponential(1.0 / args.rate, size=total)
+    drift = rng.normal(0.0, 0.05, size=(total, net.nx))
+    last_q = [P.q.copy() for P in sess]
+    last_p = [P.p.copy() for P in sess]
+    lock = threading.Lock()
+    tickets, results = [None] * total, [None] * total
+    submit_t = [0.0] * total
+    done_t = [0.0] * total
+
+    def collector():
+        for i in range(total):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            st, u0, r, lat = tapg.tapg_server_poll(srv, tickets[i], net.nu, -1)
+            done_t[i] = time.perf_counter()
+            k = i % n_sess
+            with lock:
+                if st in (tapg.TAPG_OK, tapg.TAPG_ENOTCONV):
+                    last_q[k] = np.clip(u0, net.umin, net.umax)
+            results[i] = (st, r, lat)
+
+    th = threading.Thread(target=collector)
+    th.start()
+    t_next = time.perf_counter()
+    for i in range(total):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
+        k = i % n_sess
+        with lock:
+            p = np.clip(last_p[k] + drift[i], net.xmin + 0.5, net.xmax - 0.5)
+            last_p[k] = p
+            q = last_q[k].copy()
+        submit_t[i] = time.perf_counter()
+        tickets[i] = tapg.tapg_server_submit(srv, trees[k], p, q, session=k)
+    th.join()
+    stats = tapg.tapg_server_stats(srv)
+    tapg.tapg_server_destroy(srv)
+    timed = range(n_warm, total)
+    lat_ms = np.array([results[i][2] for i in timed])
+    ok = sum(results[i][0] in (tapg.TAPG_OK, tapg.TAPG_ENOTCONV) for i in timed)
+    conv = sum(bool(results[i][1].converged) for i in timed)
+    window = max(done_t[i] for i in timed) - min(submit_t[i] for i in timed)
+    iters = np.array([results[i][1].iters for i in timed])
+    out = {
+        "metric": METRIC + " (serving)",
+        "value": round(args.requests / window, 4),
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": n_warm,
+        "ms_per_step": round(1e3 * window / args.requests, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == tapg.TAPG_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serve: Poisson {args.rate:g} req/s offered, {n_sess} sessions, "
+                               f"S in 32..512, tol={args.tol:g}, warm-started re-solves, "
+                               f"continuous batching (max {args.max_batch} in flight, "
+                               f"{args.hbm_gb:g} GB admission budget)",
+                   "offered_rate": args.rate, "requests": args.requests, "sessions": n_sess,
+                   "tol": args.tol, "precision": args.precision},
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "completed_ok": int(ok), "converged": int(conv),
+        "iters_p50": int(np.percentile(iters, 50)), "iters_max": int(iters.max()),
+        "forests_formed": stats["batches"],
+        "worker_busy_ms": round(stats["busy_ms"], 1),
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
     S.close()

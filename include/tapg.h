@@ -242,6 +242,19 @@ tapg_status tapg_server_stats(tapg_server srv, long long* batches, long long* so
 /* Stops the worker (queued requests complete with TAPG_ESTATE) and frees it. */
 void tapg_server_destroy(tapg_server srv);
 
+/* Autotuner for the sweep schedule (the levels of stages and the workgroup
+ * groups that tapg_plan_schedule describes): times `iters` iterations (one
+ * captured iteration graph) of every distinct plan the planner produces under a
+ * spread of its cost constants, on the tree (ntrees = 1) or on the batch's forest
+ * (ntrees > 1, as tapg_batch_solve would form it), and keeps the fastest for it
+ * and for every later tree or batch of the same shape on this solver (TAPG_LEVELS,
+ * if set, still wins).  *ms_per_iter (may be NULL): the winner's time per
+ * iteration; *candidates (may be NULL): plans timed.  The timing runs overwrite
+ * the tree's iterates (solve again before querying).  TAPG_EINVAL when the
+ * segment kernels do not apply. */
+tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees, int iters,
+                          double* ms_per_iter, int* candidates);
+
 /* Release the device memory a solver holds for a tree (its slot and every
  * cached batch containing it).  The tree stays valid; a later solve allocates
  * again. */

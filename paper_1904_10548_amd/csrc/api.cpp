@@ -420,7 +420,9 @@ static void check_pair(tapg_solver solver, tapg_tree tree) {
   if (tree->h.nd != solver->net.nd) fail(TAPG_EDIM, "tree nd does not match the network");
 }
 
-static double solver_gamma(tapg_solver solver, const TreeHost& t, Slot& sl) {
+}  // extern "C"
+
+double tapg::solver_gamma(tapg_solver_s* solver, const TreeHost& t, Slot& sl) {
   if (solver->cfg.gamma > 0) return solver->cfg.gamma;
   if (!sl.L_valid) {
     const int it = solver->cfg.power_iters > 0 ? solver->cfg.power_iters : 100;
@@ -430,6 +432,8 @@ static double solver_gamma(tapg_solver solver, const TreeHost& t, Slot& sl) {
   }
   return 1.0 / (1.02 * sl.L);
 }
+
+extern "C" {
 
 tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, const double* q,
                        int warm_start, double* u0_out, tapg_result* res) {
@@ -498,6 +502,29 @@ void batch_core(tapg_solver_s* solver, int ntrees, const tapg_tree* trees, const
 }  // namespace tapg
 
 extern "C" {
+
+tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees, int iters,
+                          double* ms_per_iter, int* candidates) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    need(trees, "trees");
+    if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
+    if (iters < 1 || iters > 100000) fail(TAPG_EINVAL, "iters must be in [1, 100000]");
+    std::vector<const TreeHost*> th(ntrees);
+    std::vector<uint64_t> ids;
+    for (int k = 0; k < ntrees; ++k) {
+      check_pair(solver, trees[k]);
+      th[k] = &trees[k]->h;
+      ids.push_back(th[k]->uid);
+    }
+    std::sort(ids.begin(), ids.end());
+    if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+      fail(TAPG_EINVAL, "a tree appears twice in the batch");
+    const double ms = dev_autotune(solver, th, iters, candidates);
+    if (ms_per_iter) *ms_per_iter = ms;
+    return TAPG_OK;
+  });
+}
 
 tapg_status tapg_solver_forget(tapg_solver solver, tapg_tree tree) {
   return guarded([&]() -> tapg_status {

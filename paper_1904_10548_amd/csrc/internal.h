@@ -108,6 +108,16 @@ struct DevCtl {
   unsigned pad1, pad2;
 };
 
+// Segment schedule (schedule.cpp).  A workgroup holds at most kSegNbMax nodes
+// of one stage (kernel templates NB = 1, 2, 4; wider groups would spill
+// registers).  A level covers stages [s_begin, s_end]; its workgroups own
+// groups of `group` consecutive nodes of stage s_begin and their descendants.
+constexpr int kSegNbMax = 4;
+struct LevelPlan {
+  int s_begin, s_end, group, nbm, n_wg;
+  double cost;
+};
+
 // Per-(solver, tree) device buffers.
 struct Slot {
   uint64_t tree_uid = 0, data_version = ~0ull;
@@ -152,6 +162,7 @@ struct Slot {
     int* d_wgtree;  // tree of each workgroup (forests only)
   };
   std::vector<Level> levels;
+  std::vector<LevelPlan> plans;  // the plan the levels were built from
   bool segmented = false;
   int part_total = 0;
   int ntrees = 1;                // trees of the forest held by this slot

@@ -44,9 +44,9 @@ static int widest_tree_stage(const TreeHost& t, int s) {
   return w;
 }
 
-std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us) {
+std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us,
+                                   double c_launch, double c_stage) {
   const int N = t.N;
-  const double c_launch = 3.0, c_stage = 0.25;
   const int conc = 512;  // workgroups resident at once (256 CUs x 2)
   std::vector<double> best(N + 1, 0.0);
   std::vector<LevelPlan> choice(N);
@@ -87,6 +87,26 @@ std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us)
     s = choice[s].s_end + 1;
   }
   return out;
+}
+
+std::vector<std::vector<LevelPlan>> candidate_plans(const TreeHost& t, int nbmax, double node_us) {
+  std::vector<std::vector<LevelPlan>> out;
+  auto same = [](const std::vector<LevelPlan>& a, const std::vector<LevelPlan>& b) {
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i)
+      if (a[i].s_begin != b[i].s_begin || a[i].s_end != b[i].s_end || a[i].group != b[i].group)
+        return false;
+    return true;
+  };
+  for (double cl : {3.0, 0.5, 1.5, 8.0, 20.0})
+    for (double cs : {0.25, 0.08, 0.6, 1.5})
+      for (double nf : {1.0, 0.4, 2.5}) {
+        std::vector<LevelPlan> p = plan_levels(t, nbmax, node_us * nf, cl, cs);
+        bool seen = false;
+        for (const auto& q : out) seen = seen || same(p, q);
+        if (!seen) out.push_back(std::move(p));
+      }
+  return out;  // the default plan (3.0, 0.25, 1.0) first
 }
 
 // Optional override: TAPG_LEVELS="s0:g0,s1:g1,..." (first stage and group size

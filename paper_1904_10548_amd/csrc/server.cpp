@@ -1,13 +1,14 @@
-// Request server over one solver: a worker thread repeatedly takes the
-// pending requests that fit an HBM budget (one request per tree, first come
-// first served), solves them as one batch (a forest, one set of launches per
-// iteration for all of them) and completes their tickets.  Requests that
-// arrive while a batch runs join the next batch.  A session's request is warm
-// started when the session's previous request solved the same tree.
+// Request server over one solver: a worker thread keeps the requests in
+// flight (one per tree, admitted first come first served while their
+// estimated device memory fits an HBM budget) iterating together as one
+// forest, and lets requests join and leave between chunks of iterations
+// (continuous batching).  A session's request is warm started when the
+// session's previous request solved the same tree.
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <thread>
@@ -73,25 +74,84 @@ void complete(tapg_server_s* srv, tapg_server_s::Req& r, tapg_status st, const d
   srv->done[r.ticket] = std::move(d);
 }
 
+// Continuous batching: the trees in flight are iterated as one forest, one
+// chunk of iterations at a time.  Between chunks, trees that stopped leave
+// (their tickets complete) and pending requests that fit join; whenever the
+// set changes, every running tree's exact iterate state (both dual buffers,
+// control block, history) goes back to its own slot and the forest is re-formed
+// from the new set, so a request's result does not depend on the mix.
+// After a failure: free every cached forest of the solver (best effort).
+void drop_forests(tapg_solver S) {
+  std::vector<std::vector<uint64_t>> keys;
+  for (const auto& kv : S->batches) keys.push_back(kv.first);
+  for (const auto& k : keys) {
+    try {
+      dev_drop_batch(S, k);
+    } catch (...) {
+    }
+  }
+}
+
+struct Active {
+  tapg_server_s::Req req;
+  LiveTree lt;
+  size_t bytes = 0;
+};
+
 void worker_loop(tapg_server_s* srv) {
   tapg_solver S = srv->S;
-  const int nu = S->net.nu;
+  std::vector<std::unique_ptr<Active>> active;
+  bool in_forest = false;
+  auto live_set = [&] {
+    std::vector<LiveTree*> js;
+    for (auto& a : active) js.push_back(&a->lt);
+    return js;
+  };
+  auto fail_all = [&](tapg_status code, const std::string& msg) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (auto& a : active) complete(srv, a->req, code, nullptr, nullptr, msg);
+    active.clear();
+    in_forest = false;
+    srv->cv_done.notify_all();
+  };
+  auto finish = [&] {  // complete the trees that stopped and drop them
+    std::lock_guard<std::mutex> lk(srv->mu);
+    std::vector<std::unique_ptr<Active>> keep;
+    for (auto& a : active) {
+      if (!a->lt.finished) {
+        keep.push_back(std::move(a));
+        continue;
+      }
+      const tapg_status st = a->lt.own->numeric ? TAPG_ENUMERIC
+                             : (!a->lt.res.converged && S->cfg.tol > 0) ? TAPG_ENOTCONV
+                                                                        : TAPG_OK;
+      std::vector<double> u0(S->net.nu, 0.0);
+      try {
+        dev_get_root_input(S, *a->lt.own, u0.data());
+      } catch (...) {
+      }
+      complete(srv, a->req, st, u0.data(), &a->lt.res, "");
+      srv->session_tree[a->req.session] = a->lt.t->uid;
+      srv->n_solved++;
+    }
+    active.swap(keep);
+    srv->cv_done.notify_all();
+  };
   while (true) {
-    std::vector<tapg_server_s::Req> batch;
+    std::vector<tapg_server_s::Req> admitted;
     std::vector<int> warm;
     {
       std::unique_lock<std::mutex> lk(srv->mu);
-      srv->cv_work.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
-      if (srv->stop) {
-        for (auto& r : srv->pending) complete(srv, r, TAPG_ESTATE, nullptr, nullptr, "server stopped");
-        srv->pending.clear();
-        srv->cv_done.notify_all();
-        return;
-      }
+      if (active.empty()) srv->cv_work.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
+      if (srv->stop) break;
       size_t used = 0;
       std::set<uint64_t> trees_in;
+      for (auto& a : active) {
+        used += a->bytes;
+        trees_in.insert(a->lt.t->uid);
+      }
       for (auto it = srv->pending.begin();
-           it != srv->pending.end() && (int)batch.size() < srv->max_batch;) {
+           it != srv->pending.end() && (int)(active.size() + admitted.size()) < srv->max_batch;) {
         const TreeHost& t = it->tree->h;
         const size_t b = request_bytes(S, t);
         if (b > srv->budget) {
@@ -107,62 +167,70 @@ void worker_loop(tapg_server_s* srv) {
         trees_in.insert(t.uid);
         auto s = srv->session_tree.find(it->session);
         warm.push_back(s != srv->session_tree.end() && s->second == t.uid ? 1 : 0);
-        batch.push_back(std::move(*it));
+        admitted.push_back(std::move(*it));
         it = srv->pending.erase(it);
       }
       srv->cv_done.notify_all();  // tickets completed with ENOMEM
-      if (batch.empty()) continue;
-    }
-    // solve outside the lock
-    const int n = (int)batch.size();
-    std::vector<tapg_tree> trees(n);
-    std::vector<const double*> ps(n), qs(n);
-    std::vector<std::vector<double>> u0(n, std::vector<double>(nu, 0.0));
-    std::vector<double*> u0p(n);
-    std::vector<tapg_result> res(n);
-    std::vector<tapg_status> st(n, TAPG_OK);
-    std::vector<uint64_t> key(n);
-    for (int k = 0; k < n; ++k) {
-      trees[k] = batch[k].tree;
-      ps[k] = batch[k].p.data();
-      qs[k] = batch[k].q.data();
-      u0p[k] = u0[k].data();
-      key[k] = batch[k].tree->h.uid;
-    }
-    std::string err;
-    tapg_status fail_code = TAPG_OK;
-    const auto t0 = Clock::now();
-    try {
-      batch_core(S, n, trees.data(), ps.data(), qs.data(), warm.data(), u0p.data(), res.data(),
-                 st.data());
-    } catch (const Fail& f) {
-      fail_code = f.code;
-      err = f.msg;
-    } catch (const std::exception& e) {
-      fail_code = TAPG_EDEVICE;
-      err = e.what();
     }
     try {
-      dev_drop_batch(S, key);  // compositions rarely repeat: keep no forest around
-    } catch (...) {
-    }
-    const double ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
-    {
-      std::lock_guard<std::mutex> lk(srv->mu);
-      for (int k = 0; k < n; ++k) {
-        if (fail_code != TAPG_OK) {
-          complete(srv, batch[k], fail_code, nullptr, nullptr, err);
-        } else {
-          complete(srv, batch[k], st[k], u0[k].data(), &res[k], "");
-          srv->session_tree[batch[k].session] = batch[k].tree->h.uid;
+      if (!admitted.empty()) {
+        if (in_forest) {  // running trees keep their state in their own slots
+          std::vector<LiveTree*> js = live_set();
+          dev_live_leave(S, js);
+          in_forest = false;
+          finish();
+        }
+        for (size_t k = 0; k < admitted.size(); ++k) {
+          auto a = std::make_unique<Active>();
+          a->req = std::move(admitted[k]);
+          a->bytes = request_bytes(S, a->req.tree->h);
+          a->lt.t = &a->req.tree->h;
+          a->lt.own = &dev_slot(S, *a->lt.t);
+          a->lt.p = a->req.p;
+          a->lt.q = a->req.q;
+          a->lt.gamma = solver_gamma(S, *a->lt.t, *a->lt.own);
+          a->lt.warm = warm[k] != 0;
+          dev_live_init(S, a->lt);
+          active.push_back(std::move(a));
         }
       }
-      srv->n_batches++;
-      srv->n_solved += n;
-      srv->busy_ms += ms;
+      if (active.empty()) continue;
+      if (!in_forest) {
+        dev_live_enter(S, live_set());
+        in_forest = true;
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->n_batches++;
+      }
+      const auto t0 = Clock::now();
+      std::vector<LiveTree*> js = live_set();
+      const bool stopped = dev_live_chunk(S, js);
+      {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->busy_ms += std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+      }
+      if (stopped) {
+        dev_live_leave(S, js);
+        in_forest = false;
+        finish();
+      }
+    } catch (const Fail& f) {
+      fail_all(f.code, f.msg);
+      drop_forests(S);
+    } catch (const std::exception& e) {
+      fail_all(TAPG_EDEVICE, e.what());
+      drop_forests(S);
     }
-    srv->cv_done.notify_all();
   }
+  // stopping: drop the forest, cancel what is left
+  try {
+    if (in_forest) dev_live_leave(S, live_set());
+  } catch (...) {
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  for (auto& a : active) complete(srv, a->req, TAPG_ESTATE, nullptr, nullptr, "server stopped");
+  for (auto& r : srv->pending) complete(srv, r, TAPG_ESTATE, nullptr, nullptr, "server stopped");
+  srv->pending.clear();
+  srv->cv_done.notify_all();
 }
 
 }  // namespace

@@ -66,6 +66,7 @@ struct tapg_solver_s {
   tapg::DevExtra dx;
   std::map<uint64_t, tapg::Slot> slots;
   std::map<std::vector<uint64_t>, tapg::Batch> batches;
+  std::map<std::string, std::vector<tapg::LevelPlan>> tuned;  // autotuned schedule per tree shape
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool use_graph = true;
   // structure of the network and weights (detected at creation)
@@ -85,18 +86,42 @@ struct tapg_solver_s {
 
 namespace tapg {
 
-// Segment schedule (schedule.cpp).  A workgroup holds at most kSegNbMax nodes
-// of one stage (kernel templates NB = 1, 2, 4; wider groups would spill
-// registers).
-constexpr int kSegNbMax = 4;
-struct LevelPlan {
-  int s_begin, s_end, group, nbm, n_wg;
-  double cost;
-};
+
 int nb_template(int w);
-std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us);
+std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us,
+                                   double c_launch = 3.0, double c_stage = 0.25);
+// Distinct plans of the planner under a spread of its cost constants: the
+// candidates the autotuner times.
+std::vector<std::vector<LevelPlan>> candidate_plans(const TreeHost& t, int nbmax, double node_us);
 std::vector<LevelPlan> levels_from_env(const TreeHost& t, const char* spec);
 std::vector<std::pair<int, int>> level_ranges(const TreeHost& t, const LevelPlan& L, int& wmax);
+
+// A tree in flight in the serving loop: its iterate state lives in its own
+// slot between forests (both dual buffers, control block, history).
+struct LiveTree {
+  const TreeHost* t = nullptr;
+  Slot* own = nullptr;
+  std::vector<double> p, q;
+  double gamma = 0.0;
+  bool warm = false;
+  DevCtl ctl{};
+  int it0 = 0;            // iterations done when it entered the current forest
+  bool finished = false;
+  tapg_result res{};
+};
+// Start a tree: dual (warm: its latest, else zero) and control block.
+void dev_live_init(tapg_solver_s* S, LiveTree& j);
+// Sweep the given trees as one forest from their current state.
+void dev_live_enter(tapg_solver_s* S, const std::vector<LiveTree*>& js);
+// One chunk of iterations; returns true if a tree stopped.
+bool dev_live_chunk(tapg_solver_s* S, const std::vector<LiveTree*>& js);
+// State back into every tree's own slot (results for the stopped ones, which
+// are marked finished); the forest is freed.
+void dev_live_leave(tapg_solver_s* S, const std::vector<LiveTree*>& js);
+
+// Step size of a tree: cfg.gamma if positive, else 1 / (1.02 L) with L from
+// the device power iteration, cached with the tree (api.cpp).
+double solver_gamma(tapg_solver_s* solver, const TreeHost& t, Slot& sl);
 
 // Batched solve shared by tapg_batch_solve and the server (api.cpp).
 void batch_core(tapg_solver_s* solver, int ntrees, const tapg_tree* trees, const double* const* p,
@@ -124,6 +149,11 @@ void dev_set_dual(tapg_solver_s* S, Slot& sl, const double* y);
 int dev_get_history(tapg_solver_s* S, Slot& sl, double* h, int n);
 void dev_set_kernel_timing(tapg_solver_s* S, bool on);
 void dev_free_slot(Slot& sl);
+// Autotuner: time every candidate schedule of the tree (one tree) or of the
+// batch's forest (several trees) and keep the fastest, for this slot and for
+// later slots of the same shape.  Returns ms per iteration of the winner.
+double dev_autotune(tapg_solver_s* S, const std::vector<const TreeHost*>& trees, int iters,
+                    int* ncand);
 // Free the forest (slot, graph and maps) cached for this exact batch, if any.
 void dev_drop_batch(tapg_solver_s* S, const std::vector<uint64_t>& key);
 // Free the device slot of one tree (its buffers, graph and results), if any.

@@ -3,6 +3,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <random>
 
 #include "kernels.h"
@@ -14,6 +17,29 @@ namespace tapg {
 // Host side
 // ---------------------------------------------------------------------------
 namespace {
+
+// Optional progress line on stderr every TAPG_PROGRESS seconds of a long solve
+// (iterations launched, trees still running).
+struct ProgressLine {
+  const char* what;
+  double every = 0.0;
+  std::chrono::steady_clock::time_point t0, last;
+  explicit ProgressLine(const char* w) : what(w) {
+    const char* e = std::getenv("TAPG_PROGRESS");
+    every = e ? std::atof(e) : 0.0;
+    t0 = last = std::chrono::steady_clock::now();
+  }
+  void tick(int iters, int running, int trees) {
+    if (!(every > 0.0)) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration<double>(now - last).count() < every) return;
+    last = now;
+    std::fprintf(stderr, "[tapg] %s: %d iterations, %d of %d trees running, %.1f s\n", what, iters,
+                 running, trees, std::chrono::duration<double>(now - t0).count());
+    std::fflush(stderr);
+  }
+};
+
 
 template <typename T>
 T* dmalloc(size_t n) {
@@ -394,6 +420,7 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   }
   DevCtl hc{};
   int launched = 0;
+  ProgressLine progress("solve");
   const bool timed = S->time_kernels;
   if (timed) {
     const size_t need = (size_t)2 * chunk * launches_per_iter(sl);
@@ -438,6 +465,7 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
     launched += chunk;
     TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
     TAPG_HIP(hipStreamSynchronize(st));
+    progress.tick(launched, hc.done ? 0 : 1, 1);
     if (hc.done || launched >= S->cfg.max_iter) break;
   }
   TAPG_HIP(hipEventRecord(S->ev1, st));
@@ -655,6 +683,93 @@ void dev_upload_factors(tapg_solver_s* S) {
   TAPG_HIP(hipStreamSynchronize(st));
 }
 
+// Cost-model time of one node-column of a stage (us), for the planner.
+double seg_node_us(const tapg_solver_s* S) {
+  return (double)S->net.nu * S->net.nu / 64.0 / 2400.0 * (S->fp32 ? 0.5 : 1.0);
+}
+
+// Shape of a tree or forest: the per-tree stage widths (the schedule depends
+// on nothing else).
+std::string shape_key(const TreeHost& t) {
+  std::string k = std::to_string(t.ntrees) + "|" + std::to_string(t.N);
+  for (int s = 0; s < t.N; ++s)
+    for (int j = 0; j < t.ntrees; ++j) k += "," + std::to_string(t.seg_end(s, j) - t.seg_begin(s, j));
+  return k;
+}
+
+// Schedule of a new slot: TAPG_LEVELS, else a plan the autotuner chose for
+// this shape, else the planner's.
+std::vector<LevelPlan> choose_plans(tapg_solver_s* S, const TreeHost& t) {
+  const char* spec = std::getenv("TAPG_LEVELS");
+  if (spec && spec[0]) return levels_from_env(t, spec);
+  auto it = S->tuned.find(shape_key(t));
+  if (it != S->tuned.end()) return it->second;
+  return plan_levels(t, kSegNbMax, seg_node_us(S));
+}
+
+// (Re)build the level launches of a slot from a plan.
+void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vector<LevelPlan>& plans) {
+  hipStream_t st = S->stream;
+  const int nbmax = kSegNbMax;
+  std::vector<Slot::Level> levels;
+  int ptot = 0;
+  try {
+    for (const LevelPlan& P : plans) {
+      int wmax = 0;
+      std::vector<std::pair<int, int>> rp = level_ranges(t, P, wmax);
+      std::vector<int2> rg(rp.size());
+      for (size_t k = 0; k < rp.size(); ++k) rg[k] = make_int2(rp[k].first, rp[k].second);
+      if (wmax > nbmax)
+        throw Fail{TAPG_EINVAL, "segment schedule: a workgroup would hold more than " +
+                                    std::to_string(nbmax) + " nodes of one stage"};
+      const int nst = P.s_end - P.s_begin + 1;
+      int nch = 0;
+      if (P.s_end + 1 < t.N) {
+        for (int w = 0; w < P.n_wg; ++w) {
+          const auto& q = rp[(size_t)w * nst + nst - 1];
+          nch = std::max(nch, t.cend[q.second - 1] - t.cbeg[q.first]);
+        }
+      }
+      Slot::Level L{P.s_begin, P.s_end, P.n_wg, nb_template(wmax), nch, nullptr, nullptr};
+      const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, nst, nch)
+                                 : seg_lds_probe<double>(S, L.nbm, nst, nch);
+      if (lds + kSegStaticLds > S->lds_limit)
+        throw Fail{TAPG_EINVAL, "segment schedule needs " + std::to_string(lds) +
+                                    " bytes of LDS per workgroup (limit " +
+                                    std::to_string(S->lds_limit) + ")"};
+      L.d_ranges = upload(rg, st);
+      levels.push_back(L);
+      if (t.ntrees > 1) {  // the tree of each workgroup, from its first node
+        std::vector<int> wt(P.n_wg, 0);
+        for (int w = 0; w < P.n_wg; ++w) {
+          const int n0 = rp[(size_t)w * nst].first;
+          int k = 0;
+          while (k + 1 < t.ntrees && t.seg_begin(P.s_begin, k + 1) <= n0) ++k;
+          wt[w] = k;
+        }
+        levels.back().d_wgtree = upload(wt, st);
+      }
+      ptot += P.n_wg;
+    }
+  } catch (...) {
+    for (auto& L : levels) {
+      dfree(L.d_ranges);
+      dfree(L.d_wgtree);
+    }
+    throw;
+  }
+  for (auto& L : sl.levels) {
+    dfree(L.d_ranges);
+    dfree(L.d_wgtree);
+  }
+  sl.levels = std::move(levels);
+  sl.plans = plans;
+  sl.part_total = ptot;
+  sl.segmented = true;
+  if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+  sl.graph = nullptr;
+}
+
 Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
   TAPG_HIP(hipSetDevice(S->device));
   hipStream_t st = S->stream;
@@ -722,57 +837,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       }
       sl.tile_offset[t.N] = tot;
       sl.total_tiles = tot;
-      if (S->seg_ok) {
-        const int nbmax = kSegNbMax;
-        const double node_us = (double)S->net.nu * S->net.nu / 64.0 / 2400.0 * (S->fp32 ? 0.5 : 1.0);
-        const char* spec = std::getenv("TAPG_LEVELS");
-        std::vector<LevelPlan> plans =
-            (spec && spec[0]) ? levels_from_env(t, spec) : plan_levels(t, nbmax, node_us);
-        int ptot = 0;
-        for (const LevelPlan& P : plans) {
-          int wmax = 0;
-          std::vector<std::pair<int, int>> rp = level_ranges(t, P, wmax);
-          std::vector<int2> rg(rp.size());
-          for (size_t k = 0; k < rp.size(); ++k) rg[k] = make_int2(rp[k].first, rp[k].second);
-          if (wmax > nbmax)
-            throw Fail{TAPG_EINVAL, "segment schedule: a workgroup would hold more than " +
-                                        std::to_string(nbmax) + " nodes of one stage"};
-          int nch = 0;
-          if (P.s_end + 1 < t.N) {
-            const int nst = P.s_end - P.s_begin + 1;
-            for (int w = 0; w < P.n_wg; ++w) {
-              const auto& q = rp[(size_t)w * nst + nst - 1];
-              nch = std::max(nch, t.cend[q.second - 1] - t.cbeg[q.first]);
-            }
-          }
-          Slot::Level L{P.s_begin, P.s_end, P.n_wg, nb_template(wmax), nch, nullptr, nullptr};
-          {
-            const int nst = P.s_end - P.s_begin + 1;
-            const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, nst, nch)
-                                       : seg_lds_probe<double>(S, L.nbm, nst, nch);
-            if (lds + kSegStaticLds > S->lds_limit)
-              throw Fail{TAPG_EINVAL, "segment schedule needs " + std::to_string(lds) +
-                                          " bytes of LDS per workgroup (limit " +
-                                          std::to_string(S->lds_limit) + ")"};
-          }
-          L.d_ranges = upload(rg, st);
-          if (t.ntrees > 1) {  // the tree of each workgroup, from its first node
-            const int nst = P.s_end - P.s_begin + 1;
-            std::vector<int> wt(P.n_wg, 0);
-            for (int w = 0; w < P.n_wg; ++w) {
-              const int n0 = rp[(size_t)w * nst].first;
-              int k = 0;
-              while (k + 1 < t.ntrees && t.seg_begin(P.s_begin, k + 1) <= n0) ++k;
-              wt[w] = k;
-            }
-            L.d_wgtree = upload(wt, st);
-          }
-          sl.levels.push_back(L);
-          ptot += P.n_wg;
-        }
-        sl.part_total = ptot;
-        sl.segmented = true;
-      }
+      if (S->seg_ok) build_levels(S, t, sl, choose_plans(S, t));
       sl.part_cap = std::max(tot, 4 * K);
       sl.d_part = dmalloc<double>(sl.part_cap);
     } catch (...) {
@@ -810,15 +875,11 @@ void dev_solve(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p, c
 }
 
 namespace {
-template <typename T>
-void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
-                const std::vector<Slot*>& own, const double* const* p, const double* const* q,
-                const int* warm, const std::vector<double>& gam, tapg_result* res) {
-  const NetworkHost& h = S->net;
+// The forest of a batch, cached by the member ids (its data refreshed when a
+// member's data changed).
+Batch& get_batch(tapg_solver_s* S, const std::vector<const TreeHost*>& trees) {
   hipStream_t st = S->stream;
-  const int LDX = S->LDX, LDU = S->LDU, LDY = S->LDY, PQ = LDX + LDU;
   const int nt = (int)trees.size();
-  // the forest of this batch, cached by the member ids
   std::vector<uint64_t> key(nt);
   for (int k = 0; k < nt; ++k) key[k] = trees[k]->uid;
   auto bit = S->batches.find(key);
@@ -843,7 +904,78 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
       for (int k = 0; k < nt; ++k) bit->second.versions[k] = trees[k]->version;
     }
   }
-  Batch& B = bit->second;
+  return bit->second;
+}
+
+// Iteration graph of a forest slot (chunk iterations), captured on demand.
+template <typename T>
+void ensure_graph(tapg_solver_s* S, Slot& sl, int chunk) {
+  if (!S->use_graph || (sl.graph != nullptr && sl.graph_iters == chunk)) return;
+  hipStream_t st = S->stream;
+  if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+  sl.graph = nullptr;
+  hipGraph_t g = nullptr;
+  const NetDev<T>& d = net_of<T>(S);
+  TAPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+  TAPG_HIP(hipStreamEndCapture(st, &g));
+  hipError_t e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw Fail{TAPG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+  sl.graph_iters = chunk;
+}
+
+template <typename T>
+void run_chunk(tapg_solver_s* S, Slot& sl, int chunk) {
+  if (S->use_graph) {
+    TAPG_HIP(hipGraphLaunch(sl.graph, S->stream));
+  } else {
+    const NetDev<T>& d = net_of<T>(S);
+    for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    TAPG_HIP(hipGetLastError());
+  }
+}
+
+template <typename T>
+void forest_data_step(tapg_solver_s* S, const TreeHost& f, Slot& sl) {
+  const NetworkHost& h = S->net;
+  launch_data_step<T>(f.K, h.nx, h.nu, h.nd, S->LDX, S->LDU, (const int*)sl.d_stage,
+                      (const double*)sl.d_prob64, (const double*)sl.d_demand,
+                      (const double*)sl.d_price, (const double*)S->dx.Pd,
+                      (const double*)S->dx.Gd, (const double*)S->dx.Gbar,
+                      (const double*)S->d64.F, (const double*)S->dx.alpha0,
+                      (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
+                      static_cast<T*>(sl.d_g), S->stream);
+  TAPG_HIP(hipGetLastError());
+}
+
+// Per-tree cost and violations of a forest's current primal into B.d_red.
+template <typename T>
+void forest_cost(tapg_solver_s* S, const TreeHost& f, Slot& sl, Batch& B) {
+  const NetworkHost& h = S->net;
+  launch_cost<T>(f.K, h.nx, h.nu, h.nd, h.ns, S->LDX, S->LDU, (const int*)sl.d_anc,
+                 (const double*)sl.d_prob64, (const double*)sl.d_demand,
+                 (const double*)sl.d_price, (const T*)sl.d_u, (const T*)sl.d_x,
+                 (const double*)sl.d_pq64, (const double*)S->d64.A, (const double*)S->d64.B,
+                 (const double*)S->dx.Gd, (const double*)S->dx.E, (const double*)S->dx.Ed,
+                 (const double*)S->dx.Wu, (const double*)S->dx.alpha0, (const double*)S->dx.cE,
+                 (const double*)S->d64.xmin, (const double*)S->d64.xmax,
+                 (const double*)S->d64.xs, (const double*)S->d64.umin,
+                 (const double*)S->d64.umax, S->cfg.W_alpha, S->cfg.W_x, S->cfg.W_s, sl.d_part,
+                 S->dx.red, S->stream);
+  launch_cost_reduce_forest(sl.d_part, B.d_tstart, f.N, f.ntrees, B.d_red, S->stream);
+  TAPG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
+                const std::vector<Slot*>& own, const double* const* p, const double* const* q,
+                const int* warm, const std::vector<double>& gam, tapg_result* res) {
+  const NetworkHost& h = S->net;
+  hipStream_t st = S->stream;
+  const int LDX = S->LDX, LDU = S->LDU, LDY = S->LDY, PQ = LDX + LDU;
+  const int nt = (int)trees.size();
+  Batch& B = get_batch(S, trees);
   const TreeHost& f = B.forest;
   Slot& sl = dev_slot(S, f);
   if (!sl.segmented)
@@ -903,6 +1035,7 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
     sl.graph_iters = chunk;
   }
   int launched = 0;
+  ProgressLine progress("batch");
   while (true) {
     if (S->use_graph) {
       TAPG_HIP(hipGraphLaunch(sl.graph, st));
@@ -914,7 +1047,12 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
     TAPG_HIP(hipMemcpyAsync(c.data(), sl.d_ctl, c.size() * sizeof(DevCtl), hipMemcpyDeviceToHost, st));
     TAPG_HIP(hipStreamSynchronize(st));
     bool all = true;
-    for (int k = 0; k < nt; ++k) all = all && c[k].done;
+    int running = 0;
+    for (int k = 0; k < nt; ++k) {
+      all = all && c[k].done;
+      running += c[k].done ? 0 : 1;
+    }
+    progress.tick(launched, running, nt);
     if (all || launched >= S->cfg.max_iter) break;
   }
   TAPG_HIP(hipEventRecord(S->ev1, st));
@@ -973,6 +1111,277 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
   }
 }
 }  // namespace
+
+namespace {
+std::vector<const TreeHost*> live_trees(const std::vector<LiveTree*>& js) {
+  std::vector<const TreeHost*> t(js.size());
+  for (size_t k = 0; k < js.size(); ++k) t[k] = js[k]->t;
+  return t;
+}
+
+std::vector<uint64_t> live_key(const std::vector<LiveTree*>& js) {
+  std::vector<uint64_t> key(js.size());
+  for (size_t k = 0; k < js.size(); ++k) key[k] = js[k]->t->uid;
+  return key;
+}
+
+// The forest slot of the live set (must exist).
+Slot& live_slot(tapg_solver_s* S, const std::vector<LiveTree*>& js, Batch*& B) {
+  auto bit = S->batches.find(live_key(js));
+  if (bit == S->batches.end()) throw Fail{TAPG_ESTATE, "no forest for this set of trees"};
+  B = &bit->second;
+  auto sit = S->slots.find(B->forest.uid);
+  if (sit == S->slots.end()) throw Fail{TAPG_ESTATE, "forest slot missing"};
+  return sit->second;
+}
+
+template <typename T>
+void live_init_impl(tapg_solver_s* S, LiveTree& j) {
+  Slot& o = *j.own;
+  hipStream_t st = S->stream;
+  const size_t yb = (size_t)j.t->K * S->LDY * sizeof(T);
+  if (j.warm && o.has_dual) {
+    void* src = o.last_iter_parity ? o.d_Y1 : o.d_Y0;
+    void* dst = o.last_iter_parity ? o.d_Y0 : o.d_Y1;
+    TAPG_HIP(hipMemcpyAsync(dst, src, yb, hipMemcpyDeviceToDevice, st));
+  } else {
+    TAPG_HIP(hipMemsetAsync(o.d_Y0, 0, yb, st));
+    TAPG_HIP(hipMemsetAsync(o.d_Y1, 0, yb, st));
+  }
+  o.last_iter_parity = 0;
+  j.ctl = DevCtl{};
+  j.ctl.max_iter = S->cfg.max_iter;
+  j.ctl.tol = S->cfg.tol;
+  j.ctl.gamma = j.gamma;
+  j.ctl.theta = 1.0;
+  j.ctl.theta_prev = 1.0;
+  j.ctl.beta = 0.0;
+  j.it0 = 0;
+  j.finished = false;
+  j.res = tapg_result{};
+}
+
+template <typename T>
+void live_enter_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
+  hipStream_t st = S->stream;
+  const int LDX = S->LDX, LDU = S->LDU, LDY = S->LDY, PQ = LDX + LDU;
+  const int nt = (int)js.size();
+  Batch& B = get_batch(S, live_trees(js));
+  const TreeHost& f = B.forest;
+  Slot& sl = dev_slot(S, f);
+  if (!sl.segmented)
+    throw Fail{TAPG_EINVAL, "batched solves need the segment kernels (nx, nu <= 128, sparse B)"};
+  std::vector<double> pq64((size_t)nt * PQ, 0.0);
+  std::vector<DevCtl> c(nt);
+  for (int k = 0; k < nt; ++k) {
+    std::copy(js[k]->p.begin(), js[k]->p.end(), pq64.begin() + (size_t)k * PQ);
+    std::copy(js[k]->q.begin(), js[k]->q.end(), pq64.begin() + (size_t)k * PQ + LDX);
+    c[k] = js[k]->ctl;
+    js[k]->it0 = c[k].iter;
+  }
+  std::vector<T> pqT(pq64.begin(), pq64.end());
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemcpyAsync(sl.d_ctl, c.data(), c.size() * sizeof(DevCtl), hipMemcpyHostToDevice, st));
+  for (int k = 0; k < nt; ++k) {  // both dual buffers, as the tree left them
+    const int* idx = B.d_map + B.map_off[k];
+    const Slot& o = *js[k]->own;
+    launch_copy_rows<T>(static_cast<const T*>(o.d_Y0), LDY, static_cast<T*>(sl.d_Y0), LDY, idx,
+                        js[k]->t->K, LDY, true, st);
+    launch_copy_rows<T>(static_cast<const T*>(o.d_Y1), LDY, static_cast<T*>(sl.d_Y1), LDY, idx,
+                        js[k]->t->K, LDY, true, st);
+  }
+  TAPG_HIP(hipGetLastError());
+  forest_data_step<T>(S, f, sl);
+  const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
+  ensure_graph<T>(S, sl, chunk);
+  TAPG_HIP(hipStreamSynchronize(st));
+}
+
+template <typename T>
+bool live_chunk_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
+  Batch* B = nullptr;
+  Slot& sl = live_slot(S, js, B);
+  hipStream_t st = S->stream;
+  const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
+  TAPG_HIP(hipEventRecord(S->ev0, st));
+  run_chunk<T>(S, sl, chunk);
+  TAPG_HIP(hipEventRecord(S->ev1, st));
+  std::vector<DevCtl> c(js.size());
+  TAPG_HIP(hipMemcpyAsync(c.data(), sl.d_ctl, c.size() * sizeof(DevCtl), hipMemcpyDeviceToHost, st));
+  TAPG_HIP(hipStreamSynchronize(st));
+  float ms = 0.f;
+  TAPG_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+  bool any = false;
+  for (size_t k = 0; k < js.size(); ++k) {
+    const bool was_done = js[k]->ctl.done;
+    js[k]->ctl = c[k];
+    if (!was_done) js[k]->res.solve_ms += ms;  // GPU time of the chunks the tree ran in
+    any = any || (c[k].done && !was_done);
+  }
+  return any;
+}
+
+template <typename T>
+void live_leave_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
+  Batch* B = nullptr;
+  Slot& sl = live_slot(S, js, B);
+  hipStream_t st = S->stream;
+  const int LDX = S->LDX, LDU = S->LDU, LDY = S->LDY;
+  const int nt = (int)js.size();
+  bool any_done = false;
+  for (LiveTree* j : js) any_done = any_done || j->ctl.done;
+  std::vector<double> red((size_t)3 * nt, 0.0);
+  if (any_done) {
+    forest_cost<T>(S, B->forest, sl, *B);
+    TAPG_HIP(hipMemcpyAsync(red.data(), B->d_red, red.size() * 8, hipMemcpyDeviceToHost, st));
+  }
+  for (int k = 0; k < nt; ++k) {
+    LiveTree& j = *js[k];
+    Slot& o = *j.own;
+    const int* idx = B->d_map + B->map_off[k];
+    const int Kk = j.t->K;
+    launch_copy_rows<T>(static_cast<const T*>(sl.d_Y0), LDY, static_cast<T*>(o.d_Y0), LDY, idx,
+                        Kk, LDY, false, st);
+    launch_copy_rows<T>(static_cast<const T*>(sl.d_Y1), LDY, static_cast<T*>(o.d_Y1), LDY, idx,
+                        Kk, LDY, false, st);
+    const int a = std::min(j.it0, o.hist_cap), b = std::min(j.ctl.iter, o.hist_cap);
+    if (b > a)
+      TAPG_HIP(hipMemcpyAsync(o.d_hist + a, sl.d_hist + (size_t)k * sl.hist_cap + a,
+                              (size_t)(b - a) * 8, hipMemcpyDeviceToDevice, st));
+    o.last_iter_parity = j.ctl.iter & 1;
+    if (j.ctl.done) {
+      launch_copy_rows<T>(static_cast<const T*>(sl.d_u), LDU, static_cast<T*>(o.d_u), LDU, idx,
+                          Kk, LDU, false, st);
+      launch_copy_rows<T>(static_cast<const T*>(sl.d_x), LDX, static_cast<T*>(o.d_x), LDX, idx,
+                          Kk, LDX, false, st);
+    }
+  }
+  TAPG_HIP(hipGetLastError());
+  TAPG_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < nt; ++k) {
+    LiveTree& j = *js[k];
+    if (!j.ctl.done) continue;
+    Slot& o = *j.own;
+    j.res.iters = j.ctl.iter;
+    j.res.converged = j.ctl.converged;
+    j.res.primal_res = j.ctl.last_res;
+    j.res.cost = red[3 * k + 0];
+    j.res.viol_box = red[3 * k + 1];
+    j.res.viol_eq = red[3 * k + 2];
+    j.res.gamma = j.gamma;
+    o.has_dual = true;
+    o.last = j.res;
+    o.has_result = true;
+    o.numeric = j.ctl.numeric != 0;
+    j.finished = true;
+  }
+  dev_drop_batch(S, live_key(js));
+}
+}  // namespace
+
+void dev_live_init(tapg_solver_s* S, LiveTree& j) {
+  TAPG_HIP(hipSetDevice(S->device));
+  if (S->fp32) live_init_impl<float>(S, j); else live_init_impl<double>(S, j);
+}
+
+void dev_live_enter(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
+  TAPG_HIP(hipSetDevice(S->device));
+  if (S->fp32) live_enter_impl<float>(S, js); else live_enter_impl<double>(S, js);
+}
+
+bool dev_live_chunk(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
+  TAPG_HIP(hipSetDevice(S->device));
+  return S->fp32 ? live_chunk_impl<float>(S, js) : live_chunk_impl<double>(S, js);
+}
+
+void dev_live_leave(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
+  TAPG_HIP(hipSetDevice(S->device));
+  if (S->fp32) live_leave_impl<float>(S, js); else live_leave_impl<double>(S, js);
+}
+
+namespace {
+// Device time of one APG iteration of a slot under its current levels: an
+// iteration graph of `iters` iterations, launched once to warm up and once
+// timed.  The state is synthetic (zero duals, a tiny step size, no stop), so
+// the iterates stay finite whatever the tree.
+template <typename T>
+double time_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
+  hipStream_t st = S->stream;
+  const int nt = t.ntrees, PQ = S->LDX + S->LDU;
+  std::vector<DevCtl> c(nt);
+  for (int k = 0; k < nt; ++k) {
+    c[k] = DevCtl{};
+    c[k].max_iter = 1 << 30;
+    c[k].tol = 0.0;
+    c[k].gamma = 1e-9;
+    c[k].theta = c[k].theta_prev = 1.0;
+  }
+  std::vector<double> pq64((size_t)nt * PQ, 0.0);
+  std::vector<T> pqT(pq64.size(), T(0));
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  const size_t yb = (size_t)t.K * S->LDY * sizeof(T);
+  TAPG_HIP(hipMemsetAsync(sl.d_Y0, 0, yb, st));
+  TAPG_HIP(hipMemsetAsync(sl.d_Y1, 0, yb, st));
+  forest_data_step<T>(S, t, sl);
+  const NetDev<T>& d = net_of<T>(S);
+  auto run = [&](bool timed) {
+    TAPG_HIP(hipMemcpyAsync(sl.d_ctl, c.data(), c.size() * sizeof(DevCtl), hipMemcpyHostToDevice, st));
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    TAPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < iters; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    TAPG_HIP(hipStreamEndCapture(st, &g));
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw Fail{TAPG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    if (timed) TAPG_HIP(hipEventRecord(S->ev0, st));
+    e = hipGraphLaunch(ge, st);
+    if (timed && e == hipSuccess) e = hipEventRecord(S->ev1, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(ge);
+    if (e != hipSuccess) throw Fail{TAPG_EDEVICE, std::string("autotune run: ") + hipGetErrorString(e)};
+    float ms = 0.f;
+    if (timed) TAPG_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+    return (double)ms;
+  };
+  run(false);
+  return run(true) / iters;
+}
+
+template <typename T>
+double autotune_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters, int* ncand) {
+  std::vector<std::vector<LevelPlan>> cands = candidate_plans(t, kSegNbMax, seg_node_us(S));
+  if (ncand) *ncand = (int)cands.size();
+  double best = 1e300;
+  size_t bi = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    build_levels(S, t, sl, cands[i]);
+    const double ms = time_levels<T>(S, t, sl, iters);
+    if (ms < best) {
+      best = ms;
+      bi = i;
+    }
+  }
+  build_levels(S, t, sl, cands[bi]);
+  S->tuned[shape_key(t)] = cands[bi];
+  sl.has_dual = false;  // the timing runs overwrote the iterates
+  sl.has_result = false;
+  return best;
+}
+}  // namespace
+
+double dev_autotune(tapg_solver_s* S, const std::vector<const TreeHost*>& trees, int iters,
+                    int* ncand) {
+  TAPG_HIP(hipSetDevice(S->device));
+  if (!S->seg_ok) throw Fail{TAPG_EINVAL, "the autotuner chooses segment schedules (nx, nu <= 128)"};
+  const TreeHost* t = trees[0];
+  if (trees.size() > 1) t = &get_batch(S, trees).forest;
+  Slot& sl = dev_slot(S, *t);
+  return S->fp32 ? autotune_impl<float>(S, *t, sl, iters, ncand)
+                 : autotune_impl<double>(S, *t, sl, iters, ncand);
+}
 
 void dev_drop_batch(tapg_solver_s* S, const std::vector<uint64_t>& key) {
   auto it = S->batches.find(key);

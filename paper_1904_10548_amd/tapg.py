@@ -37,7 +37,8 @@ EXPORTED = [
     "tapg_tree_num_nodes", "tapg_tree_destroy", "tapg_solver_create", "tapg_solver_destroy",
     "tapg_factor_step", "tapg_get_factors", "tapg_factor_blocks", "tapg_solve", "tapg_batch_solve", "tapg_get_primal", "tapg_get_dual",
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
-    "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_solver_forget",
+    "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune",
+    "tapg_solver_forget",
     "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
 ]
@@ -113,6 +114,8 @@ def lib() -> ctypes.CDLL:
         "tapg_get_factors": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
         "tapg_factor_blocks": ([_P, _I, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_solver_forget": ([_P, _P], ctypes.c_int),
+        "tapg_autotune": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.c_int, _D,
+                           ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_server_create": ([_P, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
         "tapg_server_submit": ([_P, _P, _D, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)],
                                ctypes.c_int),
@@ -294,6 +297,17 @@ def tapg_batch_solve(solver, trees, ps, qs, warm_start=None, nu=None):
     st = _check(lib().tapg_batch_solve(solver, n, tarr, parr, qarr, warr, uarr, res),
                 allow=(TAPG_OK, TAPG_ENOTCONV))
     return st, u0, list(res)
+
+
+def tapg_autotune(solver, trees, iters=20):
+    """Time every candidate schedule of the tree / batch and keep the fastest;
+    returns ``(ms_per_iteration, candidates)``."""
+    n = len(trees)
+    tarr = (_P * n)(*trees)
+    ms = np.zeros(1)
+    nc = ctypes.c_int(0)
+    _check(lib().tapg_autotune(solver, n, tarr, int(iters), _ptr(ms), ctypes.byref(nc)))
+    return float(ms[0]), nc.value
 
 
 def tapg_solver_forget(solver, tree):

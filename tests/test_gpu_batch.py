@@ -153,3 +153,25 @@ def test_batch_argument_errors():
             S.batch_solve([trees[0], trees[0]], [batch[0].p] * 2, [batch[0].q] * 2)
         with pytest.raises(tapg.TapgError):
             S.batch_solve([], [], [])
+
+
+def test_autotuned_schedule_keeps_parity():
+    """The autotuner times the candidate schedules of a batch's forest and of a
+    single tree; solves under the chosen schedules still match the oracle."""
+    batch = tiny_batch(SHAPES, seed=13)
+    gamma = _gamma_for(batch)
+    iters = 200
+    with make_solver(batch[0], gamma=gamma, tol=0.0, max_iter=iters, check_every=50) as S:
+        trees = [add_tree(S, P) for P in batch]
+        ms_b, nc_b = tapg.tapg_autotune(S.h, trees, 10)
+        ms_1, nc_1 = tapg.tapg_autotune(S.h, trees[2:3], 10)
+        say("autotune", ms_b, nc_b, ms_1, nc_1)
+        st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
+        u, x = S.primal(trees[2])
+    assert nc_b >= 1 and nc_1 >= 1 and ms_b > 0 and ms_1 > 0
+    for P, r in zip(batch, res):
+        ref = O.apg(P, gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
+        J = O.primal_cost(P, ref.u, ref.x)
+        assert r.iters == iters and abs(r.cost - J) <= 1e-6 * max(1.0, abs(J))
+    ref = O.apg(batch[2], gamma, O.StageFactors(batch[2].net, batch[2].weights.W_u, batch[2].tree), iters)
+    assert np.abs(u - ref.u).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())

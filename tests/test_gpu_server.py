@@ -71,6 +71,42 @@ def test_server_matches_single_solves_with_session_warm_start():
         assert abs(r2.cost - rb.cost) <= 1e-9 * max(1.0, abs(rb.cost))
 
 
+def test_server_continuous_admission_same_result_alone_and_in_the_mix():
+    """Requests arrive while others are being iterated: they join the running
+    set between chunks (the forest is re-formed, every running tree keeping
+    its exact state), and each result equals the tree solved alone."""
+    import time
+    batch = tiny_batch(SHAPES, seed=41)
+    kw = dict(gamma=0.0, tol=1e-9, max_iter=200000, check_every=20)
+    nu = batch[0].net.nu
+    say("server continuous", [P.tree.K for P in batch])
+    with make_solver(batch[0], **kw) as S:
+        trees = [add_tree(S, P) for P in batch]
+        srv = tapg.tapg_server_create(S.h, 1 << 34, 64)
+        try:
+            tickets = []
+            for k, (t, P) in enumerate(zip(trees, batch)):
+                tickets.append(tapg.tapg_server_submit(srv, t, P.p, P.q, session=k))
+                time.sleep(0.01)
+            out = [tapg.tapg_server_poll(srv, t, nu) for t in tickets]
+            stats = tapg.tapg_server_stats(srv)
+        finally:
+            tapg.tapg_server_destroy(srv)
+    with make_solver(batch[0], **kw) as S:
+        alone = []
+        for P in batch:
+            t = add_tree(S, P)
+            _, u0, r = S.solve(t, P.p, P.q)
+            alone.append((u0, r))
+    say("forests formed", stats["batches"], "iterations", [o[2].iters for o in out])
+    assert stats["batches"] >= 2
+    for (st, u0, r, lat), (u0a, ra) in zip(out, alone):
+        assert st == tapg.TAPG_OK and r.converged
+        assert r.iters == ra.iters
+        assert np.abs(u0 - u0a).max() <= 1e-12 * max(1.0, np.abs(u0a).max())
+        assert abs(r.cost - ra.cost) <= 1e-9 * max(1.0, abs(ra.cost))
+
+
 def test_server_rejects_requests_over_the_budget():
     batch = tiny_batch(SHAPES[:2], seed=3)
     nu = batch[0].net.nu
