@@ -98,6 +98,16 @@ struct SegArgs {
   int hist_stride;
   int pq_stride;     // (p, q) of tree k at pq + k * pq_stride
   unsigned* counter; // workgroups of the closing launch that have finished
+  // Projector form of the stage factor (W_u = w I): Fbar v = (v - E'(G v)) / w
+  // with G = (E E')^{-1} E, both sparse (CSR of G: ns rows, of E': nu rows).
+  int proj, ns, nnzG, nnzE;
+  const int* Grow;
+  const int* Gcol;
+  const T* Gval;
+  const int* Etrow;
+  const int* Etcol;
+  const T* Etval;
+  T winv;
 };
 
 // Launch wrappers (segment_kernels.hip).

@@ -264,6 +264,9 @@ size_t seg_lds_bytes(const SegArgs<T>& a) {
   b += (size_t)a.nst * sizeof(int2) + (size_t)(a.nst + 1) * sizeof(int);  // ranges, factor ids
   b += (size_t)(nrows + 2 + a.nnzB) * sizeof(int);
   b += (size_t)a.nnzB * sizeof(T);
+  if (a.proj)  // CSR of G and of E', each with a padding int
+    b += (size_t)(a.ns + 2 + a.nnzG + a.nu + 2 + a.nnzE) * sizeof(int) +
+         (size_t)(a.nnzG + a.nnzE) * sizeof(T) + 16;
   return (b + 15) & ~(size_t)15;
 }
 
@@ -273,7 +276,7 @@ size_t seg_lds_bytes(const SegArgs<T>& a) {
 //   v_n      = -(w3_n + B' lambda_n)/2 + W_u sum_{c} j_c
 //   j_n      = kappa_n + Fbar_s v_n
 // ---------------------------------------------------------------------------
-template <typename T, int NB>
+template <typename T, int NB, bool PROJ>
 __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
   const DevCtl* ctl = a.ctl + tree;
@@ -300,6 +303,12 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   int* sRow = sFid + a.nst + (a.nst & 1);            // CSR of B' (nu rows), 8-byte aligned
   int* sCol = sRow + nu + 1;
   T* sVal = reinterpret_cast<T*>(sCol + a.nnzB + ((nu + 1 + a.nnzB) & 1));  // 8-byte aligned
+  int* gRow = reinterpret_cast<int*>(sVal + a.nnzB);  // projector path: CSR of G, then of E'
+  int* gCol = gRow + a.ns + 1;
+  T* gVal = reinterpret_cast<T*>(gCol + a.nnzG + ((a.ns + 1 + a.nnzG) & 1));
+  int* eRow = reinterpret_cast<int*>(gVal + a.nnzG);
+  int* eCol = eRow + nu + 1;
+  T* eVal = reinterpret_cast<T*>(eCol + a.nnzE + ((nu + 1 + a.nnzE) & 1));
   {
     const int2* rg = a.ranges + (size_t)blockIdx.x * a.nst;
     for (int i = tid; i < a.nst; i += kSegThreads) {
@@ -307,6 +316,10 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
       sFid[i] = a.fid[a.s_begin + i];
     }
     csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
+    if constexpr (PROJ) {
+      csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, a.ns, a.nnzG, gRow, gCol, gVal);
+      csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
+    }
     __syncthreads();
   }
   // this thread's rows of B' (one per u-slot)
@@ -315,6 +328,18 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   for (int q = 0; q < QX; ++q) {
     const int i = (tid + q * kSegThreads) % LDU;
     brow[q].load(sRow, sCol, sVal, i, i < nu);
+  }
+  // projector path: row tid % ns of G for the node column tid / ns, rows of E'
+  const int ns = a.ns;
+  RegRow<T, 4> grow;
+  RegRow<T, 2> erow[QX];
+  if constexpr (PROJ) {
+    grow.load(gRow, gCol, gVal, ns > 0 ? tid % ns : 0, ns > 0 && tid < NB * ns);
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+      const int i = (tid + q * kSegThreads) % LDU;
+      erow[q].load(eRow, eCol, eVal, i, i < nu);
+    }
   }
 
   const int r = tid % kRT;
@@ -334,7 +359,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   // stage is served by another block (right after the GEMV that consumed it).
   T mreg[kKC];
   int f_cur = __builtin_amdgcn_readfirstlane(sFid[a.s_end - a.s_begin]);
-  load_factor<T>(a.F + (size_t)f_cur * kLDU * kLDU, r, kb, mreg);
+  if constexpr (!PROJ) load_factor<T>(a.F + (size_t)f_cur * kLDU * kLDU, r, kb, mreg);
   auto load_stage = [&](int s_, Pre& P) {
 
     const int2 rr_ = sRg[s_ - a.s_begin];
@@ -488,13 +513,18 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
       }
       __syncthreads();
     }
-    // j = kappa + Fbar_s v   (register-resident Fbar_s)
-    gemv_cols<T, NB, (NB >= 2 && sizeof(T) == 4 ? 2 : 1)>(mreg, sV, kb, ks, r, nb, red);
-    if (s > a.s_begin) {
-      const int fn = __builtin_amdgcn_readfirstlane(sFid[s - 1 - a.s_begin]);
-      if (fn != f_cur) {
-        f_cur = fn;
-        load_factor<T>(a.F + (size_t)fn * kLDU * kLDU, r, kb, mreg);
+    // j = kappa + Fbar_s v: register-resident Fbar_s, or the projector form
+    // (v - E'(G v)) / w whose G v goes through red
+    if constexpr (PROJ) {
+      if (tid < nb * ns) red[tid] = grow.apply(T(0), sV + (tid / ns) * kLDU, gCol, gVal);
+    } else {
+      gemv_cols<T, NB, (NB >= 2 && sizeof(T) == 4 ? 2 : 1)>(mreg, sV, kb, ks, r, nb, red);
+      if (s > a.s_begin) {
+        const int fn = __builtin_amdgcn_readfirstlane(sFid[s - 1 - a.s_begin]);
+        if (fn != f_cur) {
+          f_cur = fn;
+          load_factor<T>(a.F + (size_t)fn * kLDU * kLDU, r, kb, mreg);
+        }
       }
     }
     __syncthreads();
@@ -504,7 +534,11 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
       const int b = idx / LDU, i = idx - b * LDU;
       dn[q] = -1;
       if (idx < NB * LDU && b < nb && i < nu) {
-        const T jn = kap[q] + sum_partials<T, NB>(red, b, i);
+        T jn;
+        if constexpr (PROJ)
+          jn = kap[q] + a.winv * (sV[b * kLDU + i] - erow[q].apply(T(0), red + b * ns, eCol, eVal));
+        else
+          jn = kap[q] + sum_partials<T, NB>(red, b, i);
         sJ[b * LDU + i] = jn;
         dj[q] = jn;
         dn[q] = (lo + b) * LDU + i;
@@ -605,7 +639,7 @@ __device__ void seg_iteration_end(const SegArgs<T>& a, double* sred, int* s_last
 // The product Fbar_s (W_u u_anc) is formed once per parent.  The launch of
 // the last level ends the iteration in its last workgroup to finish.
 // ---------------------------------------------------------------------------
-template <typename T, int NB>
+template <typename T, int NB, bool PROJ>
 __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
   DevCtl* ctl = a.ctl + tree;
@@ -637,6 +671,12 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
   int* sRow = sFid + a.nst + (a.nst & 1);            // CSR of B (nx rows), 8-byte aligned
   int* sCol = sRow + nx + 1;
   T* sVal = reinterpret_cast<T*>(sCol + a.nnzB + ((nx + 1 + a.nnzB) & 1));  // 8-byte aligned
+  int* gRow = reinterpret_cast<int*>(sVal + a.nnzB);  // projector path: CSR of G, then of E'
+  int* gCol = gRow + a.ns + 1;
+  T* gVal = reinterpret_cast<T*>(gCol + a.nnzG + ((a.ns + 1 + a.nnzG) & 1));
+  int* eRow = reinterpret_cast<int*>(gVal + a.nnzG);
+  int* eCol = eRow + nu + 1;
+  T* eVal = reinterpret_cast<T*>(eCol + a.nnzE + ((nu + 1 + a.nnzE) & 1));
   {
     const int2* rg = a.ranges + (size_t)blockIdx.x * a.nst;
     for (int i = tid; i < a.nst; i += kSegThreads) {
@@ -644,6 +684,10 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
       sFid[i] = a.fid[a.s_begin + i];
     }
     csr_to_lds<T>(a.Brow, a.Bcol, a.Bval, nx, a.nnzB, sRow, sCol, sVal);
+    if constexpr (PROJ) {
+      csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, a.ns, a.nnzG, gRow, gCol, gVal);
+      csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
+    }
   }
 
   const int r = tid % kRT;
@@ -711,8 +755,20 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
     const int i = (tid + q * kSegThreads) % LDX;
     brow[q].load(sRow, sCol, sVal, i, i < nx);
   }
+  // projector path: row tid % ns of G for the parent column tid / ns, rows of E'
+  const int ns = a.ns;
+  RegRow<T, 4> grow;
+  RegRow<T, 2> erow[QX];
+  if constexpr (PROJ) {
+    grow.load(gRow, gCol, gVal, ns > 0 ? tid % ns : 0, ns > 0 && tid < NB * ns);
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+      const int i = (tid + q * kSegThreads) % LDU;
+      erow[q].load(eRow, eCol, eVal, i, i < nu);
+    }
+  }
   int f_cur = __builtin_amdgcn_readfirstlane(sFid[0]);
-  load_factor<T>(a.F + (size_t)f_cur * kLDU * kLDU, r, kb, mreg);
+  if constexpr (!PROJ) load_factor<T>(a.F + (size_t)f_cur * kLDU * kLDU, r, kb, mreg);
   load_stage(s, PA);
   T* sUp = sU0;  // parents (stage s-1)
   T* sUn = sU1;
@@ -794,16 +850,21 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
       __syncthreads();
       V = sUn;
     }
-    // Fbar_s (W_u u_anc), one column per parent
-    // (one column at a time in FP64: the forward kernel's registers are scarce)
-    gemv_cols<T, NB, (NB >= 2 && NB <= 4 && sizeof(T) == 4 ? 2 : 1)>(mreg, V, kb, ks, r, np, red);
-    // this stage's factor is consumed: load the next stage's into the same
-    // registers if it is another block
-    if (s < a.s_end) {
-      const int fn = __builtin_amdgcn_readfirstlane(sFid[s + 1 - a.s_begin]);
-      if (fn != f_cur) {
-        f_cur = fn;
-        load_factor<T>(a.F + (size_t)fn * kLDU * kLDU, r, kb, mreg);
+    if constexpr (PROJ) {
+      // projector form (W_u = w I): Kbar_s u_anc = u_anc - E'(G u_anc); G u_anc via red
+      if (tid < np * ns) red[tid] = grow.apply(T(0), V + (tid / ns) * kLDU, gCol, gVal);
+    } else {
+      // Fbar_s (W_u u_anc), one column per parent
+      // (one column at a time in FP64: the forward kernel's registers are scarce)
+      gemv_cols<T, NB, (NB >= 2 && NB <= 4 && sizeof(T) == 4 ? 2 : 1)>(mreg, V, kb, ks, r, np, red);
+      // this stage's factor is consumed: load the next stage's into the same
+      // registers if it is another block
+      if (s < a.s_end) {
+        const int fn = __builtin_amdgcn_readfirstlane(sFid[s + 1 - a.s_begin]);
+        if (fn != f_cur) {
+          f_cur = fn;
+          load_factor<T>(a.F + (size_t)fn * kLDU * kLDU, r, kb, mreg);
+        }
       }
     }
     __syncthreads();
@@ -817,7 +878,11 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
       dnu[q] = -1;
       if (idx < NB * LDU && b < nb && i < nu) {
         const int pb = C.pau[q] >= 0 ? C.pau[q] - lo_p : 0;
-        un = wsc * sum_partials<T, NB>(red, pb, i) + C.pj[q] * C.pp[q];
+        if constexpr (PROJ)
+          un = (V[pb * kLDU + i] - erow[q].apply(T(0), red + pb * ns, eCol, eVal)) +
+               C.pj[q] * C.pp[q];
+        else
+          un = wsc * sum_partials<T, NB>(red, pb, i) + C.pj[q] * C.pp[q];
         dnu[q] = lo + b;
       }
       du[q] = un;
@@ -997,10 +1062,17 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
 template <typename T, int NB>
 void launch_seg_nb(bool fwd, const SegArgs<T>& a, int n_wg, hipStream_t st) {
   const size_t lds = seg_lds_bytes<T, NB>(a);
-  if (fwd)
-    hipLaunchKernelGGL((seg_fwd_kernel<T, NB>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
-  else
-    hipLaunchKernelGGL((seg_bwd_kernel<T, NB>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+  if (a.proj) {
+    if (fwd)
+      hipLaunchKernelGGL((seg_fwd_kernel<T, NB, true>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+    else
+      hipLaunchKernelGGL((seg_bwd_kernel<T, NB, true>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+  } else {
+    if (fwd)
+      hipLaunchKernelGGL((seg_fwd_kernel<T, NB, false>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+    else
+      hipLaunchKernelGGL((seg_bwd_kernel<T, NB, false>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+  }
 }
 
 template <typename T>

@@ -17,6 +17,10 @@ struct NetDev {
   // CSR of B (nx rows) and of B' (nu rows); dense W_u (column-major, ld LDU)
   int *Brow = nullptr, *Bcol = nullptr, *Btrow = nullptr, *Btcol = nullptr;
   T *Bval = nullptr, *Btval = nullptr, *Wu = nullptr;
+  // projector form of the stage factor (W_u = w I): CSR of G = (E E')^{-1} E
+  // (ns rows) and of E' (nu rows)
+  int *Grow = nullptr, *Gcol = nullptr, *Etrow = nullptr, *Etcol = nullptr;
+  T *Gval = nullptr, *Etval = nullptr;
 };
 
 // A cached batch: the forest of its trees (keyed by their ids) and the
@@ -74,6 +78,11 @@ struct tapg_solver_s {
   double wu = 1.0;
   bool seg_ok = false;  // segment kernels apply (nx, nu <= 128, B with few nonzeros)
   int nnzB = 0;
+  // W_u = w I makes every stage factor Pi / w with Pi = I - E'(E E')^{-1} E;
+  // the sweeps then apply it as (v - E'(G v)) / w when G is sparse
+  bool proj = false;
+  int nnzG = 0, nnzE = 0;
+  tapg::Mat G;  // (E E')^{-1} E, ns x nu
   size_t lds_limit = 64 * 1024;  // dynamic LDS per workgroup (device attribute)
   // optional per-launch timing of the sweep kernels (HIP events around each
   // launch; graphs are bypassed while it is on)

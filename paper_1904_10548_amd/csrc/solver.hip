@@ -126,6 +126,17 @@ void init_net(tapg_solver_s* S, NetDev<T>& d) {
   d.Btcol = upload(col, st);
   d.Btval = upload(val, st);
   d.Wu = upload(colmajor<T>(Mat::from(S->Wu.data(), h.nu, h.nu), S->LDU, false), st);
+  if (S->proj) {
+    csr(S->G);
+    if (S->G.r == 0) row.assign(1, 0);
+    d.Grow = upload(row, st);
+    d.Gcol = upload(col, st);
+    d.Gval = upload(val, st);
+    csr(transpose(h.E));
+    d.Etrow = upload(row, st);
+    d.Etcol = upload(col, st);
+    d.Etval = upload(val, st);
+  }
 }
 
 template <typename T>
@@ -135,6 +146,7 @@ void free_net(NetDev<T>& d) {
   dfree(d.F); dfree(d.Kb);
   dfree(d.Brow); dfree(d.Bcol); dfree(d.Bval); dfree(d.Btrow); dfree(d.Btcol); dfree(d.Btval);
   dfree(d.Wu);
+  dfree(d.Grow); dfree(d.Gcol); dfree(d.Gval); dfree(d.Etrow); dfree(d.Etcol); dfree(d.Etval);
 }
 
 // Nodes per tile: the largest NB in {8, 4, 2, 1} that keeps at least 256
@@ -197,6 +209,10 @@ size_t seg_lds_probe(tapg_solver_s* S, int nbm, int nst, int nch) {
   probe.LDU = S->LDU;
   probe.nst = nst;
   probe.nnzB = S->nnzB;
+  probe.proj = S->proj ? 1 : 0;
+  probe.ns = S->net.ns;
+  probe.nnzG = S->nnzG;
+  probe.nnzE = S->nnzE;
   return seg_lds<T>(nbm, probe);
 }
 
@@ -224,6 +240,17 @@ SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mod
   a.invp = static_cast<const T*>(sl.d_invp);
   a.F = d.F;
   a.fid = S->d_fid;
+  a.proj = S->proj ? 1 : 0;
+  a.ns = S->net.ns;
+  a.nnzG = S->nnzG;
+  a.nnzE = S->nnzE;
+  a.Grow = d.Grow;
+  a.Gcol = d.Gcol;
+  a.Gval = d.Gval;
+  a.Etrow = d.Etrow;
+  a.Etcol = d.Etcol;
+  a.Etval = d.Etval;
+  a.winv = (T)(1.0 / S->wu);
   a.Wu = d.Wu;
   a.A = d.A;
   a.At = d.At;
@@ -563,6 +590,31 @@ void dev_init(tapg_solver_s* S) {
         if (S->Wu[(size_t)i * h.nu + j] != (i == j ? w0 : 0.0)) ws = false;
     S->wu_scalar = ws;
     S->wu = ws ? w0 : 1.0;
+    // projector form: G = (E E')^{-1} E by Cholesky of E E' (E has full row
+    // rank); used when G is sparse, as for mixing nodes with disjoint inputs
+    const char* pe = std::getenv("TAPG_PROJ");
+    S->proj = false;
+    if (ws && S->seg_ok && !(pe && pe[0] == '0')) {
+      Mat G(h.ns, h.nu);
+      bool ok = true;
+      if (h.ns > 0) {
+        Mat EEt = matmul(h.E, transpose(h.E));
+        ok = cholesky(EEt);
+        if (ok) {
+          G = h.E;
+          chol_solve(EEt, G);
+        }
+      }
+      int nnz = 0, nnzE = 0;
+      for (double v : G.a) nnz += v != 0.0;
+      for (double v : h.E.a) nnzE += v != 0.0;
+      if (ok && nnz <= 16 * std::max(1, h.ns)) {
+        S->proj = true;
+        S->G = G;
+        S->nnzG = nnz;
+        S->nnzE = nnzE;
+      }
+    }
   }
   if (S->stream == nullptr) {
     TAPG_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));

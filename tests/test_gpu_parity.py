@@ -42,9 +42,10 @@ def _oracle_run(P, gamma, iters, tol=None, factors=None):
     return O.apg(P, gamma, f, iters, tol=tol)
 
 
-def _schedule_env(graph=True, segments=True, levels=None):
+def _schedule_env(graph=True, segments=True, levels=None, proj=True):
     os.environ["TAPG_USE_GRAPH"] = "1" if graph else "0"
     os.environ["TAPG_SEGMENTS"] = "1" if segments else "0"
+    os.environ["TAPG_PROJ"] = "1" if proj else "0"
     if levels:
         os.environ["TAPG_LEVELS"] = levels
     else:
@@ -52,10 +53,10 @@ def _schedule_env(graph=True, segments=True, levels=None):
 
 
 def _compare_fixed(P, gamma, iters, precision=tapg.TAPG_FP64, check_every=50, graph=True,
-                   segments=True, levels=None):
-    _schedule_env(graph, segments, levels)
+                   segments=True, levels=None, proj=True):
+    _schedule_env(graph, segments, levels, proj)
     say(P.name, "K", P.tree.K, "iters", iters, "prec", precision, "graph", graph,
-        "segments", segments, "levels", levels)
+        "segments", segments, "levels", levels, "proj", proj)
     with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=check_every,
                      precision=precision) as S:
         t = add_tree(S, P)
@@ -126,9 +127,11 @@ def test_wide_ragged_tree_fp64_and_fp32():
     assert abs(r32.cost - J) <= 1e-4 * max(1.0, abs(J))
 
 
-@pytest.mark.parametrize("levels,fp32", [(None, False), ("0:1,2:2,4:1", False),
-                                         ("0:1,1:1,3:2,5:2", True)])
-def test_dwn128_fixed_iterations(levels, fp32):
+@pytest.mark.parametrize("levels,fp32,proj", [(None, False, True), (None, False, False),
+                                              ("0:1,2:2,4:1", False, True),
+                                              ("0:1,1:1,3:2,5:2", True, True),
+                                              ("0:1,1:1,3:2,5:2", True, False)])
+def test_dwn128_fixed_iterations(levels, fp32, proj):
     """Full-size network and tree (K = 2429): 40 iterations, every element;
     planned schedule and forced multi-level / grouped schedules."""
     P = ds.config_problem("dwn128")
@@ -136,11 +139,13 @@ def test_dwn128_fixed_iterations(levels, fp32):
     gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 60))
     if fp32:  # FP32 sweeps on a five-level schedule with groups of two
         st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40,
-                                                         precision=tapg.TAPG_FP32, levels=levels)
+                                                         precision=tapg.TAPG_FP32, levels=levels,
+                                                         proj=proj)
         J = O.primal_cost(P, ref.u, ref.x)
         assert abs(res.cost - J) <= 1e-4 * max(1.0, abs(J))
         return
-    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40, levels=levels)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40, levels=levels,
+                                                     proj=proj)
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 40)
 
 
