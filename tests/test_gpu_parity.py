@@ -9,6 +9,7 @@ hiding a wrong term.  FP32 sweeps: cost within 1e-4 relative of the FP64
 oracle.
 """
 
+import functools
 import os
 import sys
 
@@ -147,6 +148,35 @@ def test_dwn128_fixed_iterations(levels, fp32, proj):
     st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40, levels=levels,
                                                      proj=proj)
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 40)
+
+
+@functools.lru_cache(maxsize=1)
+def _dwn2048_reference():
+    """The oracle's 30 iterations on the 2,048-scenario tree (computed once)."""
+    P = ds.config_problem("dwn2048")
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 40))
+    iters = 30
+    return P, gamma, iters, O.apg(P, gamma, sf, iters)
+
+
+@pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
+def test_dwn2048_cost_error_against_oracle(precision):
+    """The 2,048-scenario tree (K = 30,717): 30 iterations, cost within 1e-6
+    (FP64 sweeps) or 1e-4 (FP32 sweeps, FP64 factors and residuals) of the FP64
+    oracle's; the root input within the same relative bounds."""
+    P, gamma, iters, ref = _dwn2048_reference()
+    say("dwn2048", P.tree.K, "prec", precision)
+    with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=iters,
+                     precision=precision) as S:
+        t = add_tree(S, P)
+        st, u0, res = S.solve(t, P.p, P.q)
+    J = O.primal_cost(P, ref.u, ref.x)
+    rel = abs(res.cost - J) / max(1.0, abs(J))
+    du = np.abs(u0 - ref.u[0]).max() / max(1.0, np.abs(ref.u[0]).max())
+    say("dwn2048 cost", res.cost, "oracle", J, "rel", rel, "root du", du)
+    bound = 1e-6 if precision == tapg.TAPG_FP64 else 1e-4
+    assert res.iters == iters and rel <= bound and du <= bound * 10
 
 
 def test_small_converged_matches_oracle_iteration_count():
