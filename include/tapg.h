@@ -208,9 +208,11 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
  * with a pair of HIP events on the solver's stream (iteration graphs are not
  * used meanwhile, and the host checks the stop flag after every iteration).
  * tapg_kernel_times returns, for the last timed solve, the summed device time
- * (ms[3]) and launch counts (launches[3]) of: [0] backward-stage kernels,
- * [1] forward-stage kernels (with the fused prox/dual update), [2] the
- * end-of-iteration kernel. */
+ * (ms[4]) and counts (launches[4]) of: [0] backward-sweep launches, [1]
+ * forward-sweep launches (with the fused prox/dual update), [2] separate
+ * end-of-iteration launches, [3] persistent-iteration launches, counted in
+ * iterations (with TAPG_CHAIN=1 a single tree whose workgroups all fit on the
+ * device runs every level in one cooperative launch per chunk of iterations). */
 tapg_status tapg_kernel_timing(tapg_solver solver, int enable);
 tapg_status tapg_kernel_times(tapg_solver solver, double* ms, long long* launches);
 

@@ -676,7 +676,7 @@ tapg_status tapg_kernel_times(tapg_solver solver, double* ms, long long* launche
     need(solver, "solver");
     need(ms, "ms");
     need(launches, "launches");
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       ms[k] = solver->kt_ms[k];
       launches[k] = solver->kt_n[k];
     }

@@ -167,6 +167,16 @@ struct Slot {
   int part_total = 0;
   int ntrees = 1;                // trees of the forest held by this slot
   unsigned* d_counter = nullptr; // closing-launch workgroup counter
+  // persistent iteration (one tree): per-level kernel arguments, hand-over
+  // tables and counters; chain_state 0: not set up, 1: usable, -1: not usable
+  void* d_chain_lev = nullptr;
+  int2* d_chain_par = nullptr;
+  int* d_chain_nchild = nullptr;
+  unsigned* d_chain_cnt = nullptr;  // backward counts, then forward flags
+  void* d_chain_sync = nullptr;
+  int chain_total = 0, chain_nbm = 0, chain_state = 0;
+  std::vector<int> chain_base;  // first workgroup of each level
+  size_t chain_lds = 0;
 };
 
 // Unique ids of trees and forests (never reused).

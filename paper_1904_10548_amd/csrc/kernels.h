@@ -110,11 +110,47 @@ struct SegArgs {
   T winv;
 };
 
+// Persistent iteration of one tree: every workgroup of every level in one
+// cooperative launch, iterating `iters` times.  Levels hand over through
+// counters instead of launch boundaries: a workgroup's backward sweep starts
+// once its child workgroups have finished theirs, its forward sweep once its
+// parent workgroup has finished its own; the top workgroup ends each iteration
+// (residual, stop test) once every workgroup has finished its forward sweep.
+constexpr int kChainMaxLevels = 8;
+struct ChainSync {
+  unsigned fwd_all;          // forward sweeps completed by all workgroups
+  int stop;                  // set by the top workgroup when the solve stops
+  int error;                 // a wait exceeded its bound
+  int pad;
+  unsigned long long res[2]; // residual max of the last two iterations (double bits)
+};
+template <typename T>
+struct ChainArgs {
+  const SegArgs<T>* lev;     // per level, top first (device memory)
+  int nlev, total, iters;
+  int base[kChainMaxLevels + 1];  // first workgroup of each level
+  const int2* parents;       // workgroups [x, y] owning the parents of a workgroup's first stage (x = -1: top)
+  const int* nchild;         // child workgroups of each workgroup
+  unsigned* bwd_cnt;         // per workgroup: backward sweeps completed by its children
+  unsigned* fwd_flag;        // per workgroup: forward sweeps completed
+  ChainSync* sync;
+  DevCtl* ctl;
+  double* hist;
+};
+
 // Launch wrappers (segment_kernels.hip).
 template <typename T>
 void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st);
 template <typename T>
 size_t seg_lds(int nbm, const SegArgs<T>& a);
+// Cooperative launch of the persistent iteration (NB: widest level's
+// template, lds: the largest level's dynamic LDS).  hipErrorCooperativeLaunch-
+// TooLarge (or any launch error) is returned, not thrown.
+template <typename T>
+hipError_t launch_chain(int nbm, bool proj, const ChainArgs<T>& c, size_t lds, hipStream_t st);
+// Workgroups of the persistent kernel resident per CU (occupancy).
+template <typename T>
+int chain_blocks_per_cu(int nbm, bool proj, size_t lds);
 
 // Launch wrappers (stage_kernels.hip).
 template <typename T>

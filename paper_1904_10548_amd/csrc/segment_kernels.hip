@@ -276,19 +276,16 @@ size_t seg_lds_bytes(const SegArgs<T>& a) {
 //   v_n      = -(w3_n + B' lambda_n)/2 + W_u sum_{c} j_c
 //   j_n      = kappa_n + Fbar_s v_n
 // ---------------------------------------------------------------------------
+// Backward sweep of one workgroup `wg` of a level in iteration `it` (its
+// extrapolation weight beta; scale: 1/|v| in the power iteration).
 template <typename T, int NB, bool PROJ>
-__global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
-  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
-  const DevCtl* ctl = a.ctl + tree;
-  if (ctl->done) return;
+__device__ __forceinline__ void seg_bwd_body(const SegArgs<T>& a, int wg, int it, T beta,
+                                             T scale) {
   constexpr int QX = NB * 128 / kSegThreads > 0 ? NB * 128 / kSegThreads : 1;
   const int tid = threadIdx.x;
-  const int it = ctl->iter;
   const bool power = a.mode == 1;
   const T* Yc = (it & 1) ? a.Y1 : a.Y0;
   const T* Yo = (it & 1) ? a.Y0 : a.Y1;
-  const T beta = (T)ctl->beta;
-  const T scale = (T)ctl->pw_scale;
   const int nx = a.nx, nu = a.nu, LDX = a.LDX, LDU = a.LDU, LDY = a.LDY;
 
   const int CB = a.nch > NB ? a.nch : NB;  // capacity of the child buffers
@@ -310,7 +307,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   int* eCol = eRow + nu + 1;
   T* eVal = reinterpret_cast<T*>(eCol + a.nnzE + ((nu + 1 + a.nnzE) & 1));
   {
-    const int2* rg = a.ranges + (size_t)blockIdx.x * a.nst;
+    const int2* rg = a.ranges + (size_t)wg * a.nst;
     for (int i = tid; i < a.nst; i += kSegThreads) {
       sRg[i] = rg[i];
       sFid[i] = a.fid[a.s_begin + i];
@@ -570,6 +567,14 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   flush();
 }
 
+template <typename T, int NB, bool PROJ>
+__global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
+  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
+  const DevCtl* ctl = a.ctl + tree;
+  if (ctl->done) return;
+  seg_bwd_body<T, NB, PROJ>(a, blockIdx.x, ctl->iter, (T)ctl->beta, (T)ctl->pw_scale);
+}
+
 // ---------------------------------------------------------------------------
 // Closing protocol of the last forward launch of an iteration: every workgroup
 // (those of trees that have stopped too) checks in, and the last one to do so
@@ -639,24 +644,18 @@ __device__ void seg_iteration_end(const SegArgs<T>& a, double* sred, int* s_last
 // The product Fbar_s (W_u u_anc) is formed once per parent.  The launch of
 // the last level ends the iteration in its last workgroup to finish.
 // ---------------------------------------------------------------------------
+// Forward sweep of workgroup `wg` of a level (tree `tree`) in iteration `it`
+// with the fused prox / dual update.  Returns the workgroup's residual max
+// max |y+ - w| / gamma (power iteration: the sum of squares of its part of the
+// new iterate); sred is scratch for the workgroup reduction.
 template <typename T, int NB, bool PROJ>
-__global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
-  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
-  DevCtl* ctl = a.ctl + tree;
-  __shared__ double sred[kSegThreads];
-  __shared__ int s_last;
-  if (ctl->done) {  // this tree has stopped; the closing launch still counts it
-    if (a.last_level) seg_iteration_end(a, sred, &s_last);
-    return;
-  }
+__device__ __forceinline__ double seg_fwd_body(const SegArgs<T>& a, int wg, int tree, int it,
+                                               T beta, double gam64, double* sred) {
   constexpr int QX = NB * 128 / kSegThreads > 0 ? NB * 128 / kSegThreads : 1;
   const int tid = threadIdx.x;
-  const int it = ctl->iter;
   const bool power = a.mode == 1;
   const T* Yc = (it & 1) ? a.Y1 : a.Y0;
   T* Yn = (it & 1) ? a.Y0 : a.Y1;  // y^{nu-1} in, y^{nu+1} out
-  const T beta = (T)ctl->beta;
-  const double gam64 = ctl->gamma;
   const T gam = (T)gam64;
   const int nx = a.nx, nu = a.nu, LDX = a.LDX, LDU = a.LDU, LDY = a.LDY;
 
@@ -678,7 +677,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
   int* eCol = eRow + nu + 1;
   T* eVal = reinterpret_cast<T*>(eCol + a.nnzE + ((nu + 1 + a.nnzE) & 1));
   {
-    const int2* rg = a.ranges + (size_t)blockIdx.x * a.nst;
+    const int2* rg = a.ranges + (size_t)wg * a.nst;
     for (int i = tid; i < a.nst; i += kSegThreads) {
       sRg[i] = rg[i];
       sFid[i] = a.fid[a.s_begin + i];
@@ -1044,18 +1043,165 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
     if (++s > a.s_end) break;
   }
   flush();
+  if (power) return block_sum512(zsq, sred);
+  // max |y+ - w| / gamma: the division by gamma > 0 is monotone, so dividing
+  // the workgroup's max once gives the max of the quotients exactly
+  return block_max512(rmax, sred) / gam64;
+}
 
-  // ---- end of the launch: residual / power partials, end of iteration ----
-  if (power) {
-    const double tot = block_sum512(zsq, sred);
-    if (tid == 0) a.part[a.part_base + blockIdx.x] = tot;
-  } else {
-    // max |y+ - w| / gamma: the division by gamma > 0 is monotone, so dividing
-    // the workgroup's max once gives the max of the quotients exactly
-    const double m = block_max512(rmax, sred) / gam64;
-    if (tid == 0) atomicMax(&ctl->res_bits, (unsigned long long)__double_as_longlong(m));
+template <typename T, int NB, bool PROJ>
+__global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
+  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
+  DevCtl* ctl = a.ctl + tree;
+  __shared__ double sred[kSegThreads];
+  __shared__ int s_last;
+  if (ctl->done) {  // this tree has stopped; the closing launch still counts it
+    if (a.last_level) seg_iteration_end(a, sred, &s_last);
+    return;
+  }
+  const double m = seg_fwd_body<T, NB, PROJ>(a, blockIdx.x, tree, ctl->iter, (T)ctl->beta,
+                                             ctl->gamma, sred);
+  if (threadIdx.x == 0) {
+    if (a.mode == 1)
+      a.part[a.part_base + blockIdx.x] = m;
+    else
+      atomicMax(&ctl->res_bits, (unsigned long long)__double_as_longlong(m));
   }
   if (a.last_level) seg_iteration_end(a, sred, &s_last);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent iteration (one tree).
+// ---------------------------------------------------------------------------
+namespace {
+
+// One step of the FISTA theta recursion (the extrapolation weights), written
+// once so that every workgroup and the closing code compute bit-identical
+// values (no contraction into FMAs).
+__device__ __forceinline__ void theta_step(double& theta, double& theta_prev, double& beta) {
+#pragma clang fp contract(off)
+  const double th = theta;
+  const double t2 = th * th;
+  const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
+  theta_prev = th;
+  theta = thn;
+  beta = thn * (1.0 / th - 1.0);
+}
+
+// A hand-over wait is declared stuck after 2 s of the 100 MHz real-time
+// counter (an iteration takes well under a millisecond).
+constexpr unsigned long long kChainWaitTicks = 200000000ull;
+
+// Thread 0 waits until *p >= target (acquire at device scope; the acquire also
+// drops this CU's stale cache lines before the workgroup reads the producer's
+// data).  Returns false when the solve was stopped or the wait hit its bound
+// (then the error flag and the stop flag are set).
+__device__ bool chain_wait(unsigned* p, unsigned target, ChainSync* sync, int* s_flag) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    while (true) {
+      if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (__hip_atomic_load(&sync->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kChainWaitTicks) {
+        __hip_atomic_store(&sync->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sync->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+}  // namespace
+
+template <typename T, int NB, bool PROJ>
+__global__ __launch_bounds__(kSegThreads) void seg_chain_kernel(ChainArgs<T> c) {
+  __shared__ double sred[kSegThreads];
+  __shared__ int s_flag;
+  const int g = blockIdx.x;
+  int l = 0;
+  while (l + 1 < c.nlev && g >= c.base[l + 1]) ++l;
+  const int wg = g - c.base[l];
+  const SegArgs<T>& a = c.lev[l];  // fields read on demand (scalar loads)
+  DevCtl* ctl = c.ctl;
+  ChainSync* sync = c.sync;
+  const int2 par = c.parents[g];  // parent workgroups [par.x, par.y] (par.x < 0: top level)
+  const unsigned need = (unsigned)c.nchild[g];
+  int it = ctl->iter;
+  double theta = ctl->theta, theta_prev = ctl->theta_prev, beta = ctl->beta;
+  const double gam64 = ctl->gamma;
+  // the top workgroup ends iteration `prev` once all forward sweeps of it are in
+  auto end_iteration = [&](int prev, unsigned all_target) -> bool {
+    if (!chain_wait(&sync->fwd_all, all_target, sync, &s_flag)) return false;
+    if (threadIdx.x == 0) {
+      const double res = __longlong_as_double(
+          (long long)__hip_atomic_exchange(&sync->res[prev & 1], 0ull, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
+      c.hist[prev] = res;
+      ctl->last_res = res;
+      ctl->iter = prev + 1;
+      if (!(res < INFINITY)) {
+        ctl->numeric = 1;
+        ctl->done = 1;
+      } else if (ctl->tol > 0.0 && res <= ctl->tol) {
+        ctl->converged = 1;
+        ctl->done = 1;
+      } else if (prev + 1 >= ctl->max_iter) {
+        ctl->done = 1;
+      }
+      double th = ctl->theta, thp = ctl->theta_prev, be = ctl->beta;
+      theta_step(th, thp, be);
+      ctl->theta = th;
+      ctl->theta_prev = thp;
+      ctl->beta = be;
+      s_flag = ctl->done;
+      if (ctl->done) __hip_atomic_store(&sync->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return s_flag == 0;
+  };
+  int k = 0;
+  for (; k < c.iters; ++k) {
+    // backward sweep, after the child workgroups' backward sweeps of this iteration
+    if (need > 0 && !chain_wait(&c.bwd_cnt[g], need * (unsigned)(k + 1), sync, &s_flag)) break;
+    seg_bwd_body<T, NB, PROJ>(a, wg, it, (T)beta, T(1));
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int p = par.x; p >= 0 && p <= par.y; ++p)
+        __hip_atomic_fetch_add(&c.bwd_cnt[p], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // forward sweep: the top workgroup first ends the previous iteration
+    if (l == 0) {
+      if (k > 0 && !end_iteration(it - 1, (unsigned)c.total * (unsigned)k)) break;
+    } else {
+      bool ok = true;
+      for (int p = par.x; ok && p <= par.y; ++p)
+        ok = chain_wait(&c.fwd_flag[p], (unsigned)(k + 1), sync, &s_flag);
+      if (!ok) break;
+    }
+    const double m = seg_fwd_body<T, NB, PROJ>(a, wg, 0, it, (T)beta, gam64, sred);
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_max(&sync->res[it & 1], (unsigned long long)__double_as_longlong(m),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&c.fwd_flag[g], (unsigned)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&sync->fwd_all, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ++it;
+    theta_step(theta, theta_prev, beta);
+  }
+  // the last iteration of the launch ends here (unless the solve stopped)
+  if (l == 0 && k == c.iters) end_iteration(it - 1, (unsigned)c.total * (unsigned)c.iters);
 }
 
 // ---------------------------------------------------------------------------
@@ -1093,6 +1239,45 @@ size_t seg_lds(int nbm, const SegArgs<T>& a) {
   }
 }
 
+template <typename T, int NB, bool PROJ>
+hipError_t launch_chain_nb(const ChainArgs<T>& c, size_t lds, hipStream_t st) {
+  void* args[] = {const_cast<ChainArgs<T>*>(&c)};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&seg_chain_kernel<T, NB, PROJ>),
+                                    dim3(c.total), dim3(kSegThreads), args, lds, st);
+}
+
+template <typename T>
+hipError_t launch_chain(int nbm, bool proj, const ChainArgs<T>& c, size_t lds, hipStream_t st) {
+  switch (nbm) {
+    case 4: return proj ? launch_chain_nb<T, 4, true>(c, lds, st) : launch_chain_nb<T, 4, false>(c, lds, st);
+    case 2: return proj ? launch_chain_nb<T, 2, true>(c, lds, st) : launch_chain_nb<T, 2, false>(c, lds, st);
+    default: return proj ? launch_chain_nb<T, 1, true>(c, lds, st) : launch_chain_nb<T, 1, false>(c, lds, st);
+  }
+}
+
+template <typename T, int NB, bool PROJ>
+int chain_occ(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&seg_chain_kernel<T, NB, PROJ>), kSegThreads, lds) !=
+      hipSuccess)
+    return 0;
+  return nb;
+}
+
+template <typename T>
+int chain_blocks_per_cu(int nbm, bool proj, size_t lds) {
+  switch (nbm) {
+    case 4: return proj ? chain_occ<T, 4, true>(lds) : chain_occ<T, 4, false>(lds);
+    case 2: return proj ? chain_occ<T, 2, true>(lds) : chain_occ<T, 2, false>(lds);
+    default: return proj ? chain_occ<T, 1, true>(lds) : chain_occ<T, 1, false>(lds);
+  }
+}
+
+template hipError_t launch_chain<double>(int, bool, const ChainArgs<double>&, size_t, hipStream_t);
+template hipError_t launch_chain<float>(int, bool, const ChainArgs<float>&, size_t, hipStream_t);
+template int chain_blocks_per_cu<double>(int, bool, size_t);
+template int chain_blocks_per_cu<float>(int, bool, size_t);
 template void launch_seg<double>(bool, int, const SegArgs<double>&, int, hipStream_t);
 template void launch_seg<float>(bool, int, const SegArgs<float>&, int, hipStream_t);
 template size_t seg_lds<double>(int, const SegArgs<double>&);

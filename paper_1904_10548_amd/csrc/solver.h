@@ -89,8 +89,10 @@ struct tapg_solver_s {
   bool time_kernels = false;
   bool server_active = false;  // a tapg_server drives this solver (other calls refused)
   std::vector<hipEvent_t> tev;      // pairs, reused per chunk
-  double kt_ms[3] = {0, 0, 0};      // backward stages, forward stages, iteration end
-  long long kt_n[3] = {0, 0, 0};
+  // backward stages, forward stages, iteration end, persistent iteration
+  // (launches; for the persistent one, iterations covered)
+  double kt_ms[4] = {0, 0, 0, 0};
+  long long kt_n[4] = {0, 0, 0, 0};
 };
 
 namespace tapg {

@@ -387,6 +387,116 @@ std::vector<T> pad_rows(const double* src, int rows, int cols, int ld) {
   return out;
 }
 
+// Whether the persistent iteration runs this slot, setting it up the first
+// time: asked for with TAPG_CHAIN=1 (it measured slower than the level
+// launches on the Barcelona-sized tree: every hand-over is a device-scope
+// release / acquire), one tree, the segment schedule with the projector form,
+// at most kChainMaxLevels levels, every workgroup resident at once.
+template <typename T>
+bool chain_usable(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
+  if (sl.chain_state) return sl.chain_state > 0;
+  sl.chain_state = -1;
+  const char* env = std::getenv("TAPG_CHAIN");
+  if (!(env && env[0] == '1')) return false;
+  const int nl = (int)sl.levels.size();
+  if (t.ntrees != 1 || !sl.segmented || !S->proj || nl < 1 || nl > kChainMaxLevels) return false;
+  int total = 0, nbm = 1;
+  for (const Slot::Level& L : sl.levels) {
+    total += L.n_wg;
+    nbm = std::max(nbm, L.nbm);
+  }
+  size_t lds = 0;
+  for (const Slot::Level& L : sl.levels)
+    lds = std::max(lds, seg_lds_probe<T>(S, nbm, L.s_end - L.s_begin + 1, L.nch));
+  if (lds + kSegStaticLds > S->lds_limit) return false;
+  int cus = 0;
+  TAPG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device));
+  const int bpc = chain_blocks_per_cu<T>(nbm, true, lds);
+  if (bpc < 1 || (long long)bpc * cus < total) return false;
+  // per-level arguments, and the workgroups that hand over to each other
+  hipStream_t st = S->stream;
+  const NetDev<T>& d = net_of<T>(S);
+  std::vector<SegArgs<T>> lev(nl);
+  std::vector<int> base(nl + 1, 0);
+  std::vector<std::vector<std::pair<int, int>>> rng(nl);
+  for (int l = 0; l < nl; ++l) {
+    const Slot::Level& L = sl.levels[l];
+    SegArgs<T> a = make_seg_args<T>(S, sl, d, 0);
+    a.s_begin = L.s_begin;
+    a.s_end = L.s_end;
+    a.nst = L.s_end - L.s_begin + 1;
+    a.ranges = L.d_ranges;
+    a.wgtree = nullptr;
+    a.part_base = base[l];
+    a.nch = L.nch;
+    a.last_level = 0;
+    lev[l] = a;
+    base[l + 1] = base[l] + L.n_wg;
+    int wmax = 0;
+    rng[l] = level_ranges(t, sl.plans[l], wmax);
+  }
+  std::vector<int2> par(total, make_int2(-1, -1));
+  std::vector<int> nchild(total, 0);
+  for (int l = 1; l < nl; ++l) {
+    const int nst_p = sl.levels[l - 1].s_end - sl.levels[l - 1].s_begin + 1;
+    const int nst = sl.levels[l].s_end - sl.levels[l].s_begin + 1;
+    auto owner = [&](int node) {  // workgroup of level l-1 holding `node` at its last stage
+      for (int w = 0; w < sl.levels[l - 1].n_wg; ++w) {
+        const auto& r = rng[l - 1][(size_t)w * nst_p + nst_p - 1];
+        if (node >= r.first && node < r.second) return w;
+      }
+      throw Fail{TAPG_EINVAL, "persistent iteration: parent workgroup not found"};
+    };
+    for (int w = 0; w < sl.levels[l].n_wg; ++w) {
+      const auto& r = rng[l][(size_t)w * nst];
+      const int p0 = owner(t.anc[r.first]), p1 = owner(t.anc[r.second - 1]);
+      par[base[l] + w] = make_int2(base[l - 1] + p0, base[l - 1] + p1);
+      for (int p = p0; p <= p1; ++p) nchild[base[l - 1] + p]++;
+    }
+  }
+  void* dlev = nullptr;
+  TAPG_HIP(hipMalloc(&dlev, sizeof(SegArgs<T>) * nl));
+  sl.d_chain_lev = dlev;
+  TAPG_HIP(hipMemcpy(dlev, lev.data(), sizeof(SegArgs<T>) * nl, hipMemcpyHostToDevice));
+  sl.d_chain_par = upload(par, st);
+  sl.d_chain_nchild = upload(nchild, st);
+  sl.d_chain_cnt = dmalloc<unsigned>((size_t)2 * total);
+  void* dsync = nullptr;
+  TAPG_HIP(hipMalloc(&dsync, sizeof(ChainSync)));
+  sl.d_chain_sync = dsync;
+  sl.chain_total = total;
+  sl.chain_nbm = nbm;
+  sl.chain_lds = lds;
+  sl.chain_state = 1;
+  sl.chain_base.assign(base.begin(), base.end());
+  return true;
+}
+
+// Run `iters` iterations with one cooperative launch of the persistent kernel.
+template <typename T>
+void chain_run(tapg_solver_s* S, Slot& sl, int iters, bool timed) {
+  hipStream_t st = S->stream;
+  ChainArgs<T> c{};
+  c.lev = static_cast<const SegArgs<T>*>(sl.d_chain_lev);
+  c.nlev = (int)sl.levels.size();
+  c.total = sl.chain_total;
+  c.iters = iters;
+  for (int l = 0; l <= c.nlev; ++l) c.base[l] = sl.chain_base[l];
+  c.parents = sl.d_chain_par;
+  c.nchild = sl.d_chain_nchild;
+  c.bwd_cnt = sl.d_chain_cnt;
+  c.fwd_flag = sl.d_chain_cnt + sl.chain_total;
+  c.sync = static_cast<ChainSync*>(sl.d_chain_sync);
+  c.ctl = sl.d_ctl;
+  c.hist = sl.d_hist;
+  TAPG_HIP(hipMemsetAsync(sl.d_chain_cnt, 0, sizeof(unsigned) * 2 * sl.chain_total, st));
+  TAPG_HIP(hipMemsetAsync(sl.d_chain_sync, 0, sizeof(ChainSync), st));
+  if (timed) TAPG_HIP(hipEventRecord(S->tev[0], st));
+  hipError_t e = launch_chain<T>(sl.chain_nbm, true, c, sl.chain_lds, st);
+  if (e != hipSuccess) throw Fail{TAPG_EDEVICE, std::string("persistent iteration launch: ") + hipGetErrorString(e)};
+  if (timed) TAPG_HIP(hipEventRecord(S->tev[1], st));
+}
+
 template <typename T>
 void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
                 const double* q, bool warm, double gamma, tapg_result& res) {
@@ -433,7 +543,8 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   // iterations, in chunks of check_every with a host check between chunks
   const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
   const NetDev<T>& d = net_of<T>(S);
-  if (S->use_graph && !S->time_kernels && (sl.graph == nullptr || sl.graph_iters != chunk)) {
+  const bool chain = chain_usable<T>(S, t, sl);
+  if (!chain && S->use_graph && !S->time_kernels && (sl.graph == nullptr || sl.graph_iters != chunk)) {
     if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
     sl.graph = nullptr;
     hipGraph_t g = nullptr;
@@ -456,12 +567,31 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
       TAPG_HIP(hipEventCreate(&e));
       S->tev.push_back(e);
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       S->kt_ms[k] = 0.0;
       S->kt_n[k] = 0;
     }
   }
-  while (true) {
+  while (chain) {  // persistent iteration: one cooperative launch per chunk
+    const int before = hc.iter;
+    chain_run<T>(S, sl, chunk, timed);
+    launched += chunk;
+    ChainSync sync{};
+    TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+    TAPG_HIP(hipMemcpyAsync(&sync, sl.d_chain_sync, sizeof(sync), hipMemcpyDeviceToHost, st));
+    TAPG_HIP(hipStreamSynchronize(st));
+    if (sync.error)
+      throw Fail{TAPG_EDEVICE, "persistent iteration: a hand-over wait exceeded its bound"};
+    if (timed) {
+      float ms = 0.f;
+      TAPG_HIP(hipEventElapsedTime(&ms, S->tev[0], S->tev[1]));
+      S->kt_ms[3] += ms;
+      S->kt_n[3] += hc.iter - before;
+    }
+    progress.tick(launched, hc.done ? 0 : 1, 1);
+    if (hc.done || launched >= S->cfg.max_iter) break;
+  }
+  while (!chain) {
     if (timed) {
       // one iteration per check so that launches after the stop are not timed
       TimedCursor tc;
@@ -637,6 +767,8 @@ void dev_init(tapg_solver_s* S) {
   TAPG_HIP(hipStreamSynchronize(st));
 }
 
+void free_chain(Slot& sl);
+
 void dev_free_slot(Slot& sl) {
   if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
   sl.graph = nullptr;
@@ -646,6 +778,7 @@ void dev_free_slot(Slot& sl) {
   dfree(sl.d_P0); dfree(sl.d_P1);
   dfree(sl.d_Y0); dfree(sl.d_Y1); dfree(sl.d_lam); dfree(sl.d_j); dfree(sl.d_u); dfree(sl.d_x);
   dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part); dfree(sl.d_counter);
+  free_chain(sl);
   for (auto& L : sl.levels) {
     dfree(L.d_ranges);
     dfree(L.d_wgtree);
@@ -759,6 +892,18 @@ std::vector<LevelPlan> choose_plans(tapg_solver_s* S, const TreeHost& t) {
   return plan_levels(t, kSegNbMax, seg_node_us(S));
 }
 
+// Resources of the persistent iteration of a slot (rebuilt on demand).
+void free_chain(Slot& sl) {
+  if (sl.d_chain_lev) (void)hipFree(sl.d_chain_lev);
+  if (sl.d_chain_sync) (void)hipFree(sl.d_chain_sync);
+  sl.d_chain_lev = nullptr;
+  sl.d_chain_sync = nullptr;
+  dfree(sl.d_chain_par);
+  dfree(sl.d_chain_nchild);
+  dfree(sl.d_chain_cnt);
+  sl.chain_state = 0;
+}
+
 // (Re)build the level launches of a slot from a plan.
 void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vector<LevelPlan>& plans) {
   hipStream_t st = S->stream;
@@ -816,6 +961,7 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
   }
   sl.levels = std::move(levels);
   sl.plans = plans;
+  free_chain(sl);
   sl.part_total = ptot;
   sl.segmented = true;
   if (sl.graph) (void)hipGraphExecDestroy(sl.graph);

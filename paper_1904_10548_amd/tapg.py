@@ -405,11 +405,12 @@ def tapg_kernel_timing(solver, enable: bool):
 
 
 def tapg_kernel_times(solver):
-    """``{'bwd': (ms, launches), 'fwd': (...), 'end': (...)}`` of the last timed solve."""
-    ms = np.zeros(3)
-    n = (ctypes.c_longlong * 3)()
+    """``{'bwd': (ms, launches), 'fwd': (...), 'end': (...), 'chain': (ms, iterations)}``
+    of the last timed solve."""
+    ms = np.zeros(4)
+    n = (ctypes.c_longlong * 4)()
     _check(lib().tapg_kernel_times(solver, _ptr(ms), n))
-    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(["bwd", "fwd", "end"])}
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(["bwd", "fwd", "end", "chain"])}
 
 
 # --------------------------------------------------------------------------

@@ -43,10 +43,11 @@ def _oracle_run(P, gamma, iters, tol=None, factors=None):
     return O.apg(P, gamma, f, iters, tol=tol)
 
 
-def _schedule_env(graph=True, segments=True, levels=None, proj=True):
+def _schedule_env(graph=True, segments=True, levels=None, proj=True, chain=True):
     os.environ["TAPG_USE_GRAPH"] = "1" if graph else "0"
     os.environ["TAPG_SEGMENTS"] = "1" if segments else "0"
     os.environ["TAPG_PROJ"] = "1" if proj else "0"
+    os.environ["TAPG_CHAIN"] = "1" if chain else "0"
     if levels:
         os.environ["TAPG_LEVELS"] = levels
     else:
@@ -54,10 +55,10 @@ def _schedule_env(graph=True, segments=True, levels=None, proj=True):
 
 
 def _compare_fixed(P, gamma, iters, precision=tapg.TAPG_FP64, check_every=50, graph=True,
-                   segments=True, levels=None, proj=True):
-    _schedule_env(graph, segments, levels, proj)
+                   segments=True, levels=None, proj=True, chain=True):
+    _schedule_env(graph, segments, levels, proj, chain)
     say(P.name, "K", P.tree.K, "iters", iters, "prec", precision, "graph", graph,
-        "segments", segments, "levels", levels, "proj", proj)
+        "segments", segments, "levels", levels, "proj", proj, "chain", chain)
     with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=check_every,
                      precision=precision) as S:
         t = add_tree(S, P)
@@ -87,14 +88,17 @@ def _assert_fp64_parity(P, res, u, x, y, hist, ref, iters):
     assert abs(res.primal_res - rh[-1]) <= 1e-7 * rh[-1] + 1e-12
 
 
-@pytest.mark.parametrize("graph,segments", [(True, True), (False, True), (True, False)])
-def test_small_500_iterations_fp64(graph, segments):
-    """The small configuration at exactly 500 iterations (no early stop)."""
+@pytest.mark.parametrize("graph,segments,chain", [(True, True, True), (True, True, False),
+                                                 (False, True, False), (True, False, False)])
+def test_small_500_iterations_fp64(graph, segments, chain):
+    """The small configuration at exactly 500 iterations (no early stop):
+    persistent iteration, level launches with and without graphs, per-stage
+    kernels."""
     P = ds.config_problem("small")
     nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
     gamma = 1.0 / O.lipschitz_dense(P, nf)
     st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 500, graph=graph,
-                                                     segments=segments)
+                                                     segments=segments, chain=chain)
     assert st == tapg.TAPG_OK
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 500)
     assert np.abs(u0 - ref.u[0]).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())
@@ -128,11 +132,13 @@ def test_wide_ragged_tree_fp64_and_fp32():
     assert abs(r32.cost - J) <= 1e-4 * max(1.0, abs(J))
 
 
-@pytest.mark.parametrize("levels,fp32,proj", [(None, False, True), (None, False, False),
-                                              ("0:1,2:2,4:1", False, True),
-                                              ("0:1,1:1,3:2,5:2", True, True),
-                                              ("0:1,1:1,3:2,5:2", True, False)])
-def test_dwn128_fixed_iterations(levels, fp32, proj):
+@pytest.mark.parametrize("levels,fp32,proj,chain", [(None, False, True, True),
+                                                    (None, False, True, False),
+                                                    (None, False, False, False),
+                                                    ("0:1,2:2,4:1", False, True, True),
+                                                    ("0:1,1:1,3:2,5:2", True, True, True),
+                                                    ("0:1,1:1,3:2,5:2", True, False, False)])
+def test_dwn128_fixed_iterations(levels, fp32, proj, chain):
     """Full-size network and tree (K = 2429): 40 iterations, every element;
     planned schedule and forced multi-level / grouped schedules."""
     P = ds.config_problem("dwn128")
@@ -141,12 +147,12 @@ def test_dwn128_fixed_iterations(levels, fp32, proj):
     if fp32:  # FP32 sweeps on a five-level schedule with groups of two
         st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40,
                                                          precision=tapg.TAPG_FP32, levels=levels,
-                                                         proj=proj)
+                                                         proj=proj, chain=chain)
         J = O.primal_cost(P, ref.u, ref.x)
         assert abs(res.cost - J) <= 1e-4 * max(1.0, abs(J))
         return
     st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40, levels=levels,
-                                                     proj=proj)
+                                                     proj=proj, chain=chain)
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 40)
 
 

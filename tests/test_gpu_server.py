@@ -21,6 +21,7 @@ SHAPES = [(2, 4), (3, 3), ("irregular", 3, 20), (1, 1), (2, 8)]
 def _default_schedule():
     os.environ.pop("TAPG_LEVELS", None)
     os.environ.pop("TAPG_PROJ", None)
+    os.environ.pop("TAPG_CHAIN", None)
     os.environ["TAPG_USE_GRAPH"] = "1"
     os.environ["TAPG_SEGMENTS"] = "1"
     yield
