@@ -133,6 +133,8 @@ struct Slot {
   double* d_pq64 = nullptr;
   void *d_P0 = nullptr, *d_P1 = nullptr;  // power-iteration vectors
   // iterates
+  // scan form: kappa - Pi kappa; Pi u at level ends; Pi q per tree
+  void *d_kperp = nullptr, *d_zb = nullptr, *d_zr = nullptr;
   void *d_Y0 = nullptr, *d_Y1 = nullptr, *d_lam = nullptr, *d_j = nullptr, *d_u = nullptr,
        *d_x = nullptr;
   DevCtl* d_ctl = nullptr;

@@ -108,6 +108,13 @@ struct SegArgs {
   const int* Etcol;
   const T* Etval;
   T winv;
+  // Scan form of the sweeps (A = I and the projector form): kperp_n = kappa_n
+  // - Pi kappa_n per node; zb_n = Pi u_n, written at a level's last stage for
+  // the level below; jv holds P_n = Pi j_n instead of j_n.
+  int scan;
+  const T* kperp;
+  T* zb;
+  const T* zr;  // Pi q of each tree (the root's parent input), LDU apart
 };
 
 // Persistent iteration of one tree: every workgroup of every level in one
@@ -139,6 +146,11 @@ struct ChainArgs {
 };
 
 // Launch wrappers (segment_kernels.hip).
+// Scan-form sweep launches and their dynamic LDS (scan_kernels.hip).
+template <typename T>
+void launch_scan(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st);
+template <typename T>
+size_t scan_lds(int nbm, const SegArgs<T>& a);
 template <typename T>
 void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st);
 template <typename T>
@@ -164,7 +176,7 @@ void launch_data_step(int K, int nx, int nu, int nd, int LDX, int LDU, const int
                       const double* prob, const double* demand, const double* price,
                       const double* Pd, const double* Gd, const double* Gbar, const double* Fbar,
                       const double* alpha0, const double* cE, double W_alpha, T* kappa, T* g,
-                      hipStream_t st);
+                      int ns, const double* Gm, const double* E, T* kperp, hipStream_t st);
 template <typename T>
 void launch_cost(int K, int nx, int nu, int nd, int ns, int LDX, int LDU, const int* anc,
                  const double* prob, const double* demand, const double* price, const T* u,

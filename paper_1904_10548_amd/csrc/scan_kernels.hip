@@ -1,0 +1,876 @@
+// Scan-form sweep kernels for gfx950: the dual-gradient sweeps (Sec. 4.4) of a
+// network with A = I and W_u = w I, whose stage factors are Fbar_s = Pi / w and
+// Kbar_s = Pi with Pi = I - E'(E E')^{-1} E, the orthogonal projector onto the
+// null space of E (Pi Pi = Pi).
+//
+// With these factors the stage-by-stage recursions unroll into sums over
+// subtrees (backward) and along root paths (forward).  Writing P_n = Pi j_n
+// and z_n = Pi u_n:
+//   lambda_n = a_n + sum_c lambda_c                  a_n = w1_n + w2_n
+//   m_n      = Pi (kappa_n - (w3_n + B' lambda_n) / (2 w))
+//   P_n      = m_n + sum_c P_c
+//   j_n      = kperp_n + P_n                         kperp_n = kappa_n - Pi kappa_n
+//   u_n      = z_anc + j_n / p_n,   z_n = z_anc + P_n / p_n
+//   x_n      = x_anc + B u_n + g_n
+// (P_n = Pi j_n follows from j_n = kappa_n + Pi v_n / w and Pi Pi = Pi; then
+// j_n = kappa_n - Pi kappa_n + P_n, and z_n = Pi u_anc + Pi j_n / p_n.)
+// Only vector additions remain on the chain from stage to stage; the products
+// with Pi, B and B' are per node.  A workgroup therefore takes its stages in
+// chunks of 16 node-stages (16 / NB stages of NB nodes): each per-node product
+// runs over the whole chunk at once, spread over all 512 threads, and each
+// chain is walked by one thread per vector component, with the values of the
+// neighbouring stage in registers.  A chunk costs five barriers (backward) or
+// four (forward) however many stages it holds.
+//
+// The workgroups, levels and node ranges are those of the segment kernels, so
+// the schedule, the forest layout and the closing protocol are shared.  Global
+// loads of the next chunk are issued while the current one computes, and a
+// chunk's stores are issued at the start of the next, after its one wait.
+#include "seg_device.h"
+
+namespace tapg {
+
+namespace {
+
+constexpr int kCN = 16;   // node-stages per chunk
+constexpr int kSU = 128;  // padded u-dimension of the segment layout
+constexpr int kSX = 64;   // x rows in LDS (nx <= 64 on this path)
+constexpr int kQU = kCN * kSU / kSegThreads;  // u-elements per thread and chunk
+constexpr int kQX = kCN * kSX / kSegThreads;  // x-elements per thread and chunk
+static_assert(kQU * kSegThreads == kCN * kSU && kQX * kSegThreads == kCN * kSX, "chunk shape");
+
+// v[k] for a runtime k < NB, without dynamic register indexing.
+template <typename T, int NB>
+__device__ __forceinline__ T pick(const T (&v)[NB], int k) {
+  T r = v[0];
+#pragma unroll
+  for (int q = 1; q < NB; ++q) r = k == q ? v[q] : r;
+  return r;
+}
+
+// sum of v[q] over q in [c0, c1), in increasing q.
+template <typename T, int NB>
+__device__ __forceinline__ T range_sum(const T (&v)[NB], int c0, int c1) {
+  T r = T(0);
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    if (q >= c0 && q < c1) r += v[q];
+  return r;
+}
+
+// Layout of a scan launch's dynamic LDS: consecutive arrays, each starting
+// on an 8-byte boundary.  Pointers are formed as offsets from the dynamic LDS
+// base itself, so the compiler keeps them in the LDS address space (a pointer
+// rebuilt from an integer would be a generic one, read with FLAT instructions
+// that also wait for every global load in flight).
+struct LdsCursor {
+  size_t off = 0;
+  __host__ __device__ size_t take(size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 7) & ~(size_t)7;
+    return o;
+  }
+};
+
+template <typename T>
+struct BwdLds {  // a (then lambda), v (then m), G v; ranges; packed children slots
+                 // (two buffers); CSR of B', G and E'
+  size_t lam, v, gv, rg, ch, brow, bcol, bval, grow, gcol, gval, erow, ecol, eval, total;
+  __host__ __device__ explicit BwdLds(const SegArgs<T>& a) {
+    LdsCursor c;
+    lam = c.take(sizeof(T) * kCN * kSX);
+    v = c.take(sizeof(T) * kCN * kSU);
+    gv = c.take(sizeof(T) * kCN * a.ns);
+    rg = c.take(sizeof(int2) * a.nst);
+    ch = c.take(sizeof(int) * 2 * kCN);
+    brow = c.take(sizeof(int) * (a.nu + 1));
+    bcol = c.take(sizeof(int) * a.nnzB);
+    bval = c.take(sizeof(T) * a.nnzB);
+    grow = c.take(sizeof(int) * (a.ns + 1));
+    gcol = c.take(sizeof(int) * a.nnzG);
+    gval = c.take(sizeof(T) * a.nnzG);
+    erow = c.take(sizeof(int) * (a.nu + 1));
+    ecol = c.take(sizeof(int) * a.nnzE);
+    eval = c.take(sizeof(T) * a.nnzE);
+    total = c.off;
+  }
+};
+
+template <typename T>
+struct FwdLds {  // c (then u), d, B u + g (then x); ranges; parent slots; CSR of B
+  size_t c, d, x, rg, par, brow, bcol, bval, total;
+  __host__ __device__ explicit FwdLds(const SegArgs<T>& a) {
+    LdsCursor k;
+    c = k.take(sizeof(T) * kCN * kSU);
+    d = k.take(sizeof(T) * kCN * kSU);
+    x = k.take(sizeof(T) * kCN * kSX);
+    rg = k.take(sizeof(int2) * a.nst);
+    par = k.take(sizeof(int) * kCN);
+    brow = k.take(sizeof(int) * (a.nx + 1));
+    bcol = k.take(sizeof(int) * a.nnzB);
+    bval = k.take(sizeof(T) * a.nnzB);
+    total = k.off;
+  }
+};
+
+template <typename T>
+size_t scan_lds_bytes(const SegArgs<T>& a, bool fwd) {
+  const size_t b = fwd ? FwdLds<T>(a).total : BwdLds<T>(a).total;
+  return (b + 15) & ~(size_t)15;
+}
+
+// One sparse row held in registers, padded to K entries with (column 0,
+// value 0) so that apply() is branch-free: its K reads of X are independent
+// and issue together.  Entries past K (none for the rows of a flow network's
+// incidence and projector at the sizes used) are read from the LDS copy of the
+// CSR.  The products are added in CSR order; a padding term adds exactly 0.
+template <typename T, int K>
+struct FixRow {
+  int col[K];
+  T val[K];
+  int xb, xe;  // LDS range of the entries past K
+  __device__ __forceinline__ void load(const int* srow, const int* scol, const T* sval, int i,
+                                       bool ok) {
+    const int p0 = ok ? srow[i] : 0, p1 = ok ? srow[i + 1] : 0;
+    const int n = min(p1 - p0, K);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      col[k] = k < n ? scol[p0 + k] : 0;
+      val[k] = k < n ? sval[p0 + k] : T(0);
+    }
+    xb = p0 + n;
+    xe = p1;
+  }
+  __device__ __forceinline__ T apply(T acc, const T* X, const int* scol, const T* sval) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc += val[k] * X[col[k]];
+    for (int p = xb; p < xe; ++p) acc += sval[p] * X[scol[p]];
+    return acc;
+  }
+};
+
+// Children slot range (c0, c1) of a node-stage packed into one int.
+__device__ __forceinline__ int pack_ch(int c0, int c1) { return c0 | (c1 << 16); }
+__device__ __forceinline__ int ch_lo(int v) { return v & 0xFFFF; }
+__device__ __forceinline__ int ch_hi(int v) { return v >> 16; }
+
+// ---------------------------------------------------------------------------
+// Backward sweep of workgroup `wg` over its level, stages s_end down to
+// s_begin, in iteration `it` (extrapolation weight beta; scale: 1/|v| in the
+// power iteration, where the data terms are zero).  Writes P_n for every node
+// and lambda_n at the level's first stage (read by the level above).
+// ---------------------------------------------------------------------------
+template <typename T, int NB>
+__device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int it, T beta,
+                                              T scale) {
+  constexpr int CS = kCN / NB;  // stages per chunk
+  const int tid = threadIdx.x;
+  const bool power = a.mode == 1;
+  const T* Yc = (it & 1) ? a.Y1 : a.Y0;
+  const T* Yo = (it & 1) ? a.Y0 : a.Y1;
+  const int nx = a.nx, nu = a.nu, LDX = a.LDX, LDY = a.LDY, ns = a.ns;
+  const int sb = a.s_begin, se = a.s_end;
+  const T hw = T(0.5) * a.winv;  // 1 / (2 w)
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BwdLds<T> L(a);
+  T* sLam = reinterpret_cast<T*>(smem_raw + L.lam);  // [kCN][kSX]: a, then lambda
+  T* sV = reinterpret_cast<T*>(smem_raw + L.v);      // [kCN][kSU]: v, then m
+  T* sGv = reinterpret_cast<T*>(smem_raw + L.gv);    // [kCN][ns]: G v
+  int2* sRg = reinterpret_cast<int2*>(smem_raw + L.rg);  // node range per stage
+  int* sCh = reinterpret_cast<int*>(smem_raw + L.ch);    // [2][kCN]: children slots, by chunk parity
+  int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);  // CSR of B' (nu rows)
+  int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
+  T* sVal = reinterpret_cast<T*>(smem_raw + L.bval);
+  int* gRow = reinterpret_cast<int*>(smem_raw + L.grow);  // CSR of G (ns rows)
+  int* gCol = reinterpret_cast<int*>(smem_raw + L.gcol);
+  T* gVal = reinterpret_cast<T*>(smem_raw + L.gval);
+  int* eRow = reinterpret_cast<int*>(smem_raw + L.erow);  // CSR of E' (nu rows)
+  int* eCol = reinterpret_cast<int*>(smem_raw + L.ecol);
+  T* eVal = reinterpret_cast<T*>(smem_raw + L.eval);
+  const bool kids_below = se + 1 < a.N;
+  int cb = 0, ce = 0;  // children of the level's last stage (in the level below)
+  {
+    const int2* rg = a.ranges + (size_t)wg * a.nst;
+    for (int i = tid; i < a.nst; i += kSegThreads) sRg[i] = rg[i];
+    csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
+    csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, ns, a.nnzG, gRow, gCol, gVal);
+    csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
+    if (kids_below) {
+      const int2 rl = rg[a.nst - 1];
+      cb = a.cbeg[rl.x];
+      ce = a.cend[rl.y - 1];
+    }
+  }
+  __syncthreads();
+
+  // u-elements of a chunk: e = tid + 512 j -> node-stage e / 128, component
+  // e % 128 = tid % 128 for every j; x-elements likewise with 64.
+  const int iu = tid & (kSU - 1);
+  const int ix = tid & (kSX - 1);
+  FixRow<T, 2> btrow, etrow;
+  btrow.load(sRow, sCol, sVal, iu, iu < nu);
+  etrow.load(eRow, eCol, eVal, iu, iu < nu);
+  const bool gfix = kCN * ns <= kSegThreads;  // one row of G per thread
+  FixRow<T, 4> grow;
+  grow.load(gRow, gCol, gVal, ns > 0 ? tid % ns : 0, gfix && tid < kCN * ns);
+
+  // Children of the level's last stage: the level below left their lambda and
+  // P in global memory.  They are staged through LDS kCN at a time (all loads
+  // of a batch in flight together) and summed per slot, in child order, by the
+  // chain threads.
+  T bndL[NB], bndP[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) bndL[b] = bndP[b] = T(0);
+  if (kids_below) {
+    const int lo_l = sRg[a.nst - 1].x;
+    for (int c0 = cb; c0 < ce; c0 += kCN) {
+#pragma unroll
+      for (int j = 0; j < kQX; ++j) {
+        const int e = tid + j * kSegThreads;
+        const int c = c0 + e / kSX;
+        sLam[e] = ldm(a.lam, (size_t)c * LDX + ix, c < ce && ix < nx);
+      }
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) {
+        const int e = tid + j * kSegThreads;
+        const int c = c0 + e / kSU;
+        sV[e] = ldm((const T*)a.jv, (size_t)c * kSU + iu, c < ce && iu < nu);
+      }
+      if (tid < kCN) sCh[tid] = c0 + tid < ce ? a.anc[c0 + tid] - lo_l : -1;
+      __syncthreads();
+      if (tid < kSU) {
+#pragma unroll
+        for (int q = 0; q < kCN; ++q) {
+          const int b = sCh[q];  // slot of child c0 + q (-1: past the last child)
+          const T lv = sLam[q * kSX + ix], pv = sV[q * kSU + iu];
+#pragma unroll
+          for (int bb = 0; bb < NB; ++bb)
+            if (b == bb) {
+              bndL[bb] += lv;
+              bndP[bb] += pv;
+            }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  const int nchunk = (a.nst + CS - 1) / CS;
+  // Inputs of one chunk: per x-element (y1, y1o, y2, y2o), per u-element (y3,
+  // y3o, kappa), per node-stage tid < kCN its children range.
+  struct Pre {
+    T x[kQX][4], u[kQU][3];
+    int c0, c1;
+  };
+  auto chunk_lo = [&](int c) { return max(sb, se - c * CS - CS + 1); };
+  auto chunk_hi = [&](int c) { return se - c * CS; };
+  auto load_chunk = [&](int c, Pre& P) {
+    const int s_lo = chunk_lo(c), s_hi = chunk_hi(c);
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      const int kb = (tid + j * kSegThreads) / kSX;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const size_t o = (size_t)(rr.x + b) * LDY + ix;
+      P.x[j][0] = ldc(Yc, o, ok);
+      P.x[j][1] = ldc(Yo, o, ok);
+      P.x[j][2] = ldc(Yc, o + LDX, ok);
+      P.x[j][3] = ldc(Yo, o + LDX, ok);
+    }
+#pragma unroll
+    for (int j = 0; j < kQU; ++j) {
+      const int kb = (tid + j * kSegThreads) / kSU;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      const size_t n = (size_t)(rr.x + b);
+      P.u[j][0] = ldc(Yc, n * LDY + 2 * LDX + iu, ok);
+      P.u[j][1] = ldc(Yo, n * LDY + 2 * LDX + iu, ok);
+      P.u[j][2] = ldc(a.kappa, n * kSU + iu, ok);
+    }
+    {
+      const int kb = tid < kCN ? tid : 0;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = tid < kCN && s <= s_hi && b < rr.y - rr.x;
+      P.c0 = ldc(a.cbeg, (size_t)(rr.x + b), ok);
+      P.c1 = ldc(a.cend, (size_t)(rr.x + b), ok);
+    }
+  };
+
+  // per chunk, registers of the u-elements: w3 and kappa
+  T w3r[kQU], kr[kQU];
+  // chain state: the neighbouring stage's lambda / P per slot (component ix / iu)
+  T prevL[NB], prevP[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) prevL[b] = prevP[b] = T(0);
+  // delayed stores of P (chain threads): the values of the chunk [ps_lo,
+  // ps_lo + pcs) that precedes the current one (pcs = 0: none)
+  T dP[kCN];
+  int ps_lo = 0, pcs = 0;
+  auto flush = [&]() {
+    if (tid < kSU && iu < nu) {
+#pragma unroll
+      for (int k = 0; k < CS; ++k) {
+        if (k < pcs) {
+          const int2 rr = sRg[ps_lo + k - sb];
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            if (b < rr.y - rr.x) a.jv[(size_t)(rr.x + b) * kSU + iu] = dP[k * NB + b];
+        }
+      }
+    }
+  };
+
+  auto chunk = [&](int c, Pre& C, Pre& Nx) {
+    vm_wait_all();  // this chunk's inputs, the stores issued a chunk ago
+    flush();
+    const int s_lo = chunk_lo(c), s_hi = chunk_hi(c);
+    const int cs = s_hi - s_lo + 1;
+    int* ch = sCh + (c & 1) * kCN;
+    // inputs into LDS (a) and registers (w3, kappa)
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      const int e = tid + j * kSegThreads;
+      const int kb = e / kSX;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const T av = power ? scale * (C.x[j][0] + C.x[j][2])
+                         : wext(C.x[j][0], C.x[j][1], beta) + wext(C.x[j][2], C.x[j][3], beta);
+      sLam[e] = ok ? av : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < kQU; ++j) {
+      const int kb = (tid + j * kSegThreads) / kSU;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      const T w3 = power ? scale * C.u[j][0] : wext(C.u[j][0], C.u[j][1], beta);
+      w3r[j] = ok ? w3 : T(0);
+      kr[j] = ok && !power ? C.u[j][2] : T(0);
+    }
+    if (tid < kCN) {
+      const int kb = tid;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      int r2 = 0;
+      if (s <= s_hi && s < se) {
+        const int2 rr = sRg[s - sb];
+        if (b < rr.y - rr.x) {
+          const int lo_c = sRg[s + 1 - sb].x;
+          r2 = pack_ch(C.c0 - lo_c, C.c1 - lo_c);
+        }
+      }
+      ch[kb] = r2;
+    }
+    // the next chunk's loads fly while this one computes (unconditional: the
+    // last chunk reloads itself)
+    load_chunk(c + 1 < nchunk ? c + 1 : c, Nx);
+    __syncthreads();
+
+    // lambda chain, bottom stage of the chunk first, in registers
+    if (tid < kSX) {
+      T av[kCN];
+      int cr[kCN];
+#pragma unroll
+      for (int q = 0; q < kCN; ++q) {
+        av[q] = sLam[q * kSX + ix];
+        cr[q] = __builtin_amdgcn_readfirstlane(ch[q]);
+      }
+#pragma unroll
+      for (int k = CS - 1; k >= 0; --k) {
+        if (k < cs) {
+          const bool bottom = s_lo + k == se;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int v = cr[k * NB + b];
+            av[k * NB + b] += bottom ? bndL[b] : range_sum<T, NB>(prevL, ch_lo(v), ch_hi(v));
+          }
+#pragma unroll
+          for (int b = 0; b < NB; ++b) prevL[b] = av[k * NB + b];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kCN; ++q) sLam[q * kSX + ix] = av[q];
+      if (s_lo == sb && sb > 0) {  // the level above reads the first stage's lambda
+        const int2 rr = sRg[0];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (b < rr.y - rr.x && ix < nx) a.lam[(size_t)(rr.x + b) * LDX + ix] = av[b];
+      }
+    }
+    __syncthreads();
+    // v = kappa - (w3 + B' lambda) / (2 w), per u-element (all reads first)
+    {
+      T t[kQU];
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) {
+        const int kb = (tid + j * kSegThreads) / kSU;
+        t[j] = btrow.apply(w3r[j], sLam + kb * kSX, sCol, sVal);
+      }
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) {
+        const int e = tid + j * kSegThreads;
+        // invalid slots have w3 = kappa = 0 and lambda = 0
+        sV[e] = e / kSU < cs * NB && iu < nu ? kr[j] - hw * t[j] : T(0);
+      }
+    }
+    __syncthreads();
+    // G v, per (node-stage, row of G)
+    if (gfix) {
+      if (tid < kCN * ns) sGv[tid] = grow.apply(T(0), sV + (tid / ns) * kSU, gCol, gVal);
+    } else {
+      for (int e = tid; e < kCN * ns; e += kSegThreads) {
+        const int kb = e / ns, r = e - kb * ns;
+        const T* v = sV + kb * kSU;
+        T acc = T(0);
+        for (int p = gRow[r]; p < gRow[r + 1]; ++p) acc += gVal[p] * v[gCol[p]];
+        sGv[e] = acc;
+      }
+    }
+    __syncthreads();
+    // m = v - E'(G v) (all reads first)
+    {
+      T m[kQU];
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) {
+        const int e = tid + j * kSegThreads;
+        m[j] = sV[e] - etrow.apply(T(0), sGv + (e / kSU) * ns, eCol, eVal);
+      }
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) sV[tid + j * kSegThreads] = iu < nu ? m[j] : T(0);
+    }
+    __syncthreads();
+    // P chain, bottom stage first, in registers; P goes to global memory one
+    // chunk later
+    if (tid < kSU) {
+      int cr[kCN];
+#pragma unroll
+      for (int q = 0; q < kCN; ++q) {
+        dP[q] = sV[q * kSU + iu];
+        cr[q] = __builtin_amdgcn_readfirstlane(ch[q]);
+      }
+#pragma unroll
+      for (int k = CS - 1; k >= 0; --k) {
+        if (k < cs) {
+          const bool bottom = s_lo + k == se;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int v = cr[k * NB + b];
+            dP[k * NB + b] += bottom ? bndP[b] : range_sum<T, NB>(prevP, ch_lo(v), ch_hi(v));
+          }
+#pragma unroll
+          for (int b = 0; b < NB; ++b) prevP[b] = dP[k * NB + b];
+        }
+      }
+    }
+    ps_lo = s_lo;
+    pcs = cs;
+  };
+
+  Pre PA, PB;
+  load_chunk(0, PA);
+  int c = 0;
+  while (true) {
+    chunk(c, PA, PB);
+    if (++c >= nchunk) break;
+    chunk(c, PB, PA);
+    if (++c >= nchunk) break;
+  }
+  flush();
+}
+
+// ---------------------------------------------------------------------------
+// Forward sweep of workgroup `wg` (tree `tree`) over its level, stages
+// s_begin up to s_end, in iteration `it`, with the fused prox / dual update
+// (as in the segment form).  Returns the workgroup's max |y+ - w| / gamma
+// (power iteration: the sum of squares of its part of the new iterate).
+// ---------------------------------------------------------------------------
+template <typename T, int NB>
+__device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int tree, int it,
+                                                T beta, double gam64, double* sred) {
+  constexpr int CS = kCN / NB;
+  const int tid = threadIdx.x;
+  const bool power = a.mode == 1;
+  const T* Yc = (it & 1) ? a.Y1 : a.Y0;
+  T* Yn = (it & 1) ? a.Y0 : a.Y1;  // y^{nu-1} in, y^{nu+1} out
+  const T gam = (T)gam64;
+  const int nx = a.nx, nu = a.nu, LDX = a.LDX, LDY = a.LDY;
+  const int sb = a.s_begin, se = a.s_end;
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const FwdLds<T> L(a);
+  T* sC = reinterpret_cast<T*>(smem_raw + L.c);  // [kCN][kSU]: j / p, then u
+  T* sD = reinterpret_cast<T*>(smem_raw + L.d);  // [kCN][kSU]: P / p
+  T* sX = reinterpret_cast<T*>(smem_raw + L.x);  // [kCN][kSX]: B u + g, then x
+  int2* sRg = reinterpret_cast<int2*>(smem_raw + L.rg);
+  int* sPar = reinterpret_cast<int*>(smem_raw + L.par);  // [kCN]: parent slot
+  int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);  // CSR of B (nx rows)
+  int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
+  T* sVal = reinterpret_cast<T*>(smem_raw + L.bval);
+  __shared__ T sBnd[5 * kSU];  // gamma-scaled bounds: xmin, xmax, xs | umin, umax
+  int par0, parl;  // parents of the level's first and last first-stage nodes
+  {
+    const int2* rg = a.ranges + (size_t)wg * a.nst;
+    for (int i = tid; i < a.nst; i += kSegThreads) sRg[i] = rg[i];
+    csr_to_lds<T>(a.Brow, a.Bcol, a.Bval, nx, a.nnzB, sRow, sCol, sVal);
+    for (int i = tid; i < kSU; i += kSegThreads) {
+      sBnd[i] = gam * ldm(a.xmin, i, i < nx);
+      sBnd[kSU + i] = gam * ldm(a.xmax, i, i < nx);
+      sBnd[2 * kSU + i] = gam * ldm(a.xs, i, i < nx);
+      sBnd[3 * kSU + i] = gam * ldm(a.umin, i, i < nu);
+      sBnd[4 * kSU + i] = gam * ldm(a.umax, i, i < nu);
+    }
+    const int2 r0 = rg[0];
+    par0 = a.anc[r0.x];
+    parl = a.anc[r0.y - 1];
+  }
+  __syncthreads();
+  const int iu = tid & (kSU - 1);
+  const int ix = tid & (kSX - 1);
+  FixRow<T, 5> brow;
+  brow.load(sRow, sCol, sVal, ix, ix < nx);
+
+  // parents of the level's first stage: the level above left x and z = Pi u in
+  // global memory; at the root they are (p, Pi q) of the tree (zero in the
+  // power iteration)
+  const int lo_p = par0 >= 0 ? par0 : 0;
+  const int np = par0 >= 0 ? parl - par0 + 1 : 1;
+  T xprev[NB], zprev[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const bool okp = par0 >= 0 && b < np;
+    xprev[b] = ldm(a.x, (size_t)(lo_p + b) * LDX + ix, okp && ix < nx);
+    zprev[b] = ldm((const T*)a.zb, (size_t)(lo_p + b) * kSU + iu, okp && iu < nu);
+  }
+  if (par0 < 0 && !power) {
+    xprev[0] = ldm(a.pq + (size_t)tree * a.pq_stride, ix, ix < nx);
+    zprev[0] = ldm(a.zr + (size_t)tree * kSU, iu, iu < nu);
+  }
+  const bool kids_below = se + 1 < a.N;
+
+  const int nchunk = (a.nst + CS - 1) / CS;
+  // Inputs of one chunk: per u-element (P, kperp, 1/p, y3, y3o), per x-element
+  // (g, y1, y1o, y2, y2o), per node-stage tid < kCN its parent.
+  struct Pre {
+    T u[kQU][5], x[kQX][5];
+    int an;
+  };
+  auto load_chunk = [&](int c, Pre& P) {
+    const int s_lo = sb + c * CS, s_hi = min(se, s_lo + CS - 1);
+#pragma unroll
+    for (int j = 0; j < kQU; ++j) {
+      const int kb = (tid + j * kSegThreads) / kSU;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      const size_t n = (size_t)(rr.x + b);
+      P.u[j][0] = ldc((const T*)a.jv, n * kSU + iu, ok);
+      P.u[j][1] = ldc(a.kperp, n * kSU + iu, ok);
+      P.u[j][2] = ldc(a.invp, n, ok);
+      P.u[j][3] = ldc(Yc, n * LDY + 2 * LDX + iu, ok);
+      P.u[j][4] = ldc((const T*)Yn, n * LDY + 2 * LDX + iu, ok);
+    }
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      const int kb = (tid + j * kSegThreads) / kSX;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const size_t n = (size_t)(rr.x + b);
+      P.x[j][0] = ldc(a.g, n * LDX + ix, ok);
+      P.x[j][1] = ldc(Yc, n * LDY + ix, ok);
+      P.x[j][2] = ldc((const T*)Yn, n * LDY + ix, ok);
+      P.x[j][3] = ldc(Yc, n * LDY + LDX + ix, ok);
+      P.x[j][4] = ldc((const T*)Yn, n * LDY + LDX + ix, ok);
+    }
+    {
+      const int kb = tid < kCN ? tid : 0;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = tid < kCN && s <= s_hi && b < rr.y - rr.x;
+      P.an = ldc(a.anc, (size_t)(rr.x + b), ok);
+    }
+  };
+
+  // per chunk, registers of this thread's elements for the prox
+  T w3r[kQU], w1r[kQX], w2r[kQX], gr[kQX];
+  double rmax = 0.0, zsq = 0.0;
+  // delayed stores: u, y3 per u-element; x, y1, y2 per x-element (-1: none)
+  T du[kQU], dy3[kQU], dxv[kQX], dy1[kQX], dy2[kQX];
+  int dnu[kQU], dnx[kQX];
+#pragma unroll
+  for (int j = 0; j < kQU; ++j) dnu[j] = -1;
+#pragma unroll
+  for (int j = 0; j < kQX; ++j) dnx[j] = -1;
+  auto flush = [&]() {
+#pragma unroll
+    for (int j = 0; j < kQU; ++j)
+      if (dnu[j] >= 0) {
+        a.u[(size_t)dnu[j] * kSU + iu] = du[j];
+        Yn[(size_t)dnu[j] * LDY + 2 * LDX + iu] = dy3[j];
+      }
+#pragma unroll
+    for (int j = 0; j < kQX; ++j)
+      if (dnx[j] >= 0) {
+        a.x[(size_t)dnx[j] * LDX + ix] = dxv[j];
+        Yn[(size_t)dnx[j] * LDY + ix] = dy1[j];
+        Yn[(size_t)dnx[j] * LDY + LDX + ix] = dy2[j];
+      }
+  };
+
+  auto chunk = [&](int c, Pre& C, Pre& Nx) {
+    vm_wait_all();
+    flush();
+    const int s_lo = sb + c * CS, s_hi = min(se, s_lo + CS - 1);
+    const int cs = s_hi - s_lo + 1;
+#pragma unroll
+    for (int j = 0; j < kQU; ++j) {
+      const int e = tid + j * kSegThreads;
+      const int kb = e / kSU;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      const T d = C.u[j][0] * C.u[j][2];
+      const T cj = power ? d : (C.u[j][1] + C.u[j][0]) * C.u[j][2];
+      sC[e] = ok ? cj : T(0);
+      sD[e] = ok ? d : T(0);
+      w3r[j] = ok ? wext(C.u[j][3], C.u[j][4], beta) : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      const int kb = (tid + j * kSegThreads) / kSX;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      gr[j] = ok && !power ? C.x[j][0] : T(0);
+      w1r[j] = ok ? wext(C.x[j][1], C.x[j][2], beta) : T(0);
+      w2r[j] = ok ? wext(C.x[j][3], C.x[j][4], beta) : T(0);
+    }
+    if (tid < kCN) {
+      const int kb = tid;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      int pb = 0;
+      if (s <= s_hi) {
+        const int2 rr = sRg[s - sb];
+        const int base = s == sb ? lo_p : sRg[s - 1 - sb].x;
+        if (b < rr.y - rr.x && C.an >= 0) pb = C.an - base;
+      }
+      sPar[kb] = pb;
+    }
+    load_chunk(c + 1 < nchunk ? c + 1 : c, Nx);
+    __syncthreads();
+
+    // u / z chain, top stage first, in registers
+    if (tid < kSU) {
+      T cv[kCN], dv[kCN];
+      int pr[kCN];
+#pragma unroll
+      for (int q = 0; q < kCN; ++q) {
+        cv[q] = sC[q * kSU + iu];
+        dv[q] = sD[q * kSU + iu];
+        pr[q] = __builtin_amdgcn_readfirstlane(sPar[q]);
+      }
+#pragma unroll
+      for (int k = 0; k < CS; ++k) {
+        if (k < cs) {
+          T cur[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const T zp = pick<T, NB>(zprev, pr[k * NB + b]);
+            cv[k * NB + b] += zp;   // u
+            cur[b] = zp + dv[k * NB + b];  // z
+          }
+#pragma unroll
+          for (int b = 0; b < NB; ++b) zprev[b] = cur[b];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kCN; ++q) sC[q * kSU + iu] = cv[q];
+      if (s_hi == se && kids_below) {  // the level below reads z of the last stage
+        const int2 rr = sRg[se - sb];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (b < rr.y - rr.x && iu < nu) a.zb[(size_t)(rr.x + b) * kSU + iu] = zprev[b];
+      }
+    }
+    __syncthreads();
+    // B u + g, per x-element (all reads first)
+    {
+      T v[kQX];
+#pragma unroll
+      for (int j = 0; j < kQX; ++j) {
+        const int kb = (tid + j * kSegThreads) / kSX;
+        v[j] = brow.apply(gr[j], sC + kb * kSU, sCol, sVal);
+      }
+#pragma unroll
+      for (int j = 0; j < kQX; ++j) {
+        const int e = tid + j * kSegThreads;
+        sX[e] = e / kSX < cs * NB && ix < nx ? v[j] : T(0);
+      }
+    }
+    __syncthreads();
+    // x chain, top stage first, in registers
+    if (tid < kSX) {
+      T xv[kCN];
+      int pr[kCN];
+#pragma unroll
+      for (int q = 0; q < kCN; ++q) {
+        xv[q] = sX[q * kSX + ix];
+        pr[q] = __builtin_amdgcn_readfirstlane(sPar[q]);
+      }
+#pragma unroll
+      for (int k = 0; k < CS; ++k) {
+        if (k < cs) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) xv[k * NB + b] += pick<T, NB>(xprev, pr[k * NB + b]);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) xprev[b] = xv[k * NB + b];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kCN; ++q) sX[q * kSX + ix] = xv[q];
+    }
+    __syncthreads();
+
+    // ---- prox / dual update, per element; stores held for the next chunk ----
+#pragma unroll
+    for (int j = 0; j < kQU; ++j) {
+      const int e = tid + j * kSegThreads;
+      const int kb = e / kSU;
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      const T u = sC[e];
+      T y;
+      if (power) {
+        y = -u;
+        if (ok) zsq += (double)u * (double)u;
+      } else {
+        const T w = w3r[j];
+        const T v = w + gam * u;
+        y = v - fmin(fmax(v, sBnd[3 * kSU + iu]), sBnd[4 * kSU + iu]);
+        if (ok) {
+          double d = fabs((double)y - (double)w);
+          if (!(d <= 1.0e308)) d = INFINITY;
+          rmax = fmax(rmax, d);
+        }
+      }
+      du[j] = u;
+      dy3[j] = y;
+      dnu[j] = ok ? rr.x + b : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      const int e = tid + j * kSegThreads;
+      const int kb = e / kSX;  // one node-stage per wave
+      const int s = s_lo + kb / NB, b = kb % NB;
+      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const T xv = sX[e];
+      dxv[j] = xv;
+      dnx[j] = ok ? rr.x + b : -1;
+      if (power) {
+        dy1[j] = -xv;
+        dy2[j] = -xv;
+        if (ok) zsq += 2.0 * (double)xv * (double)xv;
+      } else {
+        const T w1 = w1r[j], w2 = w2r[j];
+        const T v1 = w1 + gam * xv, v2 = w2 + gam * xv;
+        const T r1 = ok ? v1 - fmin(fmax(v1, sBnd[ix]), sBnd[kSU + ix]) : T(0);
+        const T r2 = ok ? v2 - fmax(v2, sBnd[2 * kSU + ix]) : T(0);
+        const double n1 = sqrt(wave_sum((double)r1 * (double)r1));
+        const double n2 = sqrt(wave_sum((double)r2 * (double)r2));
+        const T sc1 = n1 > (double)a.Wx ? (T)((double)a.Wx / n1) : T(1);
+        const T sc2 = n2 > (double)a.Ws ? (T)((double)a.Ws / n2) : T(1);
+        const T y1 = r1 * sc1, y2 = r2 * sc2;
+        dy1[j] = y1;
+        dy2[j] = y2;
+        if (ok) {
+          double d1 = fabs((double)y1 - (double)w1);
+          double d2 = fabs((double)y2 - (double)w2);
+          if (!(d1 <= 1.0e308)) d1 = INFINITY;
+          if (!(d2 <= 1.0e308)) d2 = INFINITY;
+          rmax = fmax(rmax, fmax(d1, d2));
+        }
+      }
+    }
+  };
+
+  Pre PA, PB;
+  load_chunk(0, PA);
+  int c = 0;
+  while (true) {
+    chunk(c, PA, PB);
+    if (++c >= nchunk) break;
+    chunk(c, PB, PA);
+    if (++c >= nchunk) break;
+  }
+  flush();
+  if (power) return block_sum512(zsq, sred);
+  return block_max512(rmax, sred) / gam64;
+}
+
+}  // namespace
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kSegThreads) void scan_bwd_kernel(SegArgs<T> a) {
+  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
+  const DevCtl* ctl = a.ctl + tree;
+  if (ctl->done) return;
+  scan_bwd_body<T, NB>(a, blockIdx.x, ctl->iter, (T)ctl->beta, (T)ctl->pw_scale);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kSegThreads) void scan_fwd_kernel(SegArgs<T> a) {
+  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;
+  DevCtl* ctl = a.ctl + tree;
+  __shared__ double sred[kSegThreads];
+  __shared__ int s_last;
+  if (ctl->done) {  // this tree has stopped; the closing launch still counts it
+    if (a.last_level) seg_iteration_end(a, sred, &s_last);
+    return;
+  }
+  const double m = scan_fwd_body<T, NB>(a, blockIdx.x, tree, ctl->iter, (T)ctl->beta,
+                                        ctl->gamma, sred);
+  if (threadIdx.x == 0) {
+    if (a.mode == 1)
+      a.part[a.part_base + blockIdx.x] = m;
+    else
+      atomicMax(&ctl->res_bits, (unsigned long long)__double_as_longlong(m));
+  }
+  if (a.last_level) seg_iteration_end(a, sred, &s_last);
+}
+
+template <typename T, int NB>
+void launch_scan_nb(bool fwd, const SegArgs<T>& a, int n_wg, hipStream_t st) {
+  const size_t lds = scan_lds_bytes<T>(a, fwd);
+  if (fwd)
+    hipLaunchKernelGGL((scan_fwd_kernel<T, NB>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+  else
+    hipLaunchKernelGGL((scan_bwd_kernel<T, NB>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+}
+
+template <typename T>
+void launch_scan(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st) {
+  switch (nbm) {
+    case 4: launch_scan_nb<T, 4>(fwd, a, n_wg, st); break;
+    case 2: launch_scan_nb<T, 2>(fwd, a, n_wg, st); break;
+    default: launch_scan_nb<T, 1>(fwd, a, n_wg, st); break;
+  }
+}
+
+template <typename T>
+size_t scan_lds(int, const SegArgs<T>& a) {
+  const size_t f = scan_lds_bytes<T>(a, true), b = scan_lds_bytes<T>(a, false);
+  return f > b ? f : b;
+}
+
+template void launch_scan<double>(bool, int, const SegArgs<double>&, int, hipStream_t);
+template void launch_scan<float>(bool, int, const SegArgs<float>&, int, hipStream_t);
+template size_t scan_lds<double>(int, const SegArgs<double>&);
+template size_t scan_lds<float>(int, const SegArgs<float>&);
+
+}  // namespace tapg

@@ -44,6 +44,7 @@ struct DevExtra {
   double *Wu = nullptr;    // nu x nu col-major ld LDU
   double *alpha0 = nullptr, *cE = nullptr;  // LDU
   double *red = nullptr;   // 8 doubles of reduction output
+  double *Gm = nullptr;    // G = (E E')^{-1} E, ns x nu row-major (projector form)
 };
 
 }  // namespace tapg
@@ -82,6 +83,9 @@ struct tapg_solver_s {
   // the sweeps then apply it as (v - E'(G v)) / w when G is sparse
   bool proj = false;
   int nnzG = 0, nnzE = 0;
+  // A = I as well (and nx <= 64): the sweeps run in scan form, the recursions
+  // unrolled into subtree and root-path sums (TAPG_SCAN=0 keeps the segment form)
+  bool scan = false;
   tapg::Mat G;  // (E E')^{-1} E, ns x nu
   size_t lds_limit = 64 * 1024;  // dynamic LDS per workgroup (device attribute)
   // optional per-launch timing of the sweep kernels (HIP events around each

@@ -213,6 +213,7 @@ size_t seg_lds_probe(tapg_solver_s* S, int nbm, int nst, int nch) {
   probe.ns = S->net.ns;
   probe.nnzG = S->nnzG;
   probe.nnzE = S->nnzE;
+  probe.scan = S->scan ? 1 : 0;
   return seg_lds<T>(nbm, probe);
 }
 
@@ -251,6 +252,10 @@ SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mod
   a.Etcol = d.Etcol;
   a.Etval = d.Etval;
   a.winv = (T)(1.0 / S->wu);
+  a.scan = S->scan ? 1 : 0;
+  a.kperp = static_cast<const T*>(sl.d_kperp);
+  a.zb = static_cast<T*>(sl.d_zb);
+  a.zr = static_cast<const T*>(sl.d_zr);
   a.Wu = d.Wu;
   a.A = d.A;
   a.At = d.At;
@@ -399,7 +404,8 @@ bool chain_usable(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
   const char* env = std::getenv("TAPG_CHAIN");
   if (!(env && env[0] == '1')) return false;
   const int nl = (int)sl.levels.size();
-  if (t.ntrees != 1 || !sl.segmented || !S->proj || nl < 1 || nl > kChainMaxLevels) return false;
+  if (t.ntrees != 1 || !sl.segmented || !S->proj || S->scan || nl < 1 || nl > kChainMaxLevels)
+    return false;
   int total = 0, nbm = 1;
   for (const Slot::Level& L : sl.levels) {
     total += L.n_wg;
@@ -497,6 +503,51 @@ void chain_run(tapg_solver_s* S, Slot& sl, int iters, bool timed) {
   if (timed) TAPG_HIP(hipEventRecord(S->tev[1], st));
 }
 
+// (p, q) of every tree of a slot (FP64 and sweep precision) and, for the scan
+// form, Pi q per tree (the root's parent term z = Pi u_prev), formed on the
+// host in FP64 from G = (E E')^{-1} E.
+template <typename T>
+void upload_pq(tapg_solver_s* S, Slot& sl, const std::vector<double>& pq64, hipStream_t st) {
+  std::vector<T> pqT(pq64.begin(), pq64.end());
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  if (!S->scan) return;
+  const NetworkHost& h = S->net;
+  const int LDX = S->LDX, LDU = S->LDU, PQ = LDX + LDU;
+  const int nt = (int)(pq64.size() / PQ);
+  std::vector<T> zr((size_t)nt * LDU, T(0));
+  std::vector<double> gq(h.ns);
+  for (int k = 0; k < nt; ++k) {
+    const double* q = pq64.data() + (size_t)k * PQ + LDX;
+    for (int r = 0; r < h.ns; ++r) {
+      double acc = 0.0;
+      for (int i = 0; i < h.nu; ++i) acc += S->G(r, i) * q[i];
+      gq[r] = acc;
+    }
+    for (int i = 0; i < h.nu; ++i) {
+      double acc = 0.0;
+      for (int r = 0; r < h.ns; ++r) acc += h.E(r, i) * gq[r];
+      zr[(size_t)k * LDU + i] = (T)(q[i] - acc);
+    }
+  }
+  TAPG_HIP(hipMemcpyAsync(sl.d_zr, zr.data(), zr.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+// Per-solve data step of a slot's K nodes (kappa, g; kperp for the scan form).
+template <typename T>
+void data_step(tapg_solver_s* S, Slot& sl, int K, hipStream_t st) {
+  const NetworkHost& h = S->net;
+  launch_data_step<T>(K, h.nx, h.nu, h.nd, S->LDX, S->LDU, (const int*)sl.d_stage,
+                      (const double*)sl.d_prob64, (const double*)sl.d_demand,
+                      (const double*)sl.d_price, (const double*)S->dx.Pd,
+                      (const double*)S->dx.Gd, (const double*)S->dx.Gbar,
+                      (const double*)S->d64.F, (const double*)S->dx.alpha0,
+                      (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
+                      static_cast<T*>(sl.d_g), h.ns, (const double*)S->dx.Gm,
+                      (const double*)S->dx.E, S->scan ? static_cast<T*>(sl.d_kperp) : nullptr,
+                      st);
+}
+
 template <typename T>
 void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
                 const double* q, bool warm, double gamma, tapg_result& res) {
@@ -508,9 +559,7 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   std::vector<double> pq64(LDX + LDU, 0.0);
   for (int i = 0; i < h.nx; ++i) pq64[i] = p[i];
   for (int i = 0; i < h.nu; ++i) pq64[LDX + i] = q[i];
-  std::vector<T> pqT(pq64.begin(), pq64.end());
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  upload_pq<T>(S, sl, pq64, st);
   // control block
   DevCtl c{};
   c.max_iter = S->cfg.max_iter;
@@ -532,13 +581,7 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   }
   TAPG_HIP(hipEventRecord(S->ev0, st));
   // data step
-  launch_data_step<T>(K, h.nx, h.nu, h.nd, LDX, LDU, (const int*)sl.d_stage,
-                      (const double*)sl.d_prob64, (const double*)sl.d_demand,
-                      (const double*)sl.d_price, (const double*)S->dx.Pd,
-                      (const double*)S->dx.Gd, (const double*)S->dx.Gbar,
-                      (const double*)S->d64.F, (const double*)S->dx.alpha0,
-                      (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
-                      static_cast<T*>(sl.d_g), st);
+  data_step<T>(S, sl, K, st);
   TAPG_HIP(hipGetLastError());
   // iterations, in chunks of check_every with a host check between chunks
   const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
@@ -745,6 +788,8 @@ void dev_init(tapg_solver_s* S) {
         S->nnzE = nnzE;
       }
     }
+    const char* se = std::getenv("TAPG_SCAN");
+    S->scan = S->proj && ai && h.nx <= 64 && !(se && se[0] == '0');
   }
   if (S->stream == nullptr) {
     TAPG_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
@@ -759,6 +804,7 @@ void dev_init(tapg_solver_s* S) {
   S->dx.Gd = upload(colmajor<double>(h.Gd, S->LDX, false), st);
   S->dx.Pd = upload(colmajor<double>(h.Pd, S->LDU, false), st);
   S->dx.E = upload(h.E.a.empty() ? std::vector<double>(1, 0.0) : h.E.a, st);
+  if (S->proj) S->dx.Gm = upload(S->G.a.empty() ? std::vector<double>(1, 0.0) : S->G.a, st);
   S->dx.Ed = upload(h.Ed.a.empty() ? std::vector<double>(1, 0.0) : h.Ed.a, st);
   S->dx.Wu = upload(colmajor<double>(Mat::from(S->Wu.data(), h.nu, h.nu), S->LDU, false), st);
   S->dx.alpha0 = upload(padvec<double>(S->alpha0, S->LDU), st);
@@ -777,6 +823,7 @@ void dev_free_slot(Slot& sl) {
   dfree(sl.d_kappa); dfree(sl.d_g); dfree(sl.d_pq); dfree(sl.d_pq64);
   dfree(sl.d_P0); dfree(sl.d_P1);
   dfree(sl.d_Y0); dfree(sl.d_Y1); dfree(sl.d_lam); dfree(sl.d_j); dfree(sl.d_u); dfree(sl.d_x);
+  dfree(sl.d_kperp); dfree(sl.d_zb); dfree(sl.d_zr);
   dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part); dfree(sl.d_counter);
   free_chain(sl);
   for (auto& L : sl.levels) {
@@ -800,6 +847,7 @@ void dev_release(tapg_solver_s* S) {
   free_net(S->d64);
   free_net(S->d32);
   dfree(S->dx.Gd); dfree(S->dx.Pd); dfree(S->dx.Gbar); dfree(S->dx.E); dfree(S->dx.Ed);
+  dfree(S->dx.Gm);
   dfree(S->dx.Wu); dfree(S->dx.alpha0); dfree(S->dx.cE); dfree(S->dx.red);
   dfree(S->d_fid);
   for (hipEvent_t e : S->tev) (void)hipEventDestroy(e);
@@ -1015,6 +1063,11 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       sl.d_Y1 = dalloc((size_t)K * LDY);
       sl.d_lam = dalloc((size_t)K * LDX);
       sl.d_j = dalloc((size_t)K * LDU);
+      if (S->scan) {
+        sl.d_kperp = dalloc((size_t)K * LDU);
+        sl.d_zb = dalloc((size_t)K * LDU);
+        sl.d_zr = dalloc((size_t)t.ntrees * LDU);
+      }
       sl.d_u = dalloc((size_t)K * LDU);
       sl.d_x = dalloc((size_t)K * LDX);
       sl.d_ctl = dmalloc<DevCtl>(t.ntrees);
@@ -1137,13 +1190,7 @@ void run_chunk(tapg_solver_s* S, Slot& sl, int chunk) {
 template <typename T>
 void forest_data_step(tapg_solver_s* S, const TreeHost& f, Slot& sl) {
   const NetworkHost& h = S->net;
-  launch_data_step<T>(f.K, h.nx, h.nu, h.nd, S->LDX, S->LDU, (const int*)sl.d_stage,
-                      (const double*)sl.d_prob64, (const double*)sl.d_demand,
-                      (const double*)sl.d_price, (const double*)S->dx.Pd,
-                      (const double*)S->dx.Gd, (const double*)S->dx.Gbar,
-                      (const double*)S->d64.F, (const double*)S->dx.alpha0,
-                      (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
-                      static_cast<T*>(sl.d_g), S->stream);
+  data_step<T>(S, sl, f.K, S->stream);
   TAPG_HIP(hipGetLastError());
 }
 
@@ -1192,9 +1239,7 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
     c[k].theta_prev = 1.0;
     c[k].beta = 0.0;
   }
-  std::vector<T> pqT(pq64.begin(), pq64.end());
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  upload_pq<T>(S, sl, pq64, st);
   TAPG_HIP(hipMemcpyAsync(sl.d_ctl, c.data(), c.size() * sizeof(DevCtl), hipMemcpyHostToDevice, st));
   // dual start: zero, then the warm trees' latest duals into both buffers
   const size_t ybytes = (size_t)f.K * LDY * sizeof(T);
@@ -1209,13 +1254,7 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
   }
   TAPG_HIP(hipGetLastError());
   TAPG_HIP(hipEventRecord(S->ev0, st));
-  launch_data_step<T>(f.K, h.nx, h.nu, h.nd, LDX, LDU, (const int*)sl.d_stage,
-                      (const double*)sl.d_prob64, (const double*)sl.d_demand,
-                      (const double*)sl.d_price, (const double*)S->dx.Pd,
-                      (const double*)S->dx.Gd, (const double*)S->dx.Gbar,
-                      (const double*)S->d64.F, (const double*)S->dx.alpha0,
-                      (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
-                      static_cast<T*>(sl.d_g), st);
+  data_step<T>(S, sl, f.K, st);
   TAPG_HIP(hipGetLastError());
   // iterations in graph chunks until every tree has stopped
   const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
@@ -1377,9 +1416,7 @@ void live_enter_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
     c[k] = js[k]->ctl;
     js[k]->it0 = c[k].iter;
   }
-  std::vector<T> pqT(pq64.begin(), pq64.end());
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  upload_pq<T>(S, sl, pq64, st);
   TAPG_HIP(hipMemcpyAsync(sl.d_ctl, c.data(), c.size() * sizeof(DevCtl), hipMemcpyHostToDevice, st));
   for (int k = 0; k < nt; ++k) {  // both dual buffers, as the tree left them
     const int* idx = B.d_map + B.map_off[k];
@@ -1516,9 +1553,7 @@ double time_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
     c[k].theta = c[k].theta_prev = 1.0;
   }
   std::vector<double> pq64((size_t)nt * PQ, 0.0);
-  std::vector<T> pqT(pq64.size(), T(0));
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq64, pq64.data(), pq64.size() * 8, hipMemcpyHostToDevice, st));
-  TAPG_HIP(hipMemcpyAsync(sl.d_pq, pqT.data(), pqT.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  upload_pq<T>(S, sl, pq64, st);
   const size_t yb = (size_t)t.K * S->LDY * sizeof(T);
   TAPG_HIP(hipMemsetAsync(sl.d_Y0, 0, yb, st));
   TAPG_HIP(hipMemsetAsync(sl.d_Y1, 0, yb, st));

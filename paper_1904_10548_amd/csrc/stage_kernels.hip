@@ -419,18 +419,23 @@ __global__ __launch_bounds__(kThreads) void power_end_kernel(DevCtl* c, const do
 // ---------------------------------------------------------------------------
 // Per-solve data step (FP64), one block per node:
 //   ubar_n = -E^+ Ed d_n,  c_n = W_alpha (alpha0 + pi_n c_E),
-//   kappa_n = p_n (Gammabar_s ubar_n - Fbar_s c_n / 2),  g_n = Gd d_n.
+//   kappa_n = p_n (Gammabar_s ubar_n - Fbar_s c_n / 2),  g_n = Gd d_n,
+// and, for the scan form of the sweeps (kperp != nullptr), the part of kappa_n
+// outside the range of Pi:  kperp_n = kappa_n - Pi kappa_n = E'(G kappa_n)
+// with G = (E E')^{-1} E (Gm, ns x nu row-major; E row-major).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void data_step_kernel(
     int nx, int nu, int nd, int LDX, int LDU, const int* stage, const double* prob,
     const double* demand, const double* price, const double* Pd, const double* Gd,
     const double* Gbar, const double* Fbar, const double* alpha0, const double* cE,
-    double W_alpha, T* kappa, T* g) {
+    double W_alpha, T* kappa, T* g, int ns, const double* Gm, const double* E, T* kperp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sD = reinterpret_cast<double*>(smem_raw);
   double* sUb = sD + nd;
   double* sC = sUb + LDU;
+  double* sK = sC + LDU;   // kappa_n in FP64 (scan form only)
+  double* sGk = sK + LDU;  // G kappa_n
   const int n = blockIdx.x;
   const int s = stage[n];
   for (int k = threadIdx.x; k < nd; k += kThreads) sD[k] = demand[(size_t)n * nd + k];
@@ -452,7 +457,23 @@ __global__ __launch_bounds__(kThreads) void data_step_kernel(
       gu += Gs[(size_t)k * LDU + r] * sUb[k];
       fc += Fs[(size_t)k * LDU + r] * sC[k];
     }
-    kappa[(size_t)n * LDU + r] = (T)(pn * (gu - 0.5 * fc));
+    const double kv = pn * (gu - 0.5 * fc);
+    kappa[(size_t)n * LDU + r] = (T)kv;
+    if (kperp) sK[r] = kv;
+  }
+  if (kperp) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < ns; k += kThreads) {
+      double acc = 0.0;
+      for (int r = 0; r < nu; ++r) acc += Gm[(size_t)k * nu + r] * sK[r];
+      sGk[k] = acc;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nu; r += kThreads) {
+      double acc = 0.0;
+      for (int k = 0; k < ns; ++k) acc += E[(size_t)k * nu + r] * sGk[k];
+      kperp[(size_t)n * LDU + r] = (T)acc;
+    }
   }
   for (int r = threadIdx.x; r < nx; r += kThreads) {
     double gg = 0.0;
@@ -676,11 +697,11 @@ void launch_data_step(int K, int nx, int nu, int nd, int LDX, int LDU, const int
                       const double* prob, const double* demand, const double* price,
                       const double* Pd, const double* Gd, const double* Gbar, const double* Fbar,
                       const double* alpha0, const double* cE, double W_alpha, T* kappa, T* g,
-                      hipStream_t st) {
-  const size_t lds = (size_t)(nd + 2 * LDU) * sizeof(double);
+                      int ns, const double* Gm, const double* E, T* kperp, hipStream_t st) {
+  const size_t lds = (size_t)(nd + 3 * LDU + ns) * sizeof(double);
   hipLaunchKernelGGL((data_step_kernel<T>), dim3(K), dim3(kThreads), lds, st, nx, nu, nd, LDX,
                      LDU, stage, prob, demand, price, Pd, Gd, Gbar, Fbar, alpha0, cE, W_alpha,
-                     kappa, g);
+                     kappa, g, ns, Gm, E, kperp);
 }
 
 template <typename T>
@@ -723,8 +744,8 @@ template void launch_copy_rows<float>(const float*, int, float*, int, const int*
   template void launch_data_step<T>(int, int, int, int, int, int, const int*, const double*, \
                                     const double*, const double*, const double*,             \
                                     const double*, const double*, const double*,             \
-                                    const double*, const double*, double, T*, T*,            \
-                                    hipStream_t);                                            \
+                                    const double*, const double*, double, T*, T*, int,       \
+                                    const double*, const double*, T*, hipStream_t);          \
   template void launch_cost<T>(int, int, int, int, int, int, int, const int*, const double*, \
                                const double*, const double*, const T*, const T*,             \
                                const double*, const double*, const double*, const double*,   \

@@ -26,7 +26,7 @@ SHAPES = [(2, 4), (3, 3), ("irregular", 3, 20), (1, 1), (2, 8)]
 
 @pytest.fixture(autouse=True)
 def _default_schedule():
-    for k in ("TAPG_LEVELS", "TAPG_PROJ", "TAPG_CHAIN"):
+    for k in ("TAPG_LEVELS", "TAPG_PROJ", "TAPG_CHAIN", "TAPG_SCAN"):
         os.environ.pop(k, None)
     os.environ["TAPG_USE_GRAPH"] = "1"
     os.environ["TAPG_SEGMENTS"] = "1"
