@@ -164,6 +164,11 @@ struct Slot {
     int* d_wgtree;  // tree of each workgroup (forests only)
   };
   std::vector<Level> levels;
+  // Scan form: the forward sweep in one launch over stages 0..N-1, with the
+  // workgroups of the bottom level, each also walking its nodes' ancestors;
+  // d_own: per workgroup and stage, the first node it owns (writes)
+  Level fwd_full{0, -1, 0, 1, 0, nullptr, nullptr};
+  int* d_own = nullptr;
   std::vector<LevelPlan> plans;  // the plan the levels were built from
   bool segmented = false;
   int part_total = 0;

@@ -115,6 +115,10 @@ struct SegArgs {
   const T* kperp;
   T* zb;
   const T* zr;  // Pi q of each tree (the root's parent input), LDU apart
+  // forward launch over every stage (scan form): per workgroup and stage the
+  // first node the workgroup owns; nodes before it (ancestors shared with a
+  // lower-numbered workgroup) are computed but not written (nullptr: all owned)
+  const int* own;
 };
 
 // Persistent iteration of one tree: every workgroup of every level in one

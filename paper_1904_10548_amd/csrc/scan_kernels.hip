@@ -97,14 +97,16 @@ struct BwdLds {  // a (then lambda), v (then m), G v; ranges; packed children sl
 };
 
 template <typename T>
-struct FwdLds {  // c (then u), d, B u + g (then x); ranges; parent slots; CSR of B
-  size_t c, d, x, rg, par, brow, bcol, bval, total;
+struct FwdLds {  // c (then u), d, B u + g (then x); ranges; first owned node per
+                 // stage; parent slots; CSR of B
+  size_t c, d, x, rg, own, par, brow, bcol, bval, total;
   __host__ __device__ explicit FwdLds(const SegArgs<T>& a) {
     LdsCursor k;
     c = k.take(sizeof(T) * kCN * kSU);
     d = k.take(sizeof(T) * kCN * kSU);
     x = k.take(sizeof(T) * kCN * kSX);
     rg = k.take(sizeof(int2) * a.nst);
+    own = k.take(sizeof(int) * a.nst);
     par = k.take(sizeof(int) * kCN);
     brow = k.take(sizeof(int) * (a.nx + 1));
     bcol = k.take(sizeof(int) * a.nnzB);
@@ -506,6 +508,7 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
   T* sD = reinterpret_cast<T*>(smem_raw + L.d);  // [kCN][kSU]: P / p
   T* sX = reinterpret_cast<T*>(smem_raw + L.x);  // [kCN][kSX]: B u + g, then x
   int2* sRg = reinterpret_cast<int2*>(smem_raw + L.rg);
+  int* sOwn = reinterpret_cast<int*>(smem_raw + L.own);  // first node written, per stage
   int* sPar = reinterpret_cast<int*>(smem_raw + L.par);  // [kCN]: parent slot
   int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);  // CSR of B (nx rows)
   int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
@@ -514,7 +517,10 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
   int par0, parl;  // parents of the level's first and last first-stage nodes
   {
     const int2* rg = a.ranges + (size_t)wg * a.nst;
-    for (int i = tid; i < a.nst; i += kSegThreads) sRg[i] = rg[i];
+    for (int i = tid; i < a.nst; i += kSegThreads) {
+      sRg[i] = rg[i];
+      sOwn[i] = a.own ? a.own[(size_t)wg * a.nst + i] : 0;
+    }
     csr_to_lds<T>(a.Brow, a.Bcol, a.Bval, nx, a.nnzB, sRow, sCol, sVal);
     for (int i = tid; i < kSU; i += kSegThreads) {
       sBnd[i] = gam * ldm(a.xmin, i, i < nx);
@@ -742,7 +748,10 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
       const int kb = e / kSU;
       const int s = s_lo + kb / NB, b = kb % NB;
       const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      // owned: written and counted here (an ancestor shared with a
+      // lower-numbered workgroup is computed by both, written by that one)
+      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu &&
+                      rr.x + b >= sOwn[(s <= s_hi ? s : s_lo) - sb];
       const T u = sC[e];
       T y;
       if (power) {
@@ -768,7 +777,8 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
       const int kb = e / kSX;  // one node-stage per wave
       const int s = s_lo + kb / NB, b = kb % NB;
       const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const bool valid = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const bool ok = valid && rr.x + b >= sOwn[(s <= s_hi ? s : s_lo) - sb];  // owned
       const T xv = sX[e];
       dxv[j] = xv;
       dnx[j] = ok ? rr.x + b : -1;
@@ -779,8 +789,8 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
       } else {
         const T w1 = w1r[j], w2 = w2r[j];
         const T v1 = w1 + gam * xv, v2 = w2 + gam * xv;
-        const T r1 = ok ? v1 - fmin(fmax(v1, sBnd[ix]), sBnd[kSU + ix]) : T(0);
-        const T r2 = ok ? v2 - fmax(v2, sBnd[2 * kSU + ix]) : T(0);
+        const T r1 = valid ? v1 - fmin(fmax(v1, sBnd[ix]), sBnd[kSU + ix]) : T(0);
+        const T r2 = valid ? v2 - fmax(v2, sBnd[2 * kSU + ix]) : T(0);
         const double n1 = sqrt(wave_sum((double)r1 * (double)r1));
         const double n2 = sqrt(wave_sum((double)r2 * (double)r2));
         const T sc1 = n1 > (double)a.Wx ? (T)((double)a.Wx / n1) : T(1);

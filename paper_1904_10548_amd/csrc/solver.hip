@@ -312,9 +312,10 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
         bases[l] = base;
         base += sl.levels[l].n_wg;
       }
-      for (int q = 0; q < nl; ++q) {
+      const bool full = pass == 1 && sl.fwd_full.n_wg > 0;
+      for (int q = 0; q < (full ? 1 : nl); ++q) {
         const int l = pass == 0 ? nl - 1 - q : q;
-        const Slot::Level& L = sl.levels[l];
+        const Slot::Level& L = full ? sl.fwd_full : sl.levels[l];
         a.s_begin = L.s_begin;
         a.s_end = L.s_end;
         a.nst = L.s_end - L.s_begin + 1;
@@ -322,7 +323,12 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
         a.wgtree = L.d_wgtree;
         a.part_base = bases[l];
         a.nch = L.nch;
-        a.last_level = (pass == 1 && l == nl - 1) ? 1 : 0;
+        a.last_level = (pass == 1 && (full || l == nl - 1)) ? 1 : 0;
+        a.own = full ? sl.d_own : nullptr;
+        if (full) {
+          a.part_base = 0;
+          a.part_total = L.n_wg;
+        }
         if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
         launch_seg<T>(pass == 1, L.nbm, a, L.n_wg, st);
         if (tc) {
@@ -374,7 +380,9 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
 }
 
 static int launches_per_iter(const Slot& sl) {
-  return sl.segmented ? 2 * (int)sl.levels.size() : 2 * sl.N + 1;
+  if (sl.segmented)
+    return (int)sl.levels.size() + (sl.fwd_full.n_wg > 0 ? 1 : (int)sl.levels.size());
+  return 2 * sl.N + 1;
 }
 
 template <typename T>
@@ -815,6 +823,14 @@ void dev_init(tapg_solver_s* S) {
 
 void free_chain(Slot& sl);
 
+void free_fwd_full(Slot& sl) {
+  dfree(sl.fwd_full.d_ranges);
+  dfree(sl.fwd_full.d_wgtree);
+  dfree(sl.d_own);
+  sl.fwd_full = Slot::Level{0, -1, 0, 1, 0, nullptr, nullptr};
+  sl.d_own = nullptr;
+}
+
 void dev_free_slot(Slot& sl) {
   if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
   sl.graph = nullptr;
@@ -831,6 +847,7 @@ void dev_free_slot(Slot& sl) {
     dfree(L.d_wgtree);
   }
   sl.levels.clear();
+  free_fwd_full(sl);
 }
 
 void dev_release(tapg_solver_s* S) {
@@ -953,6 +970,59 @@ void free_chain(Slot& sl) {
 }
 
 // (Re)build the level launches of a slot from a plan.
+// The scan form's forward launch: the bottom level's workgroups, each given
+// the ancestors of its nodes at every stage above the level (a contiguous
+// range no wider than the one below, by the breadth-first numbering), and the
+// first node it owns per stage (the nodes past the previous workgroup's range).
+void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPlan& B) {
+  hipStream_t st = S->stream;
+  int wmax = 0;
+  const std::vector<std::pair<int, int>> rp = level_ranges(t, B, wmax);
+  const int N = t.N, nstB = B.s_end - B.s_begin + 1, nw = B.n_wg;
+  std::vector<int2> rg((size_t)nw * N);
+  std::vector<int> own((size_t)nw * N);
+  for (int w = 0; w < nw; ++w) {
+    for (int s = B.s_begin; s < N; ++s) {
+      const auto& q = rp[(size_t)w * nstB + (s - B.s_begin)];
+      rg[(size_t)w * N + s] = make_int2(q.first, q.second);
+    }
+    for (int s = B.s_begin - 1; s >= 0; --s) {
+      const int2 c = rg[(size_t)w * N + s + 1];
+      rg[(size_t)w * N + s] = make_int2(t.anc[c.x], t.anc[c.y - 1] + 1);
+    }
+  }
+  for (int s = 0; s < N; ++s)
+    for (int w = 0; w < nw; ++w) {
+      const int2 r = rg[(size_t)w * N + s];
+      own[(size_t)w * N + s] = w == 0 ? r.x : std::max(r.x, rg[(size_t)(w - 1) * N + s].y);
+    }
+  Slot::Level L{0, N - 1, nw, nb_template(wmax), 0, nullptr, nullptr};
+  const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, N, 0)
+                             : seg_lds_probe<double>(S, L.nbm, N, 0);
+  if (lds + kSegStaticLds > S->lds_limit)
+    throw Fail{TAPG_EINVAL, "forward launch needs " + std::to_string(lds) + " bytes of LDS"};
+  try {
+    L.d_ranges = upload(rg, st);
+    sl.d_own = upload(own, st);
+    if (t.ntrees > 1) {
+      std::vector<int> wt(nw, 0);
+      for (int w = 0; w < nw; ++w) {
+        const int n0 = rg[(size_t)w * N].x;  // the root of the workgroup's tree
+        int k = 0;
+        while (k + 1 < t.ntrees && t.seg_begin(0, k + 1) <= n0) ++k;
+        wt[w] = k;
+      }
+      L.d_wgtree = upload(wt, st);
+    }
+  } catch (...) {
+    dfree(L.d_ranges);
+    dfree(sl.d_own);
+    sl.d_own = nullptr;
+    throw;
+  }
+  sl.fwd_full = L;
+}
+
 void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vector<LevelPlan>& plans) {
   hipStream_t st = S->stream;
   const int nbmax = kSegNbMax;
@@ -1009,6 +1079,8 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
   }
   sl.levels = std::move(levels);
   sl.plans = plans;
+  free_fwd_full(sl);
+  if (S->scan) build_fwd_full(S, t, sl, plans.back());
   free_chain(sl);
   sl.part_total = ptot;
   sl.segmented = true;
