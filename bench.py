@@ -33,27 +33,42 @@ METRIC = "APG solves/sec and p50/p99 solve latency at fixed dual tolerance, 1 MI
 HBM_PEAK_GBS = 8000.0
 
 
-def sweep_bytes(nx, nu, elem, K, n_blocks, kind):
+def sweep_bytes(nx, nu, elem, K, n_blocks, kind, form):
     """Algorithmic HBM bytes of one sweep direction over one iteration.
 
-    Backward, per node: y and y_prev (2 (2nx+nu)), kappa (nu) read, j (nu)
-    written.  Forward, per node: j (nu), 1/p, g (nx), y and y_prev read,
-    u (nu), x (nx) and y_next (2nx+nu) written.  Children and parents inside
-    a workgroup's subtree stay on chip.  Each distinct stage-factor block
-    (nu^2) is read once (stages with equal factors share a block)."""
+    Backward, per node: y and y_prev (2 (2nx+nu)), kappa (nu) read, j (P in
+    the scan form, nu) written.  Forward, per node: j (nu), 1/p, g (nx), y and
+    y_prev read, u (nu), x (nx) and y_next (2nx+nu) written; the scan form
+    also reads kappa - Pi kappa (nu).  Children and parents inside a
+    workgroup's subtree stay on chip (the scan form's forward launch re-reads
+    the ancestors of a workgroup's nodes: not counted).  With the stage
+    factors in registers each distinct block (nu^2) is read once; the
+    projector and scan forms read only the small CSRs of G and E'."""
     if kind == "bwd":
         per_node = 4 * nx + 4 * nu
     else:
-        per_node = 8 * nx + 5 * nu + 1
-    return (per_node * K + n_blocks * nu * nu) * elem
+        per_node = 8 * nx + (6 if form == "scan" else 5) * nu + 1
+    factors = n_blocks * nu * nu if form == "segment" else 0
+    return (per_node * K + factors) * elem
 
 
-def measured_traffic(workload, precision):
+KERNEL_SOURCES = ("paper_1904_10548_amd/csrc/segment_kernels.hip",
+                  "paper_1904_10548_amd/csrc/scan_kernels.hip",
+                  "paper_1904_10548_amd/csrc/seg_device.h",
+                  "paper_1904_10548_amd/csrc/kernels.h")
+
+
+def kernel_prefix(form):
+    return "scan" if form == "scan" else "seg"
+
+
+def measured_traffic(workload, precision, form):
     """HBM bytes per launch of each sweep kind from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, if it was taken on this workload with the
-    current kernel sources (else None)."""
+    WRITE_SIZE counter summary, if it was taken on this workload and sweep
+    form with the current kernel sources (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"seg_sweeps_{workload}_{precision}_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles",
+                        f"{kernel_prefix(form)}_sweeps_{workload}_{precision}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     line = next((l for l in open(path) if l.startswith("traffic-json:")), None)
@@ -61,7 +76,7 @@ def measured_traffic(workload, precision):
         return None
     data = json.loads(line.split(":", 1)[1])
     sha = hashlib.sha256()
-    for f in ("paper_1904_10548_amd/csrc/segment_kernels.hip", "paper_1904_10548_amd/csrc/kernels.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             sha.update(fh.read())
     if data.get("kernel_sources_sha256") != sha.hexdigest():
@@ -82,6 +97,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the planner's schedule and the default sweep form (profiling runs)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests/s")
     ap.add_argument("--requests", type=int, default=400, help="serve: timed requests")
     ap.add_argument("--sessions", type=int, default=32, help="serve: sessions (one tree each)")
@@ -127,8 +144,16 @@ def main():
     t0 = time.perf_counter()
     L = tapg.tapg_estimate_lipschitz(S.h, tree, 100)
     lipschitz_s = time.perf_counter() - t0
+    # schedule and sweep form picked by the autotuner (setup, not timed)
+    t0 = time.perf_counter()
+    tune_ms, tune_nc = (None, 0) if args.no_autotune else tapg.tapg_autotune(S.h, [tree], 20)
+    tune_s = time.perf_counter() - t0
+    if args.no_autotune:
+        S.solve(tree, P.p, P.q)  # the slot exists once solved
+    form, n_bwd = tapg.tapg_sweep_form(S.h, [tree])
     print(f"[bench] {args.config} K={P.tree.K} L={L:.6g} factor {factor_s:.3f}s "
-          f"power {lipschitz_s:.3f}s", file=sys.stderr, flush=True)
+          f"power {lipschitz_s:.3f}s autotune {tune_s:.3f}s: {form} form, {n_bwd} backward "
+          f"launches, {tune_ms} ms/iter", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         st, u0, res = S.solve(tree, P.p, P.q)
@@ -165,20 +190,20 @@ def main():
         kinds = {}
         for kind in ("bwd", "fwd"):
             ms, n = kt[kind]
-            b_iter = sweep_bytes(net.nx, net.nu, elem, P.tree.K, n_blocks, kind)
+            b_iter = sweep_bytes(net.nx, net.nu, elem, P.tree.K, n_blocks, kind, form)
             its = iters  # one timed solve of the same workload
             kinds[kind] = dict(ms=ms, launches=n, bytes=b_iter * its, avg_us=1e3 * ms / max(n, 1))
         dom = max(kinds, key=lambda k: kinds[k]["ms"])
         d = kinds[dom]
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        tb = measured_traffic(args.config, args.precision)
+        tb = measured_traffic(args.config, args.precision, form)
         traffic = None
         if tb is not None and dom in tb:
             traffic = round(tb[dom] / (d["avg_us"] * 1e-6) / 1e9, 2)
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "traffic_bytes_per_launch": tb[dom] if traffic is not None else None,
-                "kernel": f"seg_{dom}_kernel", "avg_launch_us": round(d["avg_us"], 3),
+                "kernel": f"{kernel_prefix(form)}_{dom}_kernel", "avg_launch_us": round(d["avg_us"], 3),
                 "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1),
                 "other": {k: {"avg_launch_us": round(v["avg_us"], 3), "launches": v["launches"],
                               "ms": round(v["ms"], 3)} for k, v in kinds.items()},
@@ -214,6 +239,9 @@ def main():
         "factor_step_s": round(factor_s, 4),
         "factor_blocks": n_blocks,
         "lipschitz_s": round(lipschitz_s, 4),
+        "schedule": {"form": form, "bwd_launches": n_bwd, "autotune_s": round(tune_s, 3),
+                     "autotune_candidates": tune_nc,
+                     "autotune_ms_per_iter": None if tune_ms is None else round(tune_ms, 5)},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -243,7 +271,14 @@ def main_batch(args, ds, tapg):
     for t in trees:
         tapg.tapg_estimate_lipschitz(S.h, t, 100)
     lipschitz_s = time.perf_counter() - t0
-    print(f"[bench] batch64: 64 trees, {K_tot} nodes, power {lipschitz_s:.3f}s",
+    t0 = time.perf_counter()
+    tune_ms, tune_nc = tapg.tapg_autotune(S.h, trees, 10)
+    tune_s = time.perf_counter() - t0
+    form, n_bwd = tapg.tapg_sweep_form(S.h, trees)
+    elem = 8 if prec == tapg.TAPG_FP64 else 4
+    forest_bytes = sum(sweep_bytes(net.nx, net.nu, elem, K_tot, 1, kind, form) for kind in ("bwd", "fwd"))
+    print(f"[bench] batch64: 64 trees, {K_tot} nodes, power {lipschitz_s:.3f}s, autotune "
+          f"{tune_s:.3f}s: {form} form, {n_bwd} backward launches, {tune_ms:.4f} ms/iter",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
         st, _, res = S.batch_solve(trees, ps, qs)
@@ -294,6 +329,12 @@ def main_batch(args, ds, tapg):
         "iters_min": int(min(iters)), "iters_max": int(max(iters)),
         "converged": int(sum(r.converged for r in last)),
         "lipschitz_s": round(lipschitz_s, 4),
+        # one iteration of the whole forest (every tree running), as the
+        # autotuner timed it with the schedule and form it kept
+        "schedule": {"form": form, "bwd_launches": n_bwd, "autotune_s": round(tune_s, 3),
+                     "autotune_candidates": tune_nc, "forest_ms_per_iter": round(tune_ms, 5),
+                     "forest_gb_per_iter": round(forest_bytes / 1e9, 4),
+                     "forest_gbs": round(forest_bytes / (tune_ms * 1e-3) / 1e9, 1)},
         "roofline": None,
         "cpu_baseline": cpu,
     }

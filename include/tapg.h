@@ -257,6 +257,20 @@ void tapg_server_destroy(tapg_server srv);
 tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees, int iters,
                           double* ms_per_iter, int* candidates);
 
+/* Sweep form of a tree (ntrees = 1) or of a batch's forest (ntrees > 1) as
+ * its last solve or autotune left it: *form (may be NULL) one of
+ * TAPG_FORM_*, *bwd_launches (may be NULL) the backward launches per
+ * iteration.  The scan form (Sec. 4.4 recursions with A = I and the projector
+ * factors unrolled into subtree and root-path sums) is the default where it
+ * applies; the autotuner may choose the segment form for a forest.
+ * TAPG_ESTATE before the first solve or autotune of that tree or batch. */
+#define TAPG_FORM_STAGES 0    /* per-stage kernels */
+#define TAPG_FORM_SEGMENT 1   /* segment kernels, stage factors in registers */
+#define TAPG_FORM_PROJECTOR 2 /* segment kernels, projector form of the factors */
+#define TAPG_FORM_SCAN 3      /* scan kernels */
+tapg_status tapg_sweep_form(tapg_solver solver, int ntrees, const tapg_tree* trees, int* form,
+                            int* bwd_launches);
+
 /* Release the device memory a solver holds for a tree (its slot and every
  * cached batch containing it).  The tree stays valid; a later solve allocates
  * again. */

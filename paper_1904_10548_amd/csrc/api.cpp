@@ -526,6 +526,37 @@ tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees
   });
 }
 
+tapg_status tapg_sweep_form(tapg_solver solver, int ntrees, const tapg_tree* trees, int* form,
+                            int* bwd_launches) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    need(trees, "trees");
+    if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
+    uint64_t uid = 0;
+    if (ntrees == 1) {
+      need(trees[0], "tree");
+      uid = trees[0]->h.uid;
+    } else {
+      std::vector<uint64_t> key(ntrees);
+      for (int k = 0; k < ntrees; ++k) {
+        need(trees[k], "tree");
+        key[k] = trees[k]->h.uid;
+      }
+      auto bit = solver->batches.find(key);
+      if (bit == solver->batches.end()) fail(TAPG_ESTATE, "this batch has not been solved or tuned");
+      uid = bit->second.forest.uid;
+    }
+    auto it = solver->slots.find(uid);
+    if (it == solver->slots.end()) fail(TAPG_ESTATE, "the tree has not been solved or tuned");
+    const Slot& sl = it->second;
+    int f = TAPG_FORM_STAGES;
+    if (sl.segmented) f = sl.scan ? TAPG_FORM_SCAN : solver->proj ? TAPG_FORM_PROJECTOR : TAPG_FORM_SEGMENT;
+    if (form) *form = f;
+    if (bwd_launches) *bwd_launches = sl.segmented ? (int)sl.levels.size() : sl.N;
+    return TAPG_OK;
+  });
+}
+
 tapg_status tapg_solver_forget(tapg_solver solver, tapg_tree tree) {
   return guarded([&]() -> tapg_status {
     need(solver, "solver");

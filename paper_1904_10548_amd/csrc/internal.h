@@ -171,6 +171,7 @@ struct Slot {
   int* d_own = nullptr;
   std::vector<LevelPlan> plans;  // the plan the levels were built from
   bool segmented = false;
+  bool scan = false;  // sweeps in scan form (the solver allows it; the autotuner may choose)
   int part_total = 0;
   int ntrees = 1;                // trees of the forest held by this slot
   unsigned* d_counter = nullptr; // closing-launch workgroup counter

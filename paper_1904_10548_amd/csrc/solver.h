@@ -72,6 +72,7 @@ struct tapg_solver_s {
   std::map<uint64_t, tapg::Slot> slots;
   std::map<std::vector<uint64_t>, tapg::Batch> batches;
   std::map<std::string, std::vector<tapg::LevelPlan>> tuned;  // autotuned schedule per tree shape
+  std::map<std::string, bool> tuned_scan;  // autotuned sweep form per tree shape
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool use_graph = true;
   // structure of the network and weights (detected at creation)

@@ -200,7 +200,7 @@ SweepArgs<T> make_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode)
 // One APG iteration (mode 0) or one power-iteration step (mode 1) on the
 // solver's stream: backward stages, forward stages, end-of-step kernel.
 template <typename T>
-size_t seg_lds_probe(tapg_solver_s* S, int nbm, int nst, int nch) {
+size_t seg_lds_probe(tapg_solver_s* S, int nbm, int nst, int nch, bool scan) {
   SegArgs<T> probe{};
   probe.nch = nch;
   probe.nx = S->net.nx;
@@ -213,7 +213,7 @@ size_t seg_lds_probe(tapg_solver_s* S, int nbm, int nst, int nch) {
   probe.ns = S->net.ns;
   probe.nnzG = S->nnzG;
   probe.nnzE = S->nnzE;
-  probe.scan = S->scan ? 1 : 0;
+  probe.scan = scan ? 1 : 0;
   return seg_lds<T>(nbm, probe);
 }
 
@@ -252,7 +252,7 @@ SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mod
   a.Etcol = d.Etcol;
   a.Etval = d.Etval;
   a.winv = (T)(1.0 / S->wu);
-  a.scan = S->scan ? 1 : 0;
+  a.scan = sl.scan ? 1 : 0;
   a.kperp = static_cast<const T*>(sl.d_kperp);
   a.zb = static_cast<T*>(sl.d_zb);
   a.zr = static_cast<const T*>(sl.d_zr);
@@ -412,7 +412,7 @@ bool chain_usable(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
   const char* env = std::getenv("TAPG_CHAIN");
   if (!(env && env[0] == '1')) return false;
   const int nl = (int)sl.levels.size();
-  if (t.ntrees != 1 || !sl.segmented || !S->proj || S->scan || nl < 1 || nl > kChainMaxLevels)
+  if (t.ntrees != 1 || !sl.segmented || !S->proj || sl.scan || nl < 1 || nl > kChainMaxLevels)
     return false;
   int total = 0, nbm = 1;
   for (const Slot::Level& L : sl.levels) {
@@ -421,7 +421,7 @@ bool chain_usable(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
   }
   size_t lds = 0;
   for (const Slot::Level& L : sl.levels)
-    lds = std::max(lds, seg_lds_probe<T>(S, nbm, L.s_end - L.s_begin + 1, L.nch));
+    lds = std::max(lds, seg_lds_probe<T>(S, nbm, L.s_end - L.s_begin + 1, L.nch, false));
   if (lds + kSegStaticLds > S->lds_limit) return false;
   int cus = 0;
   TAPG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device));
@@ -552,7 +552,7 @@ void data_step(tapg_solver_s* S, Slot& sl, int K, hipStream_t st) {
                       (const double*)S->d64.F, (const double*)S->dx.alpha0,
                       (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
                       static_cast<T*>(sl.d_g), h.ns, (const double*)S->dx.Gm,
-                      (const double*)S->dx.E, S->scan ? static_cast<T*>(sl.d_kperp) : nullptr,
+                      (const double*)S->dx.E, sl.scan ? static_cast<T*>(sl.d_kperp) : nullptr,
                       st);
 }
 
@@ -969,7 +969,6 @@ void free_chain(Slot& sl) {
   sl.chain_state = 0;
 }
 
-// (Re)build the level launches of a slot from a plan.
 // The scan form's forward launch: the bottom level's workgroups, each given
 // the ancestors of its nodes at every stage above the level (a contiguous
 // range no wider than the one below, by the breadth-first numbering), and the
@@ -997,8 +996,8 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
       own[(size_t)w * N + s] = w == 0 ? r.x : std::max(r.x, rg[(size_t)(w - 1) * N + s].y);
     }
   Slot::Level L{0, N - 1, nw, nb_template(wmax), 0, nullptr, nullptr};
-  const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, N, 0)
-                             : seg_lds_probe<double>(S, L.nbm, N, 0);
+  const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, N, 0, true)
+                             : seg_lds_probe<double>(S, L.nbm, N, 0, true);
   if (lds + kSegStaticLds > S->lds_limit)
     throw Fail{TAPG_EINVAL, "forward launch needs " + std::to_string(lds) + " bytes of LDS"};
   try {
@@ -1023,6 +1022,7 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
   sl.fwd_full = L;
 }
 
+// (Re)build the level launches of a slot from a plan.
 void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vector<LevelPlan>& plans) {
   hipStream_t st = S->stream;
   const int nbmax = kSegNbMax;
@@ -1046,8 +1046,8 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
         }
       }
       Slot::Level L{P.s_begin, P.s_end, P.n_wg, nb_template(wmax), nch, nullptr, nullptr};
-      const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, nst, nch)
-                                 : seg_lds_probe<double>(S, L.nbm, nst, nch);
+      const size_t lds = S->fp32 ? seg_lds_probe<float>(S, L.nbm, nst, nch, sl.scan)
+                                 : seg_lds_probe<double>(S, L.nbm, nst, nch, sl.scan);
       if (lds + kSegStaticLds > S->lds_limit)
         throw Fail{TAPG_EINVAL, "segment schedule needs " + std::to_string(lds) +
                                     " bytes of LDS per workgroup (limit " +
@@ -1080,7 +1080,7 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
   sl.levels = std::move(levels);
   sl.plans = plans;
   free_fwd_full(sl);
-  if (S->scan) build_fwd_full(S, t, sl, plans.back());
+  if (sl.scan) build_fwd_full(S, t, sl, plans.back());
   free_chain(sl);
   sl.part_total = ptot;
   sl.segmented = true;
@@ -1096,6 +1096,10 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
     Slot sl;
     sl.tree_uid = t.uid;
     sl.K = t.K;
+    {  // sweep form: scan where the network allows it, unless tuned otherwise
+      auto ts = S->tuned_scan.find(shape_key(t));
+      sl.scan = S->scan && (ts == S->tuned_scan.end() || ts->second);
+    }
     sl.N = t.N;
     sl.elem = S->fp32 ? sizeof(float) : sizeof(double);
     const int K = t.K, LDX = S->LDX, LDU = S->LDU, LDY = S->LDY;
@@ -1658,19 +1662,30 @@ double time_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
 template <typename T>
 double autotune_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters, int* ncand) {
   std::vector<std::vector<LevelPlan>> cands = candidate_plans(t, kSegNbMax, seg_node_us(S));
-  if (ncand) *ncand = (int)cands.size();
+  // both sweep forms where the scan form applies: it wins on narrow trees
+  // (fewer launches, shorter chains), the segment form on wide forests (two
+  // workgroups per compute unit against one)
+  std::vector<bool> forms = S->scan ? std::vector<bool>{true, false} : std::vector<bool>{false};
+  if (ncand) *ncand = (int)(cands.size() * forms.size());
   double best = 1e300;
   size_t bi = 0;
-  for (size_t i = 0; i < cands.size(); ++i) {
-    build_levels(S, t, sl, cands[i]);
-    const double ms = time_levels<T>(S, t, sl, iters);
-    if (ms < best) {
-      best = ms;
-      bi = i;
+  bool bscan = false;
+  for (bool form : forms) {
+    sl.scan = form;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      build_levels(S, t, sl, cands[i]);
+      const double ms = time_levels<T>(S, t, sl, iters);
+      if (ms < best) {
+        best = ms;
+        bi = i;
+        bscan = form;
+      }
     }
   }
+  sl.scan = bscan;
   build_levels(S, t, sl, cands[bi]);
   S->tuned[shape_key(t)] = cands[bi];
+  S->tuned_scan[shape_key(t)] = bscan;
   sl.has_dual = false;  // the timing runs overwrote the iterates
   sl.has_result = false;
   return best;

@@ -37,7 +37,7 @@ EXPORTED = [
     "tapg_tree_num_nodes", "tapg_tree_destroy", "tapg_solver_create", "tapg_solver_destroy",
     "tapg_factor_step", "tapg_get_factors", "tapg_factor_blocks", "tapg_solve", "tapg_batch_solve", "tapg_get_primal", "tapg_get_dual",
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
-    "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune",
+    "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune", "tapg_sweep_form",
     "tapg_solver_forget",
     "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
@@ -114,6 +114,8 @@ def lib() -> ctypes.CDLL:
         "tapg_get_factors": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
         "tapg_factor_blocks": ([_P, _I, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_solver_forget": ([_P, _P], ctypes.c_int),
+        "tapg_sweep_form": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int),
+                             ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_autotune": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.c_int, _D,
                            ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_server_create": ([_P, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
@@ -308,6 +310,19 @@ def tapg_autotune(solver, trees, iters=20):
     nc = ctypes.c_int(0)
     _check(lib().tapg_autotune(solver, n, tarr, int(iters), _ptr(ms), ctypes.byref(nc)))
     return float(ms[0]), nc.value
+
+
+FORM_NAMES = {0: "stages", 1: "segment", 2: "projector", 3: "scan"}
+
+
+def tapg_sweep_form(solver, trees):
+    """Sweep form of a tree or batch after its last solve / autotune:
+    ``(form name, backward launches per iteration)``."""
+    n = len(trees)
+    tarr = (_P * n)(*trees)
+    f, nl = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().tapg_sweep_form(solver, n, tarr, ctypes.byref(f), ctypes.byref(nl)))
+    return FORM_NAMES.get(f.value, str(f.value)), nl.value
 
 
 def tapg_solver_forget(solver, tree):

@@ -165,10 +165,16 @@ def test_autotuned_schedule_keeps_parity():
         trees = [add_tree(S, P) for P in batch]
         ms_b, nc_b = tapg.tapg_autotune(S.h, trees, 10)
         ms_1, nc_1 = tapg.tapg_autotune(S.h, trees[2:3], 10)
-        say("autotune", ms_b, nc_b, ms_1, nc_1)
+        form_b = tapg.tapg_sweep_form(S.h, trees)
+        form_1 = tapg.tapg_sweep_form(S.h, trees[2:3])
+        say("autotune", ms_b, nc_b, form_b, ms_1, nc_1, form_1)
         st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
         u, x = S.primal(trees[2])
+        assert tapg.tapg_sweep_form(S.h, trees) == form_b  # the solve keeps the tuned form
     assert nc_b >= 1 and nc_1 >= 1 and ms_b > 0 and ms_1 > 0
+    # both sweep forms are candidates where the scan form applies (A = I, W_u = w I)
+    assert form_b[0] in ("scan", "projector") and form_1[0] in ("scan", "projector")
+    assert nc_b % 2 == 0 and form_b[1] >= 1
     for P, r in zip(batch, res):
         ref = O.apg(P, gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
         J = O.primal_cost(P, ref.u, ref.x)
