@@ -224,39 +224,6 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
   T bndL[NB], bndP[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) bndL[b] = bndP[b] = T(0);
-  if (kids_below) {
-    const int lo_l = sRg[a.nst - 1].x;
-    for (int c0 = cb; c0 < ce; c0 += kCN) {
-#pragma unroll
-      for (int j = 0; j < kQX; ++j) {
-        const int e = tid + j * kSegThreads;
-        const int c = c0 + e / kSX;
-        sLam[e] = ldm(a.lam, (size_t)c * LDX + ix, c < ce && ix < nx);
-      }
-#pragma unroll
-      for (int j = 0; j < kQU; ++j) {
-        const int e = tid + j * kSegThreads;
-        const int c = c0 + e / kSU;
-        sV[e] = ldm((const T*)a.jv, (size_t)c * kSU + iu, c < ce && iu < nu);
-      }
-      if (tid < kCN) sCh[tid] = c0 + tid < ce ? a.anc[c0 + tid] - lo_l : -1;
-      __syncthreads();
-      if (tid < kSU) {
-#pragma unroll
-        for (int q = 0; q < kCN; ++q) {
-          const int b = sCh[q];  // slot of child c0 + q (-1: past the last child)
-          const T lv = sLam[q * kSX + ix], pv = sV[q * kSU + iu];
-#pragma unroll
-          for (int bb = 0; bb < NB; ++bb)
-            if (b == bb) {
-              bndL[bb] += lv;
-              bndP[bb] += pv;
-            }
-        }
-      }
-      __syncthreads();
-    }
-  }
 
   const int nchunk = (a.nst + CS - 1) / CS;
   // Inputs of one chunk: per x-element (y1, y1o, y2, y2o), per u-element (y3,
@@ -473,7 +440,41 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
   };
 
   Pre PA, PB;
-  load_chunk(0, PA);
+  load_chunk(0, PA);  // in flight while the children of the last stage are summed
+  if (kids_below) {
+    const int lo_l = sRg[a.nst - 1].x;
+    for (int c0 = cb; c0 < ce; c0 += kCN) {
+#pragma unroll
+      for (int j = 0; j < kQX; ++j) {
+        const int e = tid + j * kSegThreads;
+        const int c = c0 + e / kSX;
+        sLam[e] = ldm(a.lam, (size_t)c * LDX + ix, c < ce && ix < nx);
+      }
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) {
+        const int e = tid + j * kSegThreads;
+        const int c = c0 + e / kSU;
+        sV[e] = ldm((const T*)a.jv, (size_t)c * kSU + iu, c < ce && iu < nu);
+      }
+      if (tid < kCN) sCh[tid] = c0 + tid < ce ? a.anc[c0 + tid] - lo_l : -1;
+      __syncthreads();
+      if (tid < kSU) {
+#pragma unroll
+        for (int q = 0; q < kCN; ++q) {
+          const int b = sCh[q];  // slot of child c0 + q (-1: past the last child)
+          const T lv = sLam[q * kSX + ix], pv = sV[q * kSU + iu];
+#pragma unroll
+          for (int bb = 0; bb < NB; ++bb)
+            if (b == bb) {
+              bndL[bb] += lv;
+              bndP[bb] += pv;
+            }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
   int c = 0;
   while (true) {
     chunk(c, PA, PB);
@@ -545,16 +546,6 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
   const int lo_p = par0 >= 0 ? par0 : 0;
   const int np = par0 >= 0 ? parl - par0 + 1 : 1;
   T xprev[NB], zprev[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const bool okp = par0 >= 0 && b < np;
-    xprev[b] = ldm(a.x, (size_t)(lo_p + b) * LDX + ix, okp && ix < nx);
-    zprev[b] = ldm((const T*)a.zb, (size_t)(lo_p + b) * kSU + iu, okp && iu < nu);
-  }
-  if (par0 < 0 && !power) {
-    xprev[0] = ldm(a.pq + (size_t)tree * a.pq_stride, ix, ix < nx);
-    zprev[0] = ldm(a.zr + (size_t)tree * kSU, iu, iu < nu);
-  }
   const bool kids_below = se + 1 < a.N;
 
   const int nchunk = (a.nst + CS - 1) / CS;
@@ -810,7 +801,17 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
   };
 
   Pre PA, PB;
-  load_chunk(0, PA);
+  load_chunk(0, PA);  // in flight together with the parents' loads
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const bool okp = par0 >= 0 && b < np;
+    xprev[b] = ldm(a.x, (size_t)(lo_p + b) * LDX + ix, okp && ix < nx);
+    zprev[b] = ldm((const T*)a.zb, (size_t)(lo_p + b) * kSU + iu, okp && iu < nu);
+  }
+  if (par0 < 0 && !power) {
+    xprev[0] = ldm(a.pq + (size_t)tree * a.pq_stride, ix, ix < nx);
+    zprev[0] = ldm(a.zr + (size_t)tree * kSU, iu, iu < nu);
+  }
   int c = 0;
   while (true) {
     chunk(c, PA, PB);
