@@ -226,7 +226,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == tapg.TAPG_FP64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: nx=63 nu=114 nd=88 ns=17 N=24, "
+        "config": {"workload": f"{args.config}: nx={net.nx} nu={net.nu} nd={net.nd} "
+                               f"ns={net.ns} N={P.tree.N}, "
                                f"{P.tree.n_scenarios} scenarios, K={P.tree.K}, "
                                f"tol={args.tol:g}, cold start",
                    "K": P.tree.K, "N": P.tree.N, "tol": args.tol, "precision": args.precision},

@@ -261,8 +261,11 @@ tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees
  * its last solve or autotune left it: *form (may be NULL) one of
  * TAPG_FORM_*, *bwd_launches (may be NULL) the backward launches per
  * iteration.  The scan form (Sec. 4.4 recursions with A = I and the projector
- * factors unrolled into subtree and root-path sums) is the default where it
- * applies; the autotuner may choose the segment form for a forest.
+ * factors unrolled into subtree and root-path sums) applies when A = I and the
+ * projector form applies; untuned trees and forests use the segment form
+ * (TAPG_SCAN=1: the scan form), and tapg_autotune keeps whichever form is
+ * faster for the shape (measured: scan for a single 128-scenario tree, segment
+ * for wide trees and forests).
  * TAPG_ESTATE before the first solve or autotune of that tree or batch. */
 #define TAPG_FORM_STAGES 0    /* per-stage kernels */
 #define TAPG_FORM_SEGMENT 1   /* segment kernels, stage factors in registers */

@@ -84,9 +84,12 @@ struct tapg_solver_s {
   // the sweeps then apply it as (v - E'(G v)) / w when G is sparse
   bool proj = false;
   int nnzG = 0, nnzE = 0;
-  // A = I as well (and nx <= 64): the sweeps run in scan form, the recursions
-  // unrolled into subtree and root-path sums (TAPG_SCAN=0 keeps the segment form)
+  // A = I as well (and nx <= 64): the sweeps can run in scan form, the
+  // recursions unrolled into subtree and root-path sums (TAPG_SCAN=0: never).
+  // Untuned slots use the segment form unless TAPG_SCAN=1; the autotuner times
+  // both forms and keeps the faster per tree shape.
   bool scan = false;
+  bool scan_default = false;
   tapg::Mat G;  // (E E')^{-1} E, ns x nu
   size_t lds_limit = 64 * 1024;  // dynamic LDS per workgroup (device attribute)
   // optional per-launch timing of the sweep kernels (HIP events around each

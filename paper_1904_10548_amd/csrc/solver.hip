@@ -798,6 +798,7 @@ void dev_init(tapg_solver_s* S) {
     }
     const char* se = std::getenv("TAPG_SCAN");
     S->scan = S->proj && ai && h.nx <= 64 && !(se && se[0] == '0');
+    S->scan_default = S->scan && se && se[0] == '1';
   }
   if (S->stream == nullptr) {
     TAPG_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
@@ -1096,9 +1097,9 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
     Slot sl;
     sl.tree_uid = t.uid;
     sl.K = t.K;
-    {  // sweep form: scan where the network allows it, unless tuned otherwise
+    {  // sweep form: the tuned one for this shape, else the solver's default
       auto ts = S->tuned_scan.find(shape_key(t));
-      sl.scan = S->scan && (ts == S->tuned_scan.end() || ts->second);
+      sl.scan = S->scan && (ts == S->tuned_scan.end() ? S->scan_default : ts->second);
     }
     sl.N = t.N;
     sl.elem = S->fp32 ? sizeof(float) : sizeof(double);
