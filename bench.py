@@ -412,6 +412,7 @@ def main_serve(args, ds, tapg):
         tickets[i] = tapg.tapg_server_submit(srv, trees[k], p, q, session=k)
     th.join()
     stats = tapg.tapg_server_stats(srv)
+    timing = tapg.tapg_server_timing(srv)
     tapg.tapg_server_destroy(srv)
     timed = range(n_warm, total)
     lat_ms = np.array([results[i][2] for i in timed])
@@ -444,6 +445,7 @@ def main_serve(args, ds, tapg):
         "iters_p50": int(np.percentile(iters, 50)), "iters_max": int(iters.max()),
         "forests_formed": stats["batches"],
         "worker_busy_ms": round(stats["busy_ms"], 1),
+        "worker_ms": {k: round(v, 1) for k, v in timing.items()},
         "roofline": None,
         "cpu_baseline": None,
     }

@@ -241,6 +241,11 @@ tapg_status tapg_server_poll(tapg_server srv, long long ticket, int wait_ms, dou
 /* Counters: batches run, requests solved, worker busy time, queue length. */
 tapg_status tapg_server_stats(tapg_server srv, long long* batches, long long* solved,
                               double* busy_ms, int* pending);
+/* Worker time so far, in ms: forming forests (running trees' state in, data
+ * step, iteration graph), chunks of iterations, and leaving forests (state
+ * back to the trees' slots, results, forest freed). */
+tapg_status tapg_server_timing(tapg_server srv, double* enter_ms, double* chunk_ms,
+                               double* leave_ms);
 /* Stops the worker (queued requests complete with TAPG_ESTATE) and frees it. */
 void tapg_server_destroy(tapg_server srv);
 

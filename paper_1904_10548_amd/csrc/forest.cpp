@@ -11,7 +11,7 @@
 namespace tapg {
 
 TreeHost build_forest(const std::vector<const TreeHost*>& trees, std::vector<int>& map,
-                      std::vector<int>& map_off) {
+                      std::vector<int>& map_off, bool host_data) {
   const int T = (int)trees.size();
   if (T < 1) throw Fail{TAPG_EINVAL, "empty batch"};
   const TreeHost& t0 = *trees[0];
@@ -50,8 +50,11 @@ TreeHost build_forest(const std::vector<const TreeHost*>& trees, std::vector<int
   f.cend.assign(K, 0);
   f.stage.assign(K, 0);
   f.prob.assign(K, 0.0);
-  f.price.assign(K, 0.0);
-  f.demand.assign((size_t)K * nd, 0.0);
+  f.device_data = !host_data;
+  if (host_data) {
+    f.price.assign(K, 0.0);
+    f.demand.assign((size_t)K * nd, 0.0);
+  }
   map.assign(K, 0);
   map_off.assign(T + 1, 0);
   for (int k = 0; k < T; ++k) map_off[k + 1] = map_off[k] + trees[k]->K;
@@ -71,8 +74,10 @@ TreeHost build_forest(const std::vector<const TreeHost*>& trees, std::vector<int
       }
       f.stage[fn] = t.stage[n];
       f.prob[fn] = t.prob[n];
-      f.price[fn] = t.price[n];
-      std::copy_n(t.demand.begin() + (size_t)n * nd, nd, f.demand.begin() + (size_t)fn * nd);
+      if (host_data) {
+        f.price[fn] = t.price[n];
+        std::copy_n(t.demand.begin() + (size_t)n * nd, nd, f.demand.begin() + (size_t)fn * nd);
+      }
     }
   }
   return f;

@@ -81,6 +81,9 @@ struct TreeHost {
   // at stage s (empty for a single tree).
   int ntrees = 1;
   std::vector<int> tstart;
+  // a forest whose demand and price are gathered on the device from its trees'
+  // own slots (host arrays left empty, nothing uploaded)
+  bool device_data = false;
   int seg_begin(int s, int k) const {
     return tstart.empty() ? offset[s] : tstart[(size_t)s * (ntrees + 1) + k];
   }
@@ -191,9 +194,10 @@ struct Slot {
 uint64_t next_uid();
 
 // A batch of trees as one forest (forest.cpp); map[map_off[k] + n] is the
-// forest index of node n of tree k.
+// forest index of node n of tree k.  host_data = false: demand and price are
+// left out (gathered on the device from the trees' slots).
 TreeHost build_forest(const std::vector<const TreeHost*>& trees, std::vector<int>& map,
-                      std::vector<int>& map_off);
+                      std::vector<int>& map_off, bool host_data = true);
 // Copy the members' current demand and price into the forest (new version).
 void refresh_forest_data(const std::vector<const TreeHost*>& trees, const std::vector<int>& map,
                          const std::vector<int>& map_off, TreeHost& f);

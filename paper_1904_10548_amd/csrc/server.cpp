@@ -45,7 +45,9 @@ struct tapg_server_s {
   std::unordered_map<int, uint64_t> session_tree;  // tree last solved for each session
   long long next_ticket = 1;
   long long n_batches = 0, n_solved = 0;
-  double busy_ms = 0.0;
+  double busy_ms = 0.0;   // chunks of iterations
+  double enter_ms = 0.0;  // forming forests (state in, data step, graph)
+  double leave_ms = 0.0;  // state back to the trees' slots, results, forest freed
 };
 
 namespace tapg {
@@ -97,6 +99,12 @@ struct Active {
   LiveTree lt;
   size_t bytes = 0;
 };
+
+void add_ms(tapg_server_s* srv, double tapg_server_s::*field, Clock::time_point t0) {
+  const double ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->*field += ms;
+}
 
 void worker_loop(tapg_server_s* srv) {
   tapg_solver S = srv->S;
@@ -176,7 +184,9 @@ void worker_loop(tapg_server_s* srv) {
       if (!admitted.empty()) {
         if (in_forest) {  // running trees keep their state in their own slots
           std::vector<LiveTree*> js = live_set();
+          const auto tl = Clock::now();
           dev_live_leave(S, js);
+          add_ms(srv, &tapg_server_s::leave_ms, tl);
           in_forest = false;
           finish();
         }
@@ -196,7 +206,9 @@ void worker_loop(tapg_server_s* srv) {
       }
       if (active.empty()) continue;
       if (!in_forest) {
+        const auto te = Clock::now();
         dev_live_enter(S, live_set());
+        add_ms(srv, &tapg_server_s::enter_ms, te);
         in_forest = true;
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->n_batches++;
@@ -209,7 +221,9 @@ void worker_loop(tapg_server_s* srv) {
         srv->busy_ms += std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
       }
       if (stopped) {
+        const auto tl = Clock::now();
         dev_live_leave(S, js);
+        add_ms(srv, &tapg_server_s::leave_ms, tl);
         in_forest = false;
         finish();
       }
@@ -371,6 +385,20 @@ tapg_status tapg_server_stats(tapg_server srv, long long* batches, long long* so
   if (solved) *solved = srv->n_solved;
   if (busy_ms) *busy_ms = srv->busy_ms;
   if (pending) *pending = (int)srv->pending.size();
+  clear_error();
+  return TAPG_OK;
+}
+
+tapg_status tapg_server_timing(tapg_server srv, double* enter_ms, double* chunk_ms,
+                               double* leave_ms) {
+  if (!srv) {
+    set_error("srv is NULL");
+    return TAPG_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (enter_ms) *enter_ms = srv->enter_ms;
+  if (chunk_ms) *chunk_ms = srv->busy_ms;
+  if (leave_ms) *leave_ms = srv->leave_ms;
   clear_error();
   return TAPG_OK;
 }

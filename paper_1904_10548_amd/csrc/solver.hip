@@ -6,7 +6,11 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <random>
+#include <unordered_map>
+#include <vector>
 
 #include "kernels.h"
 #include "solver.h"
@@ -41,18 +45,85 @@ struct ProgressLine {
 };
 
 
+// Device blocks freed by the solver are kept for reuse, by device and size,
+// instead of going back to the driver: hipFree synchronises the device, and
+// the server forms and frees a forest every few chunks.  Every path that frees
+// a slot has synchronised the solver's stream first, so a reused block is idle.
+// The cache is released into the driver when an allocation fails.
+class BlockCache {
+ public:
+  void* get(size_t bytes) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto& fl = free_[{dev, bytes}];
+      if (!fl.empty()) {
+        void* p = fl.back();
+        fl.pop_back();
+        live_[p] = {dev, bytes};
+        return p;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess) throw Fail{TAPG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    std::lock_guard<std::mutex> lk(mu_);
+    live_[p] = {dev, bytes};
+    return p;
+  }
+  void put(void* p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) {  // not ours
+      (void)hipFree(p);
+      return;
+    }
+    free_[it->second].push_back(p);
+    live_.erase(it);
+  }
+  void trim() {  // every cached block back to the driver
+    std::lock_guard<std::mutex> lk(mu_);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : free_) {
+      if (kv.second.empty()) continue;
+      (void)hipSetDevice(kv.first.first);
+      for (void* p : kv.second) (void)hipFree(p);
+      kv.second.clear();
+    }
+    (void)hipSetDevice(cur);
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free_;
+  std::unordered_map<void*, std::pair<int, size_t>> live_;
+};
+
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();  // lives until the process ends
+  return *c;
+}
+
+// Device allocations are rounded up to 256 bytes (the cache's size classes).
+void* dev_alloc(size_t bytes) {
+  return block_cache().get((std::max<size_t>(bytes, 1) + 255) & ~(size_t)255);
+}
+
 template <typename T>
 T* dmalloc(size_t n) {
-  void* p = nullptr;
-  if (n == 0) n = 1;
-  hipError_t e = hipMalloc(&p, n * sizeof(T));
-  if (e != hipSuccess) throw Fail{TAPG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
-  return static_cast<T*>(p);
+  return static_cast<T*>(dev_alloc(std::max<size_t>(n, 1) * sizeof(T)));
 }
 
 template <typename T>
 void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+  if (p) block_cache().put(p);
   p = nullptr;
 }
 
@@ -1106,9 +1177,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
     const int K = t.K, LDX = S->LDX, LDU = S->LDU, LDY = S->LDY;
     const size_t e = sl.elem;
     auto dalloc = [&](size_t n) {
-      void* p = nullptr;
-      hipError_t er = hipMalloc(&p, std::max<size_t>(n, 1) * e);
-      if (er != hipSuccess) throw Fail{TAPG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(er)};
+      void* p = dev_alloc(std::max<size_t>(n, 1) * e);
       TAPG_HIP(hipMemsetAsync(p, 0, std::max<size_t>(n, 1) * e, st));
       return p;
     };
@@ -1182,7 +1251,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
     if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
     sl.graph = nullptr;
   }
-  if (sl.data_version != t.version) {
+  if (sl.data_version != t.version && !t.device_data) {
     TAPG_HIP(hipMemcpyAsync(sl.d_demand, t.demand.data(), t.demand.size() * 8,
                             hipMemcpyHostToDevice, st));
     TAPG_HIP(hipMemcpyAsync(sl.d_price, t.price.data(), t.price.size() * 8,
@@ -1204,8 +1273,11 @@ void dev_solve(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p, c
 
 namespace {
 // The forest of a batch, cached by the member ids (its data refreshed when a
-// member's data changed).
-Batch& get_batch(tapg_solver_s* S, const std::vector<const TreeHost*>& trees) {
+// member's data changed).  host_data = false (the server's forests): demand
+// and price are not copied on the host; the caller gathers them on the device
+// from the trees' own slots.
+Batch& get_batch(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
+                 bool host_data = true) {
   hipStream_t st = S->stream;
   const int nt = (int)trees.size();
   std::vector<uint64_t> key(nt);
@@ -1213,7 +1285,7 @@ Batch& get_batch(tapg_solver_s* S, const std::vector<const TreeHost*>& trees) {
   auto bit = S->batches.find(key);
   if (bit == S->batches.end()) {
     Batch b;
-    b.forest = build_forest(trees, b.map, b.map_off);
+    b.forest = build_forest(trees, b.map, b.map_off, host_data);
     for (const TreeHost* t : trees) b.versions.push_back(t->version);
     try {
       b.d_map = upload(b.map, st);
@@ -1227,7 +1299,7 @@ Batch& get_batch(tapg_solver_s* S, const std::vector<const TreeHost*>& trees) {
   } else {
     bool stale = false;
     for (int k = 0; k < nt; ++k) stale = stale || bit->second.versions[k] != trees[k]->version;
-    if (stale) {
+    if (stale && !bit->second.forest.device_data) {
       refresh_forest_data(trees, bit->second.map, bit->second.map_off, bit->second.forest);
       for (int k = 0; k < nt; ++k) bit->second.versions[k] = trees[k]->version;
     }
@@ -1251,6 +1323,28 @@ void ensure_graph(tapg_solver_s* S, Slot& sl, int chunk) {
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) throw Fail{TAPG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
   sl.graph_iters = chunk;
+}
+
+// Iterations per captured graph of a forest formed by the server: the largest
+// divisor of the chunk up to 5.  A forest lives for a few chunks only, so a
+// short graph replayed chunk / g times beats instantiating a whole chunk.
+int live_graph_iters(int chunk) {
+  for (int g = 5; g > 1; --g)
+    if (chunk % g == 0) return g;
+  return 1;
+}
+
+// `iters` iterations (a multiple of the slot's graph length) by replaying its
+// graph, or by direct launches when graphs are off.
+template <typename T>
+void run_replays(tapg_solver_s* S, Slot& sl, int iters) {
+  if (S->use_graph) {
+    for (int i = 0; i < iters; i += sl.graph_iters) TAPG_HIP(hipGraphLaunch(sl.graph, S->stream));
+  } else {
+    const NetDev<T>& d = net_of<T>(S);
+    for (int i = 0; i < iters; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    TAPG_HIP(hipGetLastError());
+  }
 }
 
 template <typename T>
@@ -1480,9 +1574,18 @@ void live_enter_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
   hipStream_t st = S->stream;
   const int LDX = S->LDX, LDU = S->LDU, LDY = S->LDY, PQ = LDX + LDU;
   const int nt = (int)js.size();
-  Batch& B = get_batch(S, live_trees(js));
+  Batch& B = get_batch(S, live_trees(js), false);
   const TreeHost& f = B.forest;
   Slot& sl = dev_slot(S, f);
+  for (int k = 0; k < nt; ++k) {  // demand and price from each tree's own slot
+    const int* idx = B.d_map + B.map_off[k];
+    const Slot& o = *js[k]->own;
+    const int nd = js[k]->t->nd;
+    launch_copy_rows<double>(static_cast<const double*>(o.d_demand), nd,
+                             static_cast<double*>(sl.d_demand), nd, idx, js[k]->t->K, nd, true, st);
+    launch_copy_rows<double>(static_cast<const double*>(o.d_price), 1,
+                             static_cast<double*>(sl.d_price), 1, idx, js[k]->t->K, 1, true, st);
+  }
   if (!sl.segmented)
     throw Fail{TAPG_EINVAL, "batched solves need the segment kernels (nx, nu <= 128, sparse B)"};
   std::vector<double> pq64((size_t)nt * PQ, 0.0);
@@ -1506,7 +1609,7 @@ void live_enter_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
   TAPG_HIP(hipGetLastError());
   forest_data_step<T>(S, f, sl);
   const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
-  ensure_graph<T>(S, sl, chunk);
+  ensure_graph<T>(S, sl, live_graph_iters(chunk));
   TAPG_HIP(hipStreamSynchronize(st));
 }
 
@@ -1517,7 +1620,7 @@ bool live_chunk_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
   hipStream_t st = S->stream;
   const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
   TAPG_HIP(hipEventRecord(S->ev0, st));
-  run_chunk<T>(S, sl, chunk);
+  run_replays<T>(S, sl, chunk);
   TAPG_HIP(hipEventRecord(S->ev1, st));
   std::vector<DevCtl> c(js.size());
   TAPG_HIP(hipMemcpyAsync(c.data(), sl.d_ctl, c.size() * sizeof(DevCtl), hipMemcpyDeviceToHost, st));

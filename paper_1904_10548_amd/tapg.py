@@ -39,7 +39,7 @@ EXPORTED = [
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
     "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune", "tapg_sweep_form",
     "tapg_solver_forget",
-    "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats",
+    "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats", "tapg_server_timing",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
 ]
 
@@ -126,6 +126,7 @@ def lib() -> ctypes.CDLL:
         "tapg_server_stats": ([_P, ctypes.POINTER(ctypes.c_longlong),
                               ctypes.POINTER(ctypes.c_longlong), _D, ctypes.POINTER(ctypes.c_int)],
                              ctypes.c_int),
+        "tapg_server_timing": ([_P, _D, _D, _D], ctypes.c_int),
         "tapg_server_destroy": ([_P], None),
         "tapg_solve": ([_P, _P, _D, _D, ctypes.c_int, _D, ctypes.POINTER(TapgResult)], ctypes.c_int),
         "tapg_batch_solve": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_D),
@@ -363,6 +364,13 @@ def tapg_server_stats(srv):
                                    ctypes.byref(pend)))
     return {"batches": b.value, "solved": s.value, "busy_ms": float(busy[0]),
             "pending": pend.value}
+
+
+def tapg_server_timing(srv):
+    """Worker time in ms: forming forests, chunks of iterations, leaving forests."""
+    t = np.zeros(3)
+    _check(lib().tapg_server_timing(srv, _ptr(t[0:1]), _ptr(t[1:2]), _ptr(t[2:3])))
+    return {"enter_ms": float(t[0]), "chunk_ms": float(t[1]), "leave_ms": float(t[2])}
 
 
 def tapg_server_destroy(srv):
