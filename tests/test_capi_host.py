@@ -168,3 +168,15 @@ def test_server_argument_errors_on_host():
     t = ctypes.c_longlong(0)
     assert L.tapg_server_submit(None, None, None, None, 0, ctypes.byref(t)) == tapg.TAPG_EINVAL
     L.tapg_server_destroy(None)  # no-op
+    assert L.tapg_server_timing(None, None, None, None) == tapg.TAPG_EINVAL
+
+
+def test_sweep_form_argument_errors_on_host():
+    """tapg_sweep_form rejects missing handles and empty batches before any
+    device work."""
+    import ctypes
+    L = tapg.lib()
+    f, nl = ctypes.c_int(-1), ctypes.c_int(-1)
+    assert L.tapg_sweep_form(None, 1, None, ctypes.byref(f), ctypes.byref(nl)) == tapg.TAPG_EINVAL
+    assert f.value == -1 and nl.value == -1
+    assert tapg.FORM_NAMES == {0: "stages", 1: "segment", 2: "projector", 3: "scan"}
