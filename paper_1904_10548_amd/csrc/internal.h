@@ -167,17 +167,19 @@ struct Slot {
     int* d_wgtree;  // tree of each workgroup (forests only)
   };
   std::vector<Level> levels;
-  // Scan form: the forward sweep in one launch over stages 0..N-1, with the
-  // workgroups of the bottom level, each also walking its nodes' ancestors;
-  // d_own: per workgroup and stage, the first node it owns (writes)
+  // Scan form: the forward sweep in one launch over stages 0..N-1, each
+  // workgroup also walking its nodes' ancestors; its workgroups are those of
+  // the bottom level (fwd_group 0) or groups of fwd_group consecutive nodes of
+  // the last stage.  d_own: per workgroup and stage, the first node it owns
+  // (writes).
   Level fwd_full{0, -1, 0, 1, 0, nullptr, nullptr};
   int* d_own = nullptr;
+  int fwd_group = 0;
   std::vector<LevelPlan> plans;  // the plan the levels were built from
   bool segmented = false;
   bool scan = false;  // sweeps in scan form (the solver allows it; the autotuner may choose)
   int part_total = 0;
   int ntrees = 1;                // trees of the forest held by this slot
-  unsigned* d_counter = nullptr; // closing-launch workgroup counter
   // persistent iteration (one tree): per-level kernel arguments, hand-over
   // tables and counters; chain_state 0: not set up, 1: usable, -1: not usable
   void* d_chain_lev = nullptr;

@@ -55,7 +55,6 @@ struct SegArgs {
   int a_ident;     // A == I
   int wu_scalar;   // W_u == wu I
   T wu;
-  int last_level;  // forward launch that ends the iteration
   int part_base, part_total;
   int nnzB;        // nonzeros of B (= of B')
   int nch;         // backward: most children of one workgroup below the level's last stage
@@ -97,7 +96,6 @@ struct SegArgs {
   int ntrees;
   int hist_stride;
   int pq_stride;     // (p, q) of tree k at pq + k * pq_stride
-  unsigned* counter; // workgroups of the closing launch that have finished
   // Projector form of the stage factor (W_u = w I): Fbar v = (v - E'(G v)) / w
   // with G = (E E')^{-1} E, both sparse (CSR of G: ns rows, of E': nu rows).
   int proj, ns, nnzG, nnzE;
@@ -173,7 +171,8 @@ template <typename T>
 void launch_bwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
 template <typename T>
 void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
-void launch_iter_end(DevCtl* c, double* hist, hipStream_t st);
+// End of an iteration of ntrees trees (per-tree control blocks and histories).
+void launch_iter_end(DevCtl* c, double* hist, int ntrees, int hist_stride, hipStream_t st);
 void launch_power_end(DevCtl* c, const double* part, int n, hipStream_t st);
 template <typename T>
 void launch_data_step(int K, int nx, int nu, int nd, int LDX, int LDU, const int* stage,

@@ -23,7 +23,9 @@
 // four (forward) however many stages it holds.
 //
 // The workgroups, levels and node ranges are those of the segment kernels, so
-// the schedule, the forest layout and the closing protocol are shared.  Global
+// the schedule and the forest layout are shared (the forward launch may also
+// take groups of last-stage nodes, each workgroup walking their ancestors).
+// The iteration ends in a small launch of its own.  Global
 // loads of the next chunk are issued while the current one computes, and a
 // chunk's stores are issued at the start of the next, after its one wait.
 #include "seg_device.h"
@@ -56,6 +58,36 @@ __device__ __forceinline__ T range_sum(const T (&v)[NB], int c0, int c1) {
   for (int q = 0; q < NB; ++q)
     if (q >= c0 && q < c1) r += v[q];
   return r;
+}
+
+// Nodes of the element groups of a chunk of stages [s_lo, s_hi]: group j
+// covers node-stage kb_j = (tid + 512 j) / W (slot kb % NB of stage s_lo +
+// kb / NB); its node, or -1 past the chunk or past the stage's node range.
+// kb_j is the same in all lanes of a wave (W = 64 or 128 lanes per
+// node-stage), so the results are made wave-uniform: the tests on them compile
+// to scalar branches.  All LDS reads are issued before the first is used (one
+// wait); with `own` (first node the workgroup writes, per stage) also the
+// owned node or -1.
+template <int NB, int W, int Q>
+__device__ __forceinline__ void chunk_nodes(const int2* sRg, const int* sOwn, int sb, int s_lo,
+                                            int s_hi, int (&node)[Q], int (*owned)[Q]) {
+  int2 rr[Q];
+  int fo[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int kb = (int)(threadIdx.x + j * kSegThreads) / W;
+    const int sc = min(s_lo + kb / NB, max(s_hi, sb)) - sb;  // in range for empty chunks too
+    rr[j] = sRg[sc];
+    if (owned) fo[j] = sOwn[sc];
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int kb = (int)(threadIdx.x + j * kSegThreads) / W;
+    const int n = rr[j].x + kb % NB;
+    const int v = s_lo + kb / NB <= s_hi && n < rr[j].y ? n : -1;
+    node[j] = __builtin_amdgcn_readfirstlane(v);
+    if (owned) (*owned)[j] = __builtin_amdgcn_readfirstlane(v >= fo[j] ? v : -1);
+  }
 }
 
 // Layout of a scan launch's dynamic LDS: consecutive arrays, each starting
@@ -231,18 +263,18 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
   struct Pre {
     T x[kQX][4], u[kQU][3];
     int c0, c1;
+    int nx[kQX], nu[kQU];  // node of each element group (-1: none)
   };
   auto chunk_lo = [&](int c) { return max(sb, se - c * CS - CS + 1); };
   auto chunk_hi = [&](int c) { return se - c * CS; };
   auto load_chunk = [&](int c, Pre& P) {
     const int s_lo = chunk_lo(c), s_hi = chunk_hi(c);
+    chunk_nodes<NB, kSX, kQX>(sRg, nullptr, sb, s_lo, s_hi, P.nx, nullptr);
+    chunk_nodes<NB, kSU, kQU>(sRg, nullptr, sb, s_lo, s_hi, P.nu, nullptr);
 #pragma unroll
     for (int j = 0; j < kQX; ++j) {
-      const int kb = (tid + j * kSegThreads) / kSX;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
-      const size_t o = (size_t)(rr.x + b) * LDY + ix;
+      const bool ok = P.nx[j] >= 0 && ix < nx;
+      const size_t o = (size_t)P.nx[j] * LDY + ix;
       P.x[j][0] = ldc(Yc, o, ok);
       P.x[j][1] = ldc(Yo, o, ok);
       P.x[j][2] = ldc(Yc, o + LDX, ok);
@@ -250,11 +282,8 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
     }
 #pragma unroll
     for (int j = 0; j < kQU; ++j) {
-      const int kb = (tid + j * kSegThreads) / kSU;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
-      const size_t n = (size_t)(rr.x + b);
+      const bool ok = P.nu[j] >= 0 && iu < nu;
+      const size_t n = (size_t)P.nu[j];
       P.u[j][0] = ldc(Yc, n * LDY + 2 * LDX + iu, ok);
       P.u[j][1] = ldc(Yo, n * LDY + 2 * LDX + iu, ok);
       P.u[j][2] = ldc(a.kappa, n * kSU + iu, ok);
@@ -303,20 +332,14 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
 #pragma unroll
     for (int j = 0; j < kQX; ++j) {
       const int e = tid + j * kSegThreads;
-      const int kb = e / kSX;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const bool ok = C.nx[j] >= 0 && ix < nx;
       const T av = power ? scale * (C.x[j][0] + C.x[j][2])
                          : wext(C.x[j][0], C.x[j][1], beta) + wext(C.x[j][2], C.x[j][3], beta);
       sLam[e] = ok ? av : T(0);
     }
 #pragma unroll
     for (int j = 0; j < kQU; ++j) {
-      const int kb = (tid + j * kSegThreads) / kSU;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      const bool ok = C.nu[j] >= 0 && iu < nu;
       const T w3 = power ? scale * C.u[j][0] : wext(C.u[j][0], C.u[j][1], beta);
       w3r[j] = ok ? w3 : T(0);
       kr[j] = ok && !power ? C.u[j][2] : T(0);
@@ -334,9 +357,9 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
       }
       ch[kb] = r2;
     }
-    // the next chunk's loads fly while this one computes (unconditional: the
-    // last chunk reloads itself)
-    load_chunk(c + 1 < nchunk ? c + 1 : c, Nx);
+    // the next chunk's loads fly while this one computes (after the last
+    // chunk: an empty one, whose clamped loads all read one element)
+    load_chunk(c + 1, Nx);
     __syncthreads();
 
     // lambda chain, bottom stage of the chunk first, in registers
@@ -439,24 +462,44 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
     pcs = cs;
   };
 
+  // A batch of the children: lambda, P and parent, loaded unmasked (clamped
+  // indices) and masked where stored.  The first batch is issued ahead of the
+  // first chunk's loads, so that waiting for it does not wait for those.
+  T bl[kQX], bp[kQU];
+  int ba = 0;
+  auto load_bnd = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      const int c = c0 + (tid + j * kSegThreads) / kSX;
+      bl[j] = ldc(a.lam, (size_t)c * LDX + ix, c < ce && ix < nx);
+    }
+#pragma unroll
+    for (int j = 0; j < kQU; ++j) {
+      const int c = c0 + (tid + j * kSegThreads) / kSU;
+      bp[j] = ldc((const T*)a.jv, (size_t)c * kSU + iu, c < ce && iu < nu);
+    }
+    ba = ldc(a.anc, (size_t)(c0 + tid), tid < kCN && c0 + tid < ce);
+  };
+  if (kids_below) load_bnd(cb);
   Pre PA, PB;
   load_chunk(0, PA);  // in flight while the children of the last stage are summed
   if (kids_below) {
     const int lo_l = sRg[a.nst - 1].x;
     for (int c0 = cb; c0 < ce; c0 += kCN) {
+      if (c0 != cb) load_bnd(c0);
 #pragma unroll
       for (int j = 0; j < kQX; ++j) {
         const int e = tid + j * kSegThreads;
         const int c = c0 + e / kSX;
-        sLam[e] = ldm(a.lam, (size_t)c * LDX + ix, c < ce && ix < nx);
+        sLam[e] = c < ce && ix < nx ? bl[j] : T(0);
       }
 #pragma unroll
       for (int j = 0; j < kQU; ++j) {
         const int e = tid + j * kSegThreads;
         const int c = c0 + e / kSU;
-        sV[e] = ldm((const T*)a.jv, (size_t)c * kSU + iu, c < ce && iu < nu);
+        sV[e] = c < ce && iu < nu ? bp[j] : T(0);
       }
-      if (tid < kCN) sCh[tid] = c0 + tid < ce ? a.anc[c0 + tid] - lo_l : -1;
+      if (tid < kCN) sCh[tid] = c0 + tid < ce ? ba - lo_l : -1;
       __syncthreads();
       if (tid < kSU) {
 #pragma unroll
@@ -554,16 +597,17 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
   struct Pre {
     T u[kQU][5], x[kQX][5];
     int an;
+    int nu[kQU], nx[kQX];  // node of each element group (-1: none)
+    int ou[kQU], ox[kQX];  // the same where this workgroup owns (writes) it
   };
   auto load_chunk = [&](int c, Pre& P) {
     const int s_lo = sb + c * CS, s_hi = min(se, s_lo + CS - 1);
+    chunk_nodes<NB, kSU, kQU>(sRg, sOwn, sb, s_lo, s_hi, P.nu, &P.ou);
+    chunk_nodes<NB, kSX, kQX>(sRg, sOwn, sb, s_lo, s_hi, P.nx, &P.ox);
 #pragma unroll
     for (int j = 0; j < kQU; ++j) {
-      const int kb = (tid + j * kSegThreads) / kSU;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
-      const size_t n = (size_t)(rr.x + b);
+      const bool ok = P.nu[j] >= 0 && iu < nu;
+      const size_t n = (size_t)P.nu[j];
       P.u[j][0] = ldc((const T*)a.jv, n * kSU + iu, ok);
       P.u[j][1] = ldc(a.kperp, n * kSU + iu, ok);
       P.u[j][2] = ldc(a.invp, n, ok);
@@ -572,11 +616,8 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
     }
 #pragma unroll
     for (int j = 0; j < kQX; ++j) {
-      const int kb = (tid + j * kSegThreads) / kSX;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
-      const size_t n = (size_t)(rr.x + b);
+      const bool ok = P.nx[j] >= 0 && ix < nx;
+      const size_t n = (size_t)P.nx[j];
       P.x[j][0] = ldc(a.g, n * LDX + ix, ok);
       P.x[j][1] = ldc(Yc, n * LDY + ix, ok);
       P.x[j][2] = ldc((const T*)Yn, n * LDY + ix, ok);
@@ -586,7 +627,7 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
     {
       const int kb = tid < kCN ? tid : 0;
       const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
+      const int2 rr = sRg[min(s, s_hi) - sb];
       const bool ok = tid < kCN && s <= s_hi && b < rr.y - rr.x;
       P.an = ldc(a.anc, (size_t)(rr.x + b), ok);
     }
@@ -605,13 +646,13 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
   auto flush = [&]() {
 #pragma unroll
     for (int j = 0; j < kQU; ++j)
-      if (dnu[j] >= 0) {
+      if (dnu[j] >= 0 && iu < nu) {
         a.u[(size_t)dnu[j] * kSU + iu] = du[j];
         Yn[(size_t)dnu[j] * LDY + 2 * LDX + iu] = dy3[j];
       }
 #pragma unroll
     for (int j = 0; j < kQX; ++j)
-      if (dnx[j] >= 0) {
+      if (dnx[j] >= 0 && ix < nx) {
         a.x[(size_t)dnx[j] * LDX + ix] = dxv[j];
         Yn[(size_t)dnx[j] * LDY + ix] = dy1[j];
         Yn[(size_t)dnx[j] * LDY + LDX + ix] = dy2[j];
@@ -626,10 +667,7 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
 #pragma unroll
     for (int j = 0; j < kQU; ++j) {
       const int e = tid + j * kSegThreads;
-      const int kb = e / kSU;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu;
+      const bool ok = C.nu[j] >= 0 && iu < nu;
       const T d = C.u[j][0] * C.u[j][2];
       const T cj = power ? d : (C.u[j][1] + C.u[j][0]) * C.u[j][2];
       sC[e] = ok ? cj : T(0);
@@ -638,10 +676,7 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
     }
 #pragma unroll
     for (int j = 0; j < kQX; ++j) {
-      const int kb = (tid + j * kSegThreads) / kSX;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool ok = s <= s_hi && b < rr.y - rr.x && ix < nx;
+      const bool ok = C.nx[j] >= 0 && ix < nx;
       gr[j] = ok && !power ? C.x[j][0] : T(0);
       w1r[j] = ok ? wext(C.x[j][1], C.x[j][2], beta) : T(0);
       w2r[j] = ok ? wext(C.x[j][3], C.x[j][4], beta) : T(0);
@@ -657,7 +692,7 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
       }
       sPar[kb] = pb;
     }
-    load_chunk(c + 1 < nchunk ? c + 1 : c, Nx);
+    load_chunk(c + 1, Nx);  // after the last chunk: an empty one
     __syncthreads();
 
     // u / z chain, top stage first, in registers
@@ -733,65 +768,68 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
     __syncthreads();
 
     // ---- prox / dual update, per element; stores held for the next chunk ----
+    // (every LDS read first, then the arithmetic; owned elements are written
+    // and counted here: an ancestor shared with a lower-numbered workgroup is
+    // computed by both and written by that one)
 #pragma unroll
     for (int j = 0; j < kQU; ++j) {
-      const int e = tid + j * kSegThreads;
-      const int kb = e / kSU;
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      // owned: written and counted here (an ancestor shared with a
-      // lower-numbered workgroup is computed by both, written by that one)
-      const bool ok = s <= s_hi && b < rr.y - rr.x && iu < nu &&
-                      rr.x + b >= sOwn[(s <= s_hi ? s : s_lo) - sb];
-      const T u = sC[e];
-      T y;
-      if (power) {
-        y = -u;
-        if (ok) zsq += (double)u * (double)u;
-      } else {
+      du[j] = sC[tid + j * kSegThreads];
+      dnu[j] = C.ou[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      dxv[j] = sX[tid + j * kSegThreads];  // one node-stage per wave
+      dnx[j] = C.ox[j];
+    }
+    if (power) {
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) {
+        dy3[j] = -du[j];
+        if (C.ou[j] >= 0 && iu < nu) zsq += (double)du[j] * (double)du[j];
+      }
+#pragma unroll
+      for (int j = 0; j < kQX; ++j) {
+        dy1[j] = dy2[j] = -dxv[j];
+        if (C.ox[j] >= 0 && ix < nx) zsq += 2.0 * (double)dxv[j] * (double)dxv[j];
+      }
+    } else {
+      const T ulo = sBnd[3 * kSU + iu], uhi = sBnd[4 * kSU + iu];
+      const T xlo = sBnd[ix], xhi = sBnd[kSU + ix], xsf = sBnd[2 * kSU + ix];
+#pragma unroll
+      for (int j = 0; j < kQU; ++j) {
         const T w = w3r[j];
-        const T v = w + gam * u;
-        y = v - fmin(fmax(v, sBnd[3 * kSU + iu]), sBnd[4 * kSU + iu]);
-        if (ok) {
-          double d = fabs((double)y - (double)w);
+        const T v = w + gam * du[j];
+        dy3[j] = v - fmin(fmax(v, ulo), uhi);
+        if (C.ou[j] >= 0 && iu < nu) {
+          double d = fabs((double)dy3[j] - (double)w);
           if (!(d <= 1.0e308)) d = INFINITY;
           rmax = fmax(rmax, d);
         }
       }
-      du[j] = u;
-      dy3[j] = y;
-      dnu[j] = ok ? rr.x + b : -1;
-    }
+      T r1[kQX], r2[kQX];
+      double q1[kQX], q2[kQX];
 #pragma unroll
-    for (int j = 0; j < kQX; ++j) {
-      const int e = tid + j * kSegThreads;
-      const int kb = e / kSX;  // one node-stage per wave
-      const int s = s_lo + kb / NB, b = kb % NB;
-      const int2 rr = sRg[(s <= s_hi ? s : s_lo) - sb];
-      const bool valid = s <= s_hi && b < rr.y - rr.x && ix < nx;
-      const bool ok = valid && rr.x + b >= sOwn[(s <= s_hi ? s : s_lo) - sb];  // owned
-      const T xv = sX[e];
-      dxv[j] = xv;
-      dnx[j] = ok ? rr.x + b : -1;
-      if (power) {
-        dy1[j] = -xv;
-        dy2[j] = -xv;
-        if (ok) zsq += 2.0 * (double)xv * (double)xv;
-      } else {
-        const T w1 = w1r[j], w2 = w2r[j];
-        const T v1 = w1 + gam * xv, v2 = w2 + gam * xv;
-        const T r1 = valid ? v1 - fmin(fmax(v1, sBnd[ix]), sBnd[kSU + ix]) : T(0);
-        const T r2 = valid ? v2 - fmax(v2, sBnd[2 * kSU + ix]) : T(0);
-        const double n1 = sqrt(wave_sum((double)r1 * (double)r1));
-        const double n2 = sqrt(wave_sum((double)r2 * (double)r2));
+      for (int j = 0; j < kQX; ++j) {
+        const bool valid = C.nx[j] >= 0 && ix < nx;
+        const T v1 = w1r[j] + gam * dxv[j], v2 = w2r[j] + gam * dxv[j];
+        r1[j] = valid ? v1 - fmin(fmax(v1, xlo), xhi) : T(0);
+        r2[j] = valid ? v2 - fmax(v2, xsf) : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < kQX; ++j) {
+        q1[j] = wave_sum((double)r1[j] * (double)r1[j]);
+        q2[j] = wave_sum((double)r2[j] * (double)r2[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < kQX; ++j) {
+        const double n1 = sqrt(q1[j]), n2 = sqrt(q2[j]);
         const T sc1 = n1 > (double)a.Wx ? (T)((double)a.Wx / n1) : T(1);
         const T sc2 = n2 > (double)a.Ws ? (T)((double)a.Ws / n2) : T(1);
-        const T y1 = r1 * sc1, y2 = r2 * sc2;
-        dy1[j] = y1;
-        dy2[j] = y2;
-        if (ok) {
-          double d1 = fabs((double)y1 - (double)w1);
-          double d2 = fabs((double)y2 - (double)w2);
+        dy1[j] = r1[j] * sc1;
+        dy2[j] = r2[j] * sc2;
+        if (C.ox[j] >= 0 && ix < nx) {
+          double d1 = fabs((double)dy1[j] - (double)w1r[j]);
+          double d2 = fabs((double)dy2[j] - (double)w2r[j]);
           if (!(d1 <= 1.0e308)) d1 = INFINITY;
           if (!(d2 <= 1.0e308)) d2 = INFINITY;
           rmax = fmax(rmax, fmax(d1, d2));
@@ -839,11 +877,7 @@ __global__ __launch_bounds__(kSegThreads) void scan_fwd_kernel(SegArgs<T> a) {
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;
   DevCtl* ctl = a.ctl + tree;
   __shared__ double sred[kSegThreads];
-  __shared__ int s_last;
-  if (ctl->done) {  // this tree has stopped; the closing launch still counts it
-    if (a.last_level) seg_iteration_end(a, sred, &s_last);
-    return;
-  }
+  if (ctl->done) return;  // this tree has stopped
   const double m = scan_fwd_body<T, NB>(a, blockIdx.x, tree, ctl->iter, (T)ctl->beta,
                                         ctl->gamma, sred);
   if (threadIdx.x == 0) {
@@ -852,7 +886,6 @@ __global__ __launch_bounds__(kSegThreads) void scan_fwd_kernel(SegArgs<T> a) {
     else
       atomicMax(&ctl->res_bits, (unsigned long long)__double_as_longlong(m));
   }
-  if (a.last_level) seg_iteration_end(a, sred, &s_last);
 }
 
 template <typename T, int NB>

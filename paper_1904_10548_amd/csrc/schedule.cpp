@@ -136,6 +136,12 @@ std::vector<LevelPlan> levels_from_env(const TreeHost& t, const char* spec) {
   return out;
 }
 
+LevelPlan stage_plan(const TreeHost& t, int s, int g) {
+  std::vector<int> lo, hi;
+  stage_groups(t, s, std::max(1, g), lo, hi);
+  return LevelPlan{s, t.N - 1, std::max(1, g), 0, (int)lo.size(), 0.0};
+}
+
 // Node ranges of every workgroup of a level, stage by stage.
 std::vector<std::pair<int, int>> level_ranges(const TreeHost& t, const LevelPlan& L, int& wmax) {
   const int nst = L.s_end - L.s_begin + 1;

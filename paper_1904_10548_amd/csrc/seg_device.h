@@ -139,63 +139,5 @@ __device__ __forceinline__ void csr_to_lds(const int* row, const int* col, const
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Closing protocol of the last forward launch of an iteration: every workgroup
-// (those of trees that have stopped too) checks in, and the last one to do so
-// ends the iteration of every tree still running: residual max into the
-// history, stop tests, theta / beta (or, in the power iteration of one tree,
-// the norm of the new iterate).
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ inline void seg_iteration_end(const SegArgs<T>& a, double* sred, int* s_last) {
-  const int tid = threadIdx.x;
-  __threadfence();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(a.counter, 1u);
-    *s_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!*s_last) return;
-  __threadfence();
-  if (a.mode == 1) {
-    double acc = 0.0;
-    for (int i = tid; i < a.part_total; i += kSegThreads) acc += a.part[i];
-    const double tot = block_sum512(acc, sred);
-    if (tid == 0) {
-      DevCtl* c = a.ctl;
-      const double L = sqrt(tot);
-      c->L = L;
-      c->pw_scale = L > 0.0 ? 1.0 / L : 0.0;
-      c->iter = c->iter + 1;
-      *a.counter = 0u;
-    }
-    return;
-  }
-  for (int k = tid; k < a.ntrees; k += kSegThreads) {
-    DevCtl* c = a.ctl + k;
-    if (c->done) continue;
-    const int it = c->iter;
-    const double res = __longlong_as_double((long long)atomicExch(&c->res_bits, 0ull));
-    a.hist[(size_t)k * a.hist_stride + it] = res;
-    c->last_res = res;
-    c->iter = it + 1;
-    if (!(res < INFINITY)) {
-      c->numeric = 1;
-      c->done = 1;
-    } else if (c->tol > 0.0 && res <= c->tol) {
-      c->converged = 1;
-      c->done = 1;
-    } else if (it + 1 >= c->max_iter) {
-      c->done = 1;
-    }
-    const double th = c->theta;
-    const double t2 = th * th;
-    const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
-    c->theta_prev = th;
-    c->theta = thn;
-    c->beta = thn * (1.0 / th - 1.0);
-  }
-  if (tid == 0) *a.counter = 0u;
-}
 
 }  // namespace tapg

@@ -865,11 +865,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
   DevCtl* ctl = a.ctl + tree;
   __shared__ double sred[kSegThreads];
-  __shared__ int s_last;
-  if (ctl->done) {  // this tree has stopped; the closing launch still counts it
-    if (a.last_level) seg_iteration_end(a, sred, &s_last);
-    return;
-  }
+  if (ctl->done) return;  // this tree has stopped
   const double m = seg_fwd_body<T, NB, PROJ>(a, blockIdx.x, tree, ctl->iter, (T)ctl->beta,
                                              ctl->gamma, sred);
   if (threadIdx.x == 0) {
@@ -878,7 +874,6 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
     else
       atomicMax(&ctl->res_bits, (unsigned long long)__double_as_longlong(m));
   }
-  if (a.last_level) seg_iteration_end(a, sred, &s_last);
 }
 
 // ---------------------------------------------------------------------------

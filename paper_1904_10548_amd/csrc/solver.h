@@ -73,6 +73,7 @@ struct tapg_solver_s {
   std::map<std::vector<uint64_t>, tapg::Batch> batches;
   std::map<std::string, std::vector<tapg::LevelPlan>> tuned;  // autotuned schedule per tree shape
   std::map<std::string, bool> tuned_scan;  // autotuned sweep form per tree shape
+  std::map<std::string, int> tuned_fwd;    // autotuned forward grouping (scan form)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool use_graph = true;
   // structure of the network and weights (detected at creation)
@@ -114,6 +115,8 @@ std::vector<LevelPlan> plan_levels(const TreeHost& t, int nbmax, double node_us,
 std::vector<std::vector<LevelPlan>> candidate_plans(const TreeHost& t, int nbmax, double node_us);
 std::vector<LevelPlan> levels_from_env(const TreeHost& t, const char* spec);
 std::vector<std::pair<int, int>> level_ranges(const TreeHost& t, const LevelPlan& L, int& wmax);
+// One level over the stages [s, N-1] with groups of g consecutive nodes of stage s.
+LevelPlan stage_plan(const TreeHost& t, int s, int g);
 
 // A tree in flight in the serving loop: its iterate state lives in its own
 // slot between forests (both dual buffers, control block, history).

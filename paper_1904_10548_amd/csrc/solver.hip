@@ -358,7 +358,6 @@ SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mod
   a.ntrees = sl.ntrees;
   a.hist_stride = sl.hist_cap;
   a.pq_stride = S->LDX + S->LDU;
-  a.counter = sl.d_counter;
   a.wgtree = nullptr;
   return a;
 }
@@ -394,7 +393,6 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
         a.wgtree = L.d_wgtree;
         a.part_base = bases[l];
         a.nch = L.nch;
-        a.last_level = (pass == 1 && (full || l == nl - 1)) ? 1 : 0;
         a.own = full ? sl.d_own : nullptr;
         if (full) {
           a.part_base = 0;
@@ -408,6 +406,20 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
           tc->next++;
         }
       }
+    }
+    // the iteration's end in a launch of its own: the forward workgroups left
+    // their residual maxima (power iteration: partial sums) in device memory
+    if (mode == 0) {
+      if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
+      launch_iter_end(sl.d_ctl, sl.d_hist, sl.ntrees, sl.hist_cap, st);
+      if (tc) {
+        (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
+        tc->kind.push_back(2);
+        tc->next++;
+      }
+    } else {
+      launch_power_end(sl.d_ctl, (const double*)sl.d_part,
+                       sl.fwd_full.n_wg > 0 ? sl.fwd_full.n_wg : sl.part_total, st);
     }
     return;
   }
@@ -440,7 +452,7 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
   }
   if (mode == 0) {
     if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
-    launch_iter_end(sl.d_ctl, sl.d_hist, st);
+    launch_iter_end(sl.d_ctl, sl.d_hist, 1, 0, st);
     if (tc) {
       (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
       tc->kind.push_back(2);
@@ -451,8 +463,8 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
 }
 
 static int launches_per_iter(const Slot& sl) {
-  if (sl.segmented)
-    return (int)sl.levels.size() + (sl.fwd_full.n_wg > 0 ? 1 : (int)sl.levels.size());
+  if (sl.segmented)  // backward levels, forward launches, iteration end
+    return (int)sl.levels.size() + (sl.fwd_full.n_wg > 0 ? 1 : (int)sl.levels.size()) + 1;
   return 2 * sl.N + 1;
 }
 
@@ -514,7 +526,6 @@ bool chain_usable(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
     a.wgtree = nullptr;
     a.part_base = base[l];
     a.nch = L.nch;
-    a.last_level = 0;
     lev[l] = a;
     base[l + 1] = base[l] + L.n_wg;
     int wmax = 0;
@@ -912,7 +923,7 @@ void dev_free_slot(Slot& sl) {
   dfree(sl.d_P0); dfree(sl.d_P1);
   dfree(sl.d_Y0); dfree(sl.d_Y1); dfree(sl.d_lam); dfree(sl.d_j); dfree(sl.d_u); dfree(sl.d_x);
   dfree(sl.d_kperp); dfree(sl.d_zb); dfree(sl.d_zr);
-  dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part); dfree(sl.d_counter);
+  dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part);
   free_chain(sl);
   for (auto& L : sl.levels) {
     dfree(L.d_ranges);
@@ -1152,7 +1163,8 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
   sl.levels = std::move(levels);
   sl.plans = plans;
   free_fwd_full(sl);
-  if (sl.scan) build_fwd_full(S, t, sl, plans.back());
+  if (sl.scan)
+    build_fwd_full(S, t, sl, sl.fwd_group > 0 ? stage_plan(t, t.N - 1, sl.fwd_group) : plans.back());
   free_chain(sl);
   sl.part_total = ptot;
   sl.segmented = true;
@@ -1171,6 +1183,10 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
     {  // sweep form: the tuned one for this shape, else the solver's default
       auto ts = S->tuned_scan.find(shape_key(t));
       sl.scan = S->scan && (ts == S->tuned_scan.end() ? S->scan_default : ts->second);
+      auto tf = S->tuned_fwd.find(shape_key(t));
+      const char* fg = std::getenv("TAPG_FWD_GROUP");
+      sl.fwd_group = (fg && fg[0]) ? std::max(0, std::atoi(fg))
+                                   : (tf == S->tuned_fwd.end() ? 0 : tf->second);
     }
     sl.N = t.N;
     sl.elem = S->fp32 ? sizeof(float) : sizeof(double);
@@ -1203,8 +1219,6 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       sl.ntrees = t.ntrees;
       sl.d_pq = dalloc((size_t)t.ntrees * (LDX + LDU));
       sl.d_pq64 = dmalloc<double>((size_t)t.ntrees * (LDX + LDU));
-      sl.d_counter = dmalloc<unsigned>(1);
-      TAPG_HIP(hipMemsetAsync(sl.d_counter, 0, sizeof(unsigned), st));
       sl.d_Y0 = dalloc((size_t)K * LDY);
       sl.d_Y1 = dalloc((size_t)K * LDY);
       sl.d_lam = dalloc((size_t)K * LDX);
@@ -1787,9 +1801,28 @@ double autotune_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters, i
     }
   }
   sl.scan = bscan;
+  // the scan form's forward launch: the bottom level's workgroups, or groups of
+  // 1, 2 or 4 last-stage nodes (more workgroups, each walking its ancestors)
+  int bfg = sl.fwd_group;  // the grouping the plans were timed with
+  if (bscan) {
+    const int fg0 = sl.fwd_group;
+    for (int fg : {0, 1, 2, 4}) {
+      if (fg == fg0) continue;
+      sl.fwd_group = fg;
+      build_levels(S, t, sl, cands[bi]);
+      const double ms = time_levels<T>(S, t, sl, iters);
+      if (ncand) ++*ncand;
+      if (ms < best) {
+        best = ms;
+        bfg = fg;
+      }
+    }
+  }
+  sl.fwd_group = bfg;
   build_levels(S, t, sl, cands[bi]);
   S->tuned[shape_key(t)] = cands[bi];
   S->tuned_scan[shape_key(t)] = bscan;
+  S->tuned_fwd[shape_key(t)] = bfg;
   sl.has_dual = false;  // the timing runs overwrote the iterates
   sl.has_result = false;
   return best;

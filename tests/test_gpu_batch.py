@@ -26,7 +26,7 @@ SHAPES = [(2, 4), (3, 3), ("irregular", 3, 20), (1, 1), (2, 8)]
 
 @pytest.fixture(autouse=True)
 def _default_schedule():
-    for k in ("TAPG_LEVELS", "TAPG_PROJ", "TAPG_CHAIN", "TAPG_SCAN"):
+    for k in ("TAPG_LEVELS", "TAPG_PROJ", "TAPG_CHAIN", "TAPG_SCAN", "TAPG_FWD_GROUP"):
         os.environ.pop(k, None)
     os.environ["TAPG_USE_GRAPH"] = "1"
     os.environ["TAPG_SEGMENTS"] = "1"
@@ -46,11 +46,18 @@ def _gamma_for(batch):
     return 0.9 / max(Ls)
 
 
-def test_batch_fixed_iterations_matches_oracle_per_tree():
+@pytest.mark.parametrize("scan,fwd_group", [(None, None), ("1", None), ("1", "1")])
+def test_batch_fixed_iterations_matches_oracle_per_tree(scan, fwd_group):
+    """Every tree of a forest against its own oracle run: the default form, the
+    scan form, and the scan form's forward launch on one leaf per workgroup."""
+    if scan:
+        os.environ["TAPG_SCAN"] = scan
+    if fwd_group:
+        os.environ["TAPG_FWD_GROUP"] = fwd_group
     batch = tiny_batch(SHAPES)
     gamma = _gamma_for(batch)
     iters = 300
-    say("batch fixed", [P.tree.K for P in batch], "iters", iters)
+    say("batch fixed", [P.tree.K for P in batch], "iters", iters, "scan", scan, "fwd", fwd_group)
     with make_solver(batch[0], gamma=gamma, tol=0.0, max_iter=iters, check_every=64) as S:
         trees = [add_tree(S, P) for P in batch]
         st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
@@ -174,7 +181,9 @@ def test_autotuned_schedule_keeps_parity():
     assert nc_b >= 1 and nc_1 >= 1 and ms_b > 0 and ms_1 > 0
     # both sweep forms are candidates where the scan form applies (A = I, W_u = w I)
     assert form_b[0] in ("scan", "projector") and form_1[0] in ("scan", "projector")
-    assert nc_b % 2 == 0 and form_b[1] >= 1
+    # every schedule candidate in both forms, then (scan form chosen) three
+    # further groupings of its forward launch
+    assert (nc_b - (3 if form_b[0] == "scan" else 0)) % 2 == 0 and form_b[1] >= 1
     for P, r in zip(batch, res):
         ref = O.apg(P, gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
         J = O.primal_cost(P, ref.u, ref.x)

@@ -43,12 +43,17 @@ def _oracle_run(P, gamma, iters, tol=None, factors=None):
     return O.apg(P, gamma, f, iters, tol=tol)
 
 
-def _schedule_env(graph=True, segments=True, levels=None, proj=True, chain=False, scan=True):
+def _schedule_env(graph=True, segments=True, levels=None, proj=True, chain=False, scan=True,
+                  fwd_group=0):
     os.environ["TAPG_USE_GRAPH"] = "1" if graph else "0"
     os.environ["TAPG_SEGMENTS"] = "1" if segments else "0"
     os.environ["TAPG_PROJ"] = "1" if proj else "0"
     os.environ["TAPG_CHAIN"] = "1" if chain else "0"
     os.environ["TAPG_SCAN"] = "1" if scan else "0"
+    if fwd_group:
+        os.environ["TAPG_FWD_GROUP"] = str(fwd_group)
+    else:
+        os.environ.pop("TAPG_FWD_GROUP", None)
     if levels:
         os.environ["TAPG_LEVELS"] = levels
     else:
@@ -56,10 +61,11 @@ def _schedule_env(graph=True, segments=True, levels=None, proj=True, chain=False
 
 
 def _compare_fixed(P, gamma, iters, precision=tapg.TAPG_FP64, check_every=50, graph=True,
-                   segments=True, levels=None, proj=True, chain=False, scan=True):
-    _schedule_env(graph, segments, levels, proj, chain, scan)
+                   segments=True, levels=None, proj=True, chain=False, scan=True, fwd_group=0):
+    _schedule_env(graph, segments, levels, proj, chain, scan, fwd_group)
     say(P.name, "K", P.tree.K, "iters", iters, "prec", precision, "graph", graph,
-        "segments", segments, "levels", levels, "proj", proj, "chain", chain, "scan", scan)
+        "segments", segments, "levels", levels, "proj", proj, "chain", chain, "scan", scan,
+        "fwd_group", fwd_group)
     with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=check_every,
                      precision=precision) as S:
         t = add_tree(S, P)
@@ -108,15 +114,16 @@ def test_small_500_iterations_fp64(graph, segments, chain, scan):
     assert np.abs(u0 - ref.u[0]).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())
 
 
-@pytest.mark.parametrize("scan", [True, False])
-def test_wide_ragged_tree_scan_and_segment_fp64(scan):
+@pytest.mark.parametrize("scan,fwd_group", [(True, 0), (True, 1), (True, 4), (False, 0)])
+def test_wide_ragged_tree_scan_and_segment_fp64(scan, fwd_group):
     """Irregular branching up to 40 children per node: the scan form (children
-    of a workgroup's last stage in the level below, ragged node ranges) and the
-    segment form."""
+    of a workgroup's last stage in the level below, ragged node ranges; the
+    forward launch on the bottom level's workgroups or on groups of 1 or 4
+    leaves, each walking its ancestors) and the segment form."""
     P = tiny_problem(N=7, irregular=True, seed=12, max_children=40, max_width=3000)
     sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
     gamma = 0.9 / O.lipschitz_power(P, sf, 200)
-    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 80, scan=scan)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 80, scan=scan, fwd_group=fwd_group)
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 80)
 
 
@@ -148,18 +155,21 @@ def test_wide_ragged_tree_fp64_and_fp32():
     assert abs(r32.cost - J) <= 1e-4 * max(1.0, abs(J))
 
 
-@pytest.mark.parametrize("levels,fp32,proj,chain,scan",
-                         [(None, False, True, False, True),
-                          (None, False, True, True, False),
-                          (None, False, True, False, False),
-                          (None, False, False, False, False),
-                          ("0:1,2:2,4:1", False, True, False, True),
-                          ("0:1,2:2,4:1", False, True, True, False),
-                          ("0:1,2:1,4:1,6:2,15:4", False, True, False, True),
-                          ("0:1,1:1,3:2,5:2", True, True, False, True),
-                          ("0:1,1:1,3:2,5:2", True, True, True, False),
-                          ("0:1,1:1,3:2,5:2", True, False, False, False)])
-def test_dwn128_fixed_iterations(levels, fp32, proj, chain, scan):
+@pytest.mark.parametrize("levels,fp32,proj,chain,scan,fwd_group",
+                         [(None, False, True, False, True, 1),
+                          (None, True, True, False, True, 2),
+                          (None, False, True, False, True, 0),
+                          (None, False, True, True, False, 0),
+                          (None, False, True, False, False, 0),
+                          (None, False, False, False, False, 0),
+                          ("0:1,2:2,4:1", False, True, False, True, 0),
+                          ("0:1,2:2,4:1", False, True, True, False, 0),
+                          ("0:1,2:1,4:1,6:2,15:4", False, True, False, True, 0),
+                          ("0:1,2:1,4:1,6:2,15:4", False, True, False, True, 1),
+                          ("0:1,1:1,3:2,5:2", True, True, False, True, 0),
+                          ("0:1,1:1,3:2,5:2", True, True, True, False, 0),
+                          ("0:1,1:1,3:2,5:2", True, False, False, False, 0)])
+def test_dwn128_fixed_iterations(levels, fp32, proj, chain, scan, fwd_group):
     """Full-size network and tree (K = 2429): 40 iterations, every element;
     planned schedule and forced multi-level / grouped schedules, in scan form,
     segment form and as one persistent launch."""
@@ -169,12 +179,14 @@ def test_dwn128_fixed_iterations(levels, fp32, proj, chain, scan):
     if fp32:  # FP32 sweeps on a five-level schedule with groups of two
         st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40,
                                                          precision=tapg.TAPG_FP32, levels=levels,
-                                                         proj=proj, chain=chain, scan=scan)
+                                                         proj=proj, chain=chain, scan=scan,
+                                                         fwd_group=fwd_group)
         J = O.primal_cost(P, ref.u, ref.x)
         assert abs(res.cost - J) <= 1e-4 * max(1.0, abs(J))
         return
     st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=40, levels=levels,
-                                                     proj=proj, chain=chain, scan=scan)
+                                                     proj=proj, chain=chain, scan=scan,
+                                                     fwd_group=fwd_group)
     _assert_fp64_parity(P, res, u, x, y, hist, ref, 40)
 
 

@@ -23,6 +23,7 @@ def _default_schedule():
     os.environ.pop("TAPG_PROJ", None)
     os.environ.pop("TAPG_CHAIN", None)
     os.environ.pop("TAPG_SCAN", None)
+    os.environ.pop("TAPG_FWD_GROUP", None)
     os.environ["TAPG_USE_GRAPH"] = "1"
     os.environ["TAPG_SEGMENTS"] = "1"
     yield
