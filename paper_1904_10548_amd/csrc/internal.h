@@ -165,6 +165,7 @@ struct Slot {
     int nch;  // most children of one workgroup below the level's last stage
     int2* d_ranges;
     int* d_wgtree;  // tree of each workgroup (forests only)
+    int2* d_wgx = nullptr;  // children of the last stage, parents of the first
   };
   std::vector<Level> levels;
   // Scan form: the forward sweep in one launch over stages 0..N-1, each

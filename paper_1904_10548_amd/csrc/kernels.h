@@ -59,6 +59,10 @@ struct SegArgs {
   int nnzB;        // nonzeros of B (= of B')
   int nch;         // backward: most children of one workgroup below the level's last stage
   const int2* ranges;  // [n_wg][nst] node range [lo, hi) per stage
+  // [n_wg][2] per workgroup: the children [cb, ce) of its last stage's nodes
+  // (none at the last stage of the tree), then the parents of its first
+  // stage's first and last node (-1 at the root)
+  const int2* wgx;
   const int* anc;
   const int* cbeg;
   const int* cend;

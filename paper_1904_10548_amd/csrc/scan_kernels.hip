@@ -223,25 +223,43 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
   int* eCol = reinterpret_cast<int*>(smem_raw + L.ecol);
   T* eVal = reinterpret_cast<T*>(smem_raw + L.eval);
   const bool kids_below = se + 1 < a.N;
-  int cb = 0, ce = 0;  // children of the level's last stage (in the level below)
+  // u-elements of a chunk: e = tid + 512 j -> node-stage e / 128, component
+  // e % 128 = tid % 128 for every j; x-elements likewise with 64.
+  const int iu = tid & (kSU - 1);
+  const int ix = tid & (kSX - 1);
+  // Children of the level's last stage (in the level below): lambda, P and
+  // parent of a batch of kCN of them, loaded unmasked (clamped indices) and
+  // masked where stored.  The first batch flies with the first chunk's loads.
+  int cb = 0, ce = 0;
+  T bl[kQX], bp[kQU];
+  int ba = 0;
+  auto load_bnd = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < kQX; ++j) {
+      const int c = c0 + (tid + j * kSegThreads) / kSX;
+      bl[j] = ldc(a.lam, (size_t)c * LDX + ix, c < ce && ix < nx);
+    }
+#pragma unroll
+    for (int j = 0; j < kQU; ++j) {
+      const int c = c0 + (tid + j * kSegThreads) / kSU;
+      bp[j] = ldc((const T*)a.jv, (size_t)c * kSU + iu, c < ce && iu < nu);
+    }
+    ba = ldc(a.anc, (size_t)(c0 + tid), tid < kCN && c0 + tid < ce);
+  };
+  if (kids_below) {
+    const int2 kc = a.wgx[2 * wg];
+    cb = kc.x;
+    ce = kc.y;
+  }
   {
     const int2* rg = a.ranges + (size_t)wg * a.nst;
     for (int i = tid; i < a.nst; i += kSegThreads) sRg[i] = rg[i];
     csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
     csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, ns, a.nnzG, gRow, gCol, gVal);
     csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
-    if (kids_below) {
-      const int2 rl = rg[a.nst - 1];
-      cb = a.cbeg[rl.x];
-      ce = a.cend[rl.y - 1];
-    }
   }
   __syncthreads();
 
-  // u-elements of a chunk: e = tid + 512 j -> node-stage e / 128, component
-  // e % 128 = tid % 128 for every j; x-elements likewise with 64.
-  const int iu = tid & (kSU - 1);
-  const int ix = tid & (kSX - 1);
   FixRow<T, 2> btrow, etrow;
   btrow.load(sRow, sCol, sVal, iu, iu < nu);
   etrow.load(eRow, eCol, eVal, iu, iu < nu);
@@ -462,24 +480,6 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
     pcs = cs;
   };
 
-  // A batch of the children: lambda, P and parent, loaded unmasked (clamped
-  // indices) and masked where stored.  The first batch is issued ahead of the
-  // first chunk's loads, so that waiting for it does not wait for those.
-  T bl[kQX], bp[kQU];
-  int ba = 0;
-  auto load_bnd = [&](int c0) {
-#pragma unroll
-    for (int j = 0; j < kQX; ++j) {
-      const int c = c0 + (tid + j * kSegThreads) / kSX;
-      bl[j] = ldc(a.lam, (size_t)c * LDX + ix, c < ce && ix < nx);
-    }
-#pragma unroll
-    for (int j = 0; j < kQU; ++j) {
-      const int c = c0 + (tid + j * kSegThreads) / kSU;
-      bp[j] = ldc((const T*)a.jv, (size_t)c * kSU + iu, c < ce && iu < nu);
-    }
-    ba = ldc(a.anc, (size_t)(c0 + tid), tid < kCN && c0 + tid < ce);
-  };
   if (kids_below) load_bnd(cb);
   Pre PA, PB;
   load_chunk(0, PA);  // in flight while the children of the last stage are summed
@@ -573,9 +573,9 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
       sBnd[3 * kSU + i] = gam * ldm(a.umin, i, i < nu);
       sBnd[4 * kSU + i] = gam * ldm(a.umax, i, i < nu);
     }
-    const int2 r0 = rg[0];
-    par0 = a.anc[r0.x];
-    parl = a.anc[r0.y - 1];
+    const int2 pp = a.wgx[2 * wg + 1];
+    par0 = pp.x;
+    parl = pp.y;
   }
   __syncthreads();
   const int iu = tid & (kSU - 1);

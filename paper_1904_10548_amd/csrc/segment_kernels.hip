@@ -264,9 +264,9 @@ __device__ __forceinline__ void seg_bwd_body(const SegArgs<T>& a, int wg, int it
   T* sLn = sL1;  // this stage's lambda
   int lo_c = 0;  // first child node held in LDS
   if (s + 1 < a.N) {  // children of the level's last stage: written by the level below
-    const int2 rr = sRg[s - a.s_begin];
-    lo_c = a.cbeg[rr.x];
-    const int nc = a.cend[rr.y - 1] - lo_c;
+    const int2 kc = a.wgx[2 * wg];
+    lo_c = kc.x;
+    const int nc = kc.y - lo_c;
     for (int idx = tid; idx < nc * LDX; idx += kSegThreads) {
       const int b = idx / LDX, i = idx - b * LDX;
       sLc[idx] = i < nx ? a.lam[(size_t)(lo_c + b) * LDX + i] : T(0);
@@ -586,10 +586,10 @@ __device__ __forceinline__ double seg_fwd_body(const SegArgs<T>& a, int wg, int 
   T* sXn = sX1;
   int lo_p = 0, np = 0;
   {  // parents of the first stage come from global memory (or p, q at the root)
-    const int2 rr = sRg[0];
-    const int par0 = a.anc[rr.x];
+    const int2 pp = a.wgx[2 * wg + 1];
+    const int par0 = pp.x;
     lo_p = par0 >= 0 ? par0 : 0;
-    np = par0 >= 0 ? a.anc[rr.y - 1] - par0 + 1 : 1;
+    np = par0 >= 0 ? pp.y - par0 + 1 : 1;
     for (int idx = tid; idx < NB * LDU; idx += kSegThreads) {
       const int b = idx / LDU, i = idx - b * LDU;
       T v = T(0);

@@ -390,6 +390,7 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
         a.s_end = L.s_end;
         a.nst = L.s_end - L.s_begin + 1;
         a.ranges = L.d_ranges;
+        a.wgx = L.d_wgx;
         a.wgtree = L.d_wgtree;
         a.part_base = bases[l];
         a.nch = L.nch;
@@ -523,6 +524,7 @@ bool chain_usable(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
     a.s_end = L.s_end;
     a.nst = L.s_end - L.s_begin + 1;
     a.ranges = L.d_ranges;
+    a.wgx = L.d_wgx;
     a.wgtree = nullptr;
     a.part_base = base[l];
     a.nch = L.nch;
@@ -909,6 +911,7 @@ void free_chain(Slot& sl);
 void free_fwd_full(Slot& sl) {
   dfree(sl.fwd_full.d_ranges);
   dfree(sl.fwd_full.d_wgtree);
+  dfree(sl.fwd_full.d_wgx);
   dfree(sl.d_own);
   sl.fwd_full = Slot::Level{0, -1, 0, 1, 0, nullptr, nullptr};
   sl.d_own = nullptr;
@@ -928,6 +931,7 @@ void dev_free_slot(Slot& sl) {
   for (auto& L : sl.levels) {
     dfree(L.d_ranges);
     dfree(L.d_wgtree);
+    dfree(L.d_wgx);
   }
   sl.levels.clear();
   free_fwd_full(sl);
@@ -1056,6 +1060,20 @@ void free_chain(Slot& sl) {
 // the ancestors of its nodes at every stage above the level (a contiguous
 // range no wider than the one below, by the breadth-first numbering), and the
 // first node it owns per stage (the nodes past the previous workgroup's range).
+// Per workgroup of a level whose node ranges are rg ([nw][nst], stages
+// s_begin..s_end): the children [cb, ce) of its last stage's nodes and the
+// parents of its first stage's first and last node (the kernels' SegArgs::wgx).
+static int2* upload_wgx(const TreeHost& t, const std::vector<int2>& rg, int nw, int nst,
+                        int s_end, hipStream_t st) {
+  std::vector<int2> x((size_t)2 * nw);
+  for (int w = 0; w < nw; ++w) {
+    const int2 f = rg[(size_t)w * nst], l = rg[(size_t)w * nst + nst - 1];
+    x[2 * w] = s_end + 1 < t.N ? make_int2(t.cbeg[l.x], t.cend[l.y - 1]) : make_int2(0, 0);
+    x[2 * w + 1] = make_int2(t.anc[f.x], t.anc[f.y - 1]);
+  }
+  return upload(x, st);
+}
+
 void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPlan& B) {
   hipStream_t st = S->stream;
   int wmax = 0;
@@ -1085,6 +1103,7 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
     throw Fail{TAPG_EINVAL, "forward launch needs " + std::to_string(lds) + " bytes of LDS"};
   try {
     L.d_ranges = upload(rg, st);
+    L.d_wgx = upload_wgx(t, rg, nw, N, N - 1, st);
     sl.d_own = upload(own, st);
     if (t.ntrees > 1) {
       std::vector<int> wt(nw, 0);
@@ -1098,6 +1117,7 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
     }
   } catch (...) {
     dfree(L.d_ranges);
+    dfree(L.d_wgx);
     dfree(sl.d_own);
     sl.d_own = nullptr;
     throw;
@@ -1137,6 +1157,7 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
                                     std::to_string(S->lds_limit) + ")"};
       L.d_ranges = upload(rg, st);
       levels.push_back(L);
+      levels.back().d_wgx = upload_wgx(t, rg, P.n_wg, nst, P.s_end, st);
       if (t.ntrees > 1) {  // the tree of each workgroup, from its first node
         std::vector<int> wt(P.n_wg, 0);
         for (int w = 0; w < P.n_wg; ++w) {
@@ -1153,12 +1174,14 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
     for (auto& L : levels) {
       dfree(L.d_ranges);
       dfree(L.d_wgtree);
+      dfree(L.d_wgx);
     }
     throw;
   }
   for (auto& L : sl.levels) {
     dfree(L.d_ranges);
     dfree(L.d_wgtree);
+    dfree(L.d_wgx);
   }
   sl.levels = std::move(levels);
   sl.plans = plans;
