@@ -146,11 +146,13 @@ def main():
     lipschitz_s = time.perf_counter() - t0
     # schedule and sweep form picked by the autotuner (setup, not timed)
     t0 = time.perf_counter()
-    tune_ms, tune_nc = (None, 0) if args.no_autotune else tapg.tapg_autotune(S.h, [tree], 20)
+    tune_ms, tune_nc = (None, 0) if args.no_autotune else tapg.tapg_autotune(S.h, [tree], 50)
     tune_s = time.perf_counter() - t0
     if args.no_autotune:
         S.solve(tree, P.p, P.q)  # the slot exists once solved
     form, n_bwd = tapg.tapg_sweep_form(S.h, [tree])
+    spec = tapg.tapg_schedule_spec(S.h, [tree])
+    print(f"[bench] schedule {spec}", file=sys.stderr, flush=True)
     print(f"[bench] {args.config} K={P.tree.K} L={L:.6g} factor {factor_s:.3f}s "
           f"power {lipschitz_s:.3f}s autotune {tune_s:.3f}s: {form} form, {n_bwd} backward "
           f"launches, {tune_ms} ms/iter", file=sys.stderr, flush=True)
@@ -182,17 +184,22 @@ def main():
     kt = None
     if not args.no_kernel_timing:
         # Device time of every sweep-kernel launch, HIP events on the solver's
-        # stream, over one more solve of the same workload.
+        # stream, over one more solve of the same workload; each launch's event
+        # pair also reads the dispatch cost of an empty launch (measured the
+        # same way), which is taken off.
         tapg.tapg_kernel_timing(S.h, True)
         S.solve(tree, P.p, P.q)
         kt = tapg.tapg_kernel_times(S.h)
         tapg.tapg_kernel_timing(S.h, False)
+        pair_us = tapg.tapg_event_pair_overhead(S.h)
         kinds = {}
         for kind in ("bwd", "fwd"):
-            ms, n = kt[kind]
+            ms_raw, n = kt[kind]
+            ms = ms_raw - n * pair_us * 1e-3
             b_iter = sweep_bytes(net.nx, net.nu, elem, P.tree.K, n_blocks, kind, form)
             its = iters  # one timed solve of the same workload
-            kinds[kind] = dict(ms=ms, launches=n, bytes=b_iter * its, avg_us=1e3 * ms / max(n, 1))
+            kinds[kind] = dict(ms=ms, launches=n, bytes=b_iter * its, avg_us=1e3 * ms / max(n, 1),
+                               avg_us_raw=1e3 * ms_raw / max(n, 1))
         dom = max(kinds, key=lambda k: kinds[k]["ms"])
         d = kinds[dom]
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
@@ -204,8 +211,12 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "traffic_bytes_per_launch": tb[dom] if traffic is not None else None,
                 "kernel": f"{kernel_prefix(form)}_{dom}_kernel", "avg_launch_us": round(d["avg_us"], 3),
+                "avg_launch_us_event_pairs": round(d["avg_us_raw"], 3),
+                "event_pair_overhead_us": round(pair_us, 3),
                 "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1),
-                "other": {k: {"avg_launch_us": round(v["avg_us"], 3), "launches": v["launches"],
+                "other": {k: {"avg_launch_us": round(v["avg_us"], 3),
+                              "avg_launch_us_event_pairs": round(v["avg_us_raw"], 3),
+                              "launches": v["launches"],
                               "ms": round(v["ms"], 3)} for k, v in kinds.items()},
                 "iteration_end_ms": round(kt["end"][0], 3)}
 
@@ -240,8 +251,8 @@ def main():
         "factor_step_s": round(factor_s, 4),
         "factor_blocks": n_blocks,
         "lipschitz_s": round(lipschitz_s, 4),
-        "schedule": {"form": form, "bwd_launches": n_bwd, "autotune_s": round(tune_s, 3),
-                     "autotune_candidates": tune_nc,
+        "schedule": {"form": form, "bwd_launches": n_bwd, "spec": spec,
+                     "autotune_s": round(tune_s, 3), "autotune_candidates": tune_nc,
                      "autotune_ms_per_iter": None if tune_ms is None else round(tune_ms, 5)},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -276,6 +287,7 @@ def main_batch(args, ds, tapg):
     tune_ms, tune_nc = tapg.tapg_autotune(S.h, trees, 10)
     tune_s = time.perf_counter() - t0
     form, n_bwd = tapg.tapg_sweep_form(S.h, trees)
+    spec = tapg.tapg_schedule_spec(S.h, trees)
     elem = 8 if prec == tapg.TAPG_FP64 else 4
     forest_bytes = sum(sweep_bytes(net.nx, net.nu, elem, K_tot, 1, kind, form) for kind in ("bwd", "fwd"))
     print(f"[bench] batch64: 64 trees, {K_tot} nodes, power {lipschitz_s:.3f}s, autotune "
@@ -332,7 +344,8 @@ def main_batch(args, ds, tapg):
         "lipschitz_s": round(lipschitz_s, 4),
         # one iteration of the whole forest (every tree running), as the
         # autotuner timed it with the schedule and form it kept
-        "schedule": {"form": form, "bwd_launches": n_bwd, "autotune_s": round(tune_s, 3),
+        "schedule": {"form": form, "bwd_launches": n_bwd, "spec": spec,
+                     "autotune_s": round(tune_s, 3),
                      "autotune_candidates": tune_nc, "forest_ms_per_iter": round(tune_ms, 5),
                      "forest_gb_per_iter": round(forest_bytes / 1e9, 4),
                      "forest_gbs": round(forest_bytes / (tune_ms * 1e-3) / 1e9, 1)},

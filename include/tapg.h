@@ -215,6 +215,11 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
  * device runs every level in one cooperative launch per chunk of iterations). */
 tapg_status tapg_kernel_timing(tapg_solver solver, int enable);
 tapg_status tapg_kernel_times(tapg_solver solver, double* ms, long long* launches);
+/* The dispatch cost that each timed launch above carries on top of its kernel:
+ * the median time (*us, microseconds) that a pair of events reads around a
+ * launch of known length (a 10 us wait) queued the same way, less that length.  Subtracting it per launch brings the
+ * timed averages close to a kernel trace's durations. */
+tapg_status tapg_event_pair_overhead(tapg_solver solver, double* us);
 
 /* Request server (the solve loop of a controller serving many requests,
  * Sec. 5's SmpcController::controlAction per request): a worker thread owns the
@@ -272,6 +277,17 @@ tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees
  * faster for the shape (measured: scan for a single 128-scenario tree, segment
  * for wide trees and forests).
  * TAPG_ESTATE before the first solve or autotune of that tree or batch. */
+/* The schedule of a tree (ntrees = 1) or of a batch's forest as its last
+ * solve or autotune left it, written to buf (cap bytes, NUL-terminated) as the
+ * environment settings that force it on a fresh solver, for instance
+ * "TAPG_SCAN=1 TAPG_LEVELS=0:1,2:1,5:1 TAPG_FWD_GROUP=1" (levels: first stage
+ * and workgroup group of each; forward group: last-stage nodes per forward
+ * workgroup of the scan form, 0 = the bottom level's workgroups) or
+ * "TAPG_SEGMENTS=0" (per-stage kernels).  TAPG_EINVAL if cap is too small,
+ * TAPG_ESTATE before the first solve or autotune of that tree or batch. */
+tapg_status tapg_schedule_spec(tapg_solver solver, int ntrees, const tapg_tree* trees, char* buf,
+                               int cap);
+
 #define TAPG_FORM_STAGES 0    /* per-stage kernels */
 #define TAPG_FORM_SEGMENT 1   /* segment kernels, stage factors in registers */
 #define TAPG_FORM_PROJECTOR 2 /* segment kernels, projector form of the factors */

@@ -526,29 +526,56 @@ tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees
   });
 }
 
+// The device slot of a tree (ntrees = 1) or of a batch's forest, once solved or tuned.
+static const Slot& solved_slot(tapg_solver solver, int ntrees, const tapg_tree* trees) {
+  need(trees, "trees");
+  if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
+  uint64_t uid = 0;
+  if (ntrees == 1) {
+    need(trees[0], "tree");
+    uid = trees[0]->h.uid;
+  } else {
+    std::vector<uint64_t> key(ntrees);
+    for (int k = 0; k < ntrees; ++k) {
+      need(trees[k], "tree");
+      key[k] = trees[k]->h.uid;
+    }
+    auto bit = solver->batches.find(key);
+    if (bit == solver->batches.end()) fail(TAPG_ESTATE, "this batch has not been solved or tuned");
+    uid = bit->second.forest.uid;
+  }
+  auto it = solver->slots.find(uid);
+  if (it == solver->slots.end()) fail(TAPG_ESTATE, "the tree has not been solved or tuned");
+  return it->second;
+}
+
+tapg_status tapg_schedule_spec(tapg_solver solver, int ntrees, const tapg_tree* trees, char* buf,
+                               int cap) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    need(buf, "buf");
+    const Slot& sl = solved_slot(solver, ntrees, trees);
+    std::string s;
+    if (!sl.segmented) {
+      s = "TAPG_SEGMENTS=0";
+    } else {
+      s = std::string("TAPG_SCAN=") + (sl.scan ? "1" : "0") + " TAPG_LEVELS=";
+      for (size_t l = 0; l < sl.plans.size(); ++l)
+        s += (l ? "," : "") + std::to_string(sl.plans[l].s_begin) + ":" +
+             std::to_string(sl.plans[l].group);
+      if (sl.scan) s += " TAPG_FWD_GROUP=" + std::to_string(sl.fwd_group);
+    }
+    if ((int)s.size() + 1 > cap) fail(TAPG_EINVAL, "buffer too small for the schedule");
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return TAPG_OK;
+  });
+}
+
 tapg_status tapg_sweep_form(tapg_solver solver, int ntrees, const tapg_tree* trees, int* form,
                             int* bwd_launches) {
   return guarded([&]() -> tapg_status {
     need(solver, "solver");
-    need(trees, "trees");
-    if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
-    uint64_t uid = 0;
-    if (ntrees == 1) {
-      need(trees[0], "tree");
-      uid = trees[0]->h.uid;
-    } else {
-      std::vector<uint64_t> key(ntrees);
-      for (int k = 0; k < ntrees; ++k) {
-        need(trees[k], "tree");
-        key[k] = trees[k]->h.uid;
-      }
-      auto bit = solver->batches.find(key);
-      if (bit == solver->batches.end()) fail(TAPG_ESTATE, "this batch has not been solved or tuned");
-      uid = bit->second.forest.uid;
-    }
-    auto it = solver->slots.find(uid);
-    if (it == solver->slots.end()) fail(TAPG_ESTATE, "the tree has not been solved or tuned");
-    const Slot& sl = it->second;
+    const Slot& sl = solved_slot(solver, ntrees, trees);
     int f = TAPG_FORM_STAGES;
     if (sl.segmented) f = sl.scan ? TAPG_FORM_SCAN : solver->proj ? TAPG_FORM_PROJECTOR : TAPG_FORM_SEGMENT;
     if (form) *form = f;
@@ -698,6 +725,16 @@ tapg_status tapg_kernel_timing(tapg_solver solver, int enable) {
     need(solver, "solver");
     if (solver->server_active) fail(TAPG_ESTATE, "the solver is driven by a server");
     dev_set_kernel_timing(solver, enable != 0);
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_event_pair_overhead(tapg_solver solver, double* us) {
+  return guarded([&]() -> tapg_status {
+    need(solver, "solver");
+    need(us, "us");
+    if (solver->server_active) fail(TAPG_ESTATE, "the solver is driven by a server");
+    *us = dev_event_pair_us(solver);
     return TAPG_OK;
   });
 }

@@ -178,6 +178,8 @@ void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
 // End of an iteration of ntrees trees (per-tree control blocks and histories).
 void launch_iter_end(DevCtl* c, double* hist, int ntrees, int hist_stride, hipStream_t st);
 void launch_power_end(DevCtl* c, const double* part, int n, hipStream_t st);
+// Holds the stream for `ticks` periods of the device wall clock (at most 50 ms).
+void launch_hold(long long ticks, hipStream_t st);
 template <typename T>
 void launch_data_step(int K, int nx, int nu, int nd, int LDX, int LDU, const int* stage,
                       const double* prob, const double* demand, const double* price,

@@ -96,6 +96,8 @@ struct tapg_solver_s {
   // optional per-launch timing of the sweep kernels (HIP events around each
   // launch; graphs are bypassed while it is on)
   bool time_kernels = false;
+  double hold_us = 2000.0;       // kernel timing: device hold ahead of a chunk's launches
+  double wall_clock_mhz = 100.0; // rate of the device wall clock
   bool server_active = false;  // a tapg_server drives this solver (other calls refused)
   std::vector<hipEvent_t> tev;      // pairs, reused per chunk
   // backward stages, forward stages, iteration end, persistent iteration
@@ -170,6 +172,7 @@ void dev_get_root_input(tapg_solver_s* S, Slot& sl, double* u0);
 void dev_set_dual(tapg_solver_s* S, Slot& sl, const double* y);
 int dev_get_history(tapg_solver_s* S, Slot& sl, double* h, int n);
 void dev_set_kernel_timing(tapg_solver_s* S, bool on);
+double dev_event_pair_us(tapg_solver_s* S);
 void dev_free_slot(Slot& sl);
 // Autotuner: time every candidate schedule of the tree (one tree) or of the
 // batch's forest (several trees) and keep the fastest, for this slot and for

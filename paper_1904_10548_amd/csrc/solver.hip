@@ -728,20 +728,25 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   }
   while (!chain) {
     if (timed) {
-      // one iteration per check so that launches after the stop are not timed
+      // The chunk's launches, each between two events, are queued behind a
+      // short hold on the device (sized from the previous chunk's host enqueue
+      // time), so that all of them are queued before the first starts and the
+      // event pairs time the kernels, not the host.  Launches of iterations
+      // after the stop (no-ops) are not counted.
+      TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+      TAPG_HIP(hipStreamSynchronize(st));
+      const int before = hc.iter;
+      launch_hold((long long)(std::min(S->hold_us, 50000.0) * S->wall_clock_mhz), st);
+      const auto h0 = std::chrono::steady_clock::now();
       TimedCursor tc;
-      for (int i = 0; i < chunk; ++i) {
-        enqueue_iteration<T>(S, sl, d, 0, &tc);
-        TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
-        TAPG_HIP(hipStreamSynchronize(st));
-        if (hc.done && hc.iter <= launched + i) {  // this iteration was a no-op
-          tc.kind.resize(tc.kind.size() - launches_per_iter(sl));
-          tc.next -= launches_per_iter(sl);
-          break;
-        }
-        if (hc.done) break;
-      }
+      for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0, &tc);
+      const double enq_us =
+          std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - h0).count();
+      S->hold_us = 1.5 * enq_us + 200.0;
       TAPG_HIP(hipGetLastError());
+      TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+      TAPG_HIP(hipStreamSynchronize(st));
+      tc.next = std::min(tc.next, std::max(0, hc.iter - before) * launches_per_iter(sl));
       for (int k = 0; k < tc.next; ++k) {
         float ms = 0.f;
         TAPG_HIP(hipEventElapsedTime(&ms, S->tev[2 * k], S->tev[2 * k + 1]));
@@ -840,6 +845,10 @@ void dev_init(tapg_solver_s* S) {
             hipSuccess &&
         lds > 0)
       S->lds_limit = (size_t)lds;
+    int khz = 0;  // the wall clock that the kernel-timing hold counts
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) == hipSuccess &&
+        khz > 0)
+      S->wall_clock_mhz = khz / 1000.0;
   }
   {  // structure of A and W_u; segment kernels need nx, nu <= 128
     const NetworkHost& h = S->net;
@@ -1976,6 +1985,37 @@ void dev_set_dual(tapg_solver_s* S, Slot& sl, const double* y) {
 }
 
 void dev_set_kernel_timing(tapg_solver_s* S, bool on) { S->time_kernels = on; }
+
+// Median time that an event pair reads around a launch of known length (a
+// 10 us hold) queued behind a hold, as the kernel-timing path queues its
+// launches, less those 10 us: the dispatch cost that every timed launch
+// carries on top of its kernel.
+double dev_event_pair_us(tapg_solver_s* S) {
+  TAPG_HIP(hipSetDevice(S->device));
+  hipStream_t st = S->stream;
+  constexpr int n = 64;
+  while (S->tev.size() < 2 * n) {
+    hipEvent_t e;
+    TAPG_HIP(hipEventCreate(&e));
+    S->tev.push_back(e);
+  }
+  launch_hold((long long)(2000.0 * S->wall_clock_mhz), st);
+  for (int i = 0; i < n; ++i) {
+    TAPG_HIP(hipEventRecord(S->tev[2 * i], st));
+    launch_hold((long long)(10.0 * S->wall_clock_mhz), st);
+    TAPG_HIP(hipEventRecord(S->tev[2 * i + 1], st));
+  }
+  TAPG_HIP(hipGetLastError());
+  TAPG_HIP(hipStreamSynchronize(st));
+  std::vector<double> us(n);
+  for (int i = 0; i < n; ++i) {
+    float ms = 0.f;
+    TAPG_HIP(hipEventElapsedTime(&ms, S->tev[2 * i], S->tev[2 * i + 1]));
+    us[i] = 1e3 * ms - 10.0;
+  }
+  std::nth_element(us.begin(), us.begin() + n / 2, us.end());
+  return us[n / 2];
+}
 
 int dev_get_history(tapg_solver_s* S, Slot& sl, double* hbuf, int n) {
   TAPG_HIP(hipSetDevice(S->device));

@@ -403,6 +403,13 @@ __global__ void iter_end_kernel(DevCtl* ctl, double* hist, int ntrees, int hist_
   ctl[k] = c;
 }
 
+// A bounded wait of `ticks` periods of the device's constant-rate clock (one
+// thread): holds a stream while the host enqueues the work behind it.
+__global__ void hold_kernel(long long ticks) {
+  const long long t0 = wall_clock64();
+  while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(32);
+}
+
 // Power iteration step end: |M v| from the per-tile partial sums (fixed order).
 __global__ __launch_bounds__(kThreads) void power_end_kernel(DevCtl* c, const double* part, int n) {
   __shared__ double s[kThreads];
@@ -693,6 +700,10 @@ void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st) 
 void launch_iter_end(DevCtl* c, double* hist, int ntrees, int hist_stride, hipStream_t st) {
   const int nb = (ntrees + 63) / 64;
   hipLaunchKernelGGL(iter_end_kernel, dim3(nb), dim3(64), 0, st, c, hist, ntrees, hist_stride);
+}
+
+void launch_hold(long long ticks, hipStream_t st) {
+  hipLaunchKernelGGL(hold_kernel, dim3(1), dim3(1), 0, st, ticks);
 }
 
 void launch_power_end(DevCtl* c, const double* part, int n, hipStream_t st) {

@@ -38,6 +38,7 @@ EXPORTED = [
     "tapg_factor_step", "tapg_get_factors", "tapg_factor_blocks", "tapg_solve", "tapg_batch_solve", "tapg_get_primal", "tapg_get_dual",
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
     "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune", "tapg_sweep_form",
+    "tapg_schedule_spec", "tapg_event_pair_overhead",
     "tapg_solver_forget",
     "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats", "tapg_server_timing",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
@@ -116,6 +117,9 @@ def lib() -> ctypes.CDLL:
         "tapg_solver_forget": ([_P, _P], ctypes.c_int),
         "tapg_sweep_form": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int),
                              ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "tapg_schedule_spec": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.c_char_p, ctypes.c_int],
+                               ctypes.c_int),
+        "tapg_event_pair_overhead": ([_P, _D], ctypes.c_int),
         "tapg_autotune": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.c_int, _D,
                            ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "tapg_server_create": ([_P, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
@@ -316,6 +320,17 @@ def tapg_autotune(solver, trees, iters=20):
 FORM_NAMES = {0: "stages", 1: "segment", 2: "projector", 3: "scan"}
 
 
+def tapg_schedule_spec(solver, trees):
+    """Schedule of a tree or batch after its last solve / autotune, as the
+    environment settings that force it (e.g. "TAPG_SCAN=1 TAPG_LEVELS=0:1,5:1
+    TAPG_FWD_GROUP=1")."""
+    n = len(trees)
+    tarr = (_P * n)(*trees)
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().tapg_schedule_spec(solver, n, tarr, buf, len(buf)))
+    return buf.value.decode()
+
+
 def tapg_sweep_form(solver, trees):
     """Sweep form of a tree or batch after its last solve / autotune:
     ``(form name, backward launches per iteration)``."""
@@ -425,6 +440,13 @@ def tapg_plan_schedule(tree, precision=TAPG_FP64, levels=None):
 
 def tapg_kernel_timing(solver, enable: bool):
     _check(lib().tapg_kernel_timing(solver, int(bool(enable))))
+
+
+def tapg_event_pair_overhead(solver):
+    """Microseconds that an event pair adds to each timed launch (median)."""
+    us = np.zeros(1)
+    _check(lib().tapg_event_pair_overhead(solver, _ptr(us)))
+    return float(us[0])
 
 
 def tapg_kernel_times(solver):

@@ -179,4 +179,10 @@ def test_sweep_form_argument_errors_on_host():
     f, nl = ctypes.c_int(-1), ctypes.c_int(-1)
     assert L.tapg_sweep_form(None, 1, None, ctypes.byref(f), ctypes.byref(nl)) == tapg.TAPG_EINVAL
     assert f.value == -1 and nl.value == -1
+    buf = ctypes.create_string_buffer(64)
+    assert L.tapg_schedule_spec(None, 1, None, buf, 64) == tapg.TAPG_EINVAL
+    assert buf.value == b""
+    us = ctypes.c_double(-1.0)
+    assert L.tapg_event_pair_overhead(None, ctypes.byref(us)) == tapg.TAPG_EINVAL
+    assert us.value == -1.0
     assert tapg.FORM_NAMES == {0: "stages", 1: "segment", 2: "projector", 3: "scan"}

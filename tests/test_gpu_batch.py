@@ -174,7 +174,11 @@ def test_autotuned_schedule_keeps_parity():
         ms_1, nc_1 = tapg.tapg_autotune(S.h, trees[2:3], 10)
         form_b = tapg.tapg_sweep_form(S.h, trees)
         form_1 = tapg.tapg_sweep_form(S.h, trees[2:3])
-        say("autotune", ms_b, nc_b, form_b, ms_1, nc_1, form_1)
+        spec_1 = tapg.tapg_schedule_spec(S.h, trees[2:3])
+        say("autotune", ms_b, nc_b, form_b, ms_1, nc_1, form_1, spec_1)
+        env = dict(kv.split("=") for kv in spec_1.split())
+        assert env["TAPG_SCAN"] == ("1" if form_1[0] == "scan" else "0")
+        assert len(env["TAPG_LEVELS"].split(",")) == form_1[1]
         st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
         u, x = S.primal(trees[2])
         assert tapg.tapg_sweep_form(S.h, trees) == form_b  # the solve keeps the tuned form
