@@ -5,6 +5,41 @@
 
 namespace tapg {
 
+// End of one APG iteration for one tree (Sec. 4.3): from its control state
+// and the residual max |y+ - w| / gamma that the forward sweep left in
+// res_bits, the state of the next iteration: residual recorded (*res, and
+// *record when the tree was still running), iteration count, stop flags,
+// theta_{nu+1} = (sqrt(theta^4 + 4 theta^2) - theta^2) / 2 and
+// beta_{nu+1} = theta_{nu+1} (1/theta_nu - 1).  A stopped tree's state is
+// returned unchanged.  Every caller uses this one routine, so the closing
+// launch and the workgroups that close an iteration themselves agree bit for bit.
+__device__ inline DevCtl ctl_advance(DevCtl c, bool* record, double* res) {
+  *record = false;
+  if (c.done) return c;
+  const double r = __longlong_as_double((long long)c.res_bits);
+  *record = true;
+  *res = r;
+  c.res_bits = 0ull;
+  c.last_res = r;
+  c.iter += 1;
+  if (!(r < INFINITY)) {
+    c.numeric = 1;
+    c.done = 1;
+  } else if (c.tol > 0.0 && r <= c.tol) {
+    c.converged = 1;
+    c.done = 1;
+  } else if (c.iter >= c.max_iter) {
+    c.done = 1;
+  }
+  const double th = c.theta;
+  const double t2 = th * th;
+  const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
+  c.theta_prev = th;
+  c.theta = thn;
+  c.beta = thn * (1.0 / th - 1.0);
+  return c;
+}
+
 constexpr int kThreads = 256;     // per-stage kernels
 constexpr int kSegThreads = 512;  // segment kernels
 // static LDS of a segment kernel (reductions, gamma-scaled bounds), reserved
@@ -94,6 +129,13 @@ struct SegArgs {
   T* u;
   T* x;
   DevCtl* ctl;       // control block of each tree of the forest (one for a tree)
+  // With close != 0 (the first backward launch of an iteration after the
+  // first of a chunk), the state is advanced from ctl_prev here: every
+  // workgroup computes the next state of its tree from ctl_prev and the
+  // residual that the previous iteration left in it, and the tree's first
+  // workgroup of the launch writes it to ctl (and the residual to the history).
+  const DevCtl* ctl_prev;
+  int close;
   double* part;
   double* hist;      // residual history, hist_stride entries per tree
   const int* wgtree; // tree of each workgroup of the launch (nullptr: one tree)
@@ -177,6 +219,9 @@ template <typename T>
 void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
 // End of an iteration of ntrees trees (per-tree control blocks and histories).
 void launch_iter_end(DevCtl* c, double* hist, int ntrees, int hist_stride, hipStream_t st);
+// The same from the states in prev into out (out == prev allowed).
+void launch_iter_end_from(const DevCtl* prev, DevCtl* out, double* hist, int ntrees,
+                          int hist_stride, hipStream_t st);
 void launch_power_end(DevCtl* c, const double* part, int n, hipStream_t st);
 // Holds the stream for `ticks` periods of the device wall clock (at most 50 ms).
 void launch_hold(long long ticks, hipStream_t st);

@@ -867,9 +867,9 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
 template <typename T, int NB>
 __global__ __launch_bounds__(kSegThreads) void scan_bwd_kernel(SegArgs<T> a) {
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
-  const DevCtl* ctl = a.ctl + tree;
-  if (ctl->done) return;
-  scan_bwd_body<T, NB>(a, blockIdx.x, ctl->iter, (T)ctl->beta, (T)ctl->pw_scale);
+  const DevCtl c = bwd_ctl(a, tree);
+  if (c.done) return;
+  scan_bwd_body<T, NB>(a, blockIdx.x, c.iter, (T)c.beta, (T)c.pw_scale);
 }
 
 template <typename T, int NB>

@@ -9,6 +9,25 @@ namespace tapg {
 
 namespace {
 
+// Control state of a backward launch's tree: read from ctl, or, in the first
+// backward launch of an iteration that closes the previous one, advanced from
+// ctl_prev by every workgroup alike and written (with the residual history
+// entry) by the tree's first workgroup of the launch.
+template <typename T>
+__device__ inline DevCtl bwd_ctl(const SegArgs<T>& a, int tree) {
+  if (!a.close) return a.ctl[tree];
+  const DevCtl p = a.ctl_prev[tree];
+  bool record;
+  double res = 0.0;
+  const DevCtl n = ctl_advance(p, &record, &res);
+  const bool writer = blockIdx.x == 0 || (a.wgtree && a.wgtree[blockIdx.x - 1] != tree);
+  if (writer && threadIdx.x == 0) {
+    a.ctl[tree] = n;
+    if (record) a.hist[(size_t)tree * a.hist_stride + p.iter] = res;
+  }
+  return n;
+}
+
 template <typename T>
 __device__ __forceinline__ T wext(T y, T yp, T beta) {
   return y + beta * (y - yp);

@@ -440,9 +440,9 @@ __device__ __forceinline__ void seg_bwd_body(const SegArgs<T>& a, int wg, int it
 template <typename T, int NB, bool PROJ>
 __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
-  const DevCtl* ctl = a.ctl + tree;
-  if (ctl->done) return;
-  seg_bwd_body<T, NB, PROJ>(a, blockIdx.x, ctl->iter, (T)ctl->beta, (T)ctl->pw_scale);
+  const DevCtl c = bwd_ctl(a, tree);
+  if (c.done) return;
+  seg_bwd_body<T, NB, PROJ>(a, blockIdx.x, c.iter, (T)c.beta, (T)c.pw_scale);
 }
 
 // ---------------------------------------------------------------------------

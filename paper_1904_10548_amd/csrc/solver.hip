@@ -366,14 +366,25 @@ SegArgs<T> make_seg_args(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mod
 struct TimedCursor {
   int next = 0;
   std::vector<int> kind;  // kind of each recorded pair
+  std::vector<int> it;    // iteration of each pair within the chunk (-1: chunk end)
+  int iter = 0;           // iteration being enqueued
 };
 
+// One iteration.  Level launches: the control state is read from block blk of
+// the slot's two control blocks (block b of tree k at d_ctl[b * ntrees + k]);
+// with `close`, the first backward launch first ends the previous iteration,
+// advancing the state from the other block into block blk.  The iteration
+// itself is not ended here (enqueue_iterations ends a run of them).  Power
+// iteration and per-stage kernels: block 0 only, each iteration ended by a
+// launch of its own.
 template <typename T>
 void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
-                       TimedCursor* tc = nullptr) {
+                       TimedCursor* tc = nullptr, int blk = 0, bool close = false) {
   hipStream_t st = S->stream;
   if (sl.segmented) {
     SegArgs<T> a = make_seg_args<T>(S, sl, d, mode);
+    a.ctl = sl.d_ctl + (size_t)blk * sl.ntrees;
+    a.ctl_prev = sl.d_ctl + (size_t)(1 - blk) * sl.ntrees;
     const int nl = (int)sl.levels.size();
     for (int pass = 0; pass < 2; ++pass) {
       int base = 0;
@@ -399,29 +410,22 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
           a.part_base = 0;
           a.part_total = L.n_wg;
         }
+        a.close = (close && mode == 0 && pass == 0 && q == 0) ? 1 : 0;
         if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
         launch_seg<T>(pass == 1, L.nbm, a, L.n_wg, st);
         if (tc) {
           (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
           tc->kind.push_back(pass);
+          tc->it.push_back(tc->iter);
           tc->next++;
         }
       }
     }
-    // the iteration's end in a launch of its own: the forward workgroups left
-    // their residual maxima (power iteration: partial sums) in device memory
-    if (mode == 0) {
-      if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
-      launch_iter_end(sl.d_ctl, sl.d_hist, sl.ntrees, sl.hist_cap, st);
-      if (tc) {
-        (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
-        tc->kind.push_back(2);
-        tc->next++;
-      }
-    } else {
+    // the power iteration's step ends in a launch of its own (the forward
+    // workgroups left their partial sums in device memory)
+    if (mode == 1)
       launch_power_end(sl.d_ctl, (const double*)sl.d_part,
                        sl.fwd_full.n_wg > 0 ? sl.fwd_full.n_wg : sl.part_total, st);
-    }
     return;
   }
   SweepArgs<T> a = make_args<T>(S, sl, d, mode);
@@ -447,6 +451,7 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
       if (tc) {
         (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
         tc->kind.push_back(pass);
+        tc->it.push_back(tc->iter);
         tc->next++;
       }
     }
@@ -457,6 +462,7 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
     if (tc) {
       (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
       tc->kind.push_back(2);
+      tc->it.push_back(tc->iter);
       tc->next++;
     }
   } else
@@ -464,9 +470,40 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
 }
 
 static int launches_per_iter(const Slot& sl) {
-  if (sl.segmented)  // backward levels, forward launches, iteration end
-    return (int)sl.levels.size() + (sl.fwd_full.n_wg > 0 ? 1 : (int)sl.levels.size()) + 1;
+  if (sl.segmented)  // backward levels, forward launches (the end is fused or per run)
+    return (int)sl.levels.size() + (sl.fwd_full.n_wg > 0 ? 1 : (int)sl.levels.size());
   return 2 * sl.N + 1;
+}
+
+// n APG iterations from the state in control block 0 back to block 0.  Level
+// launches: iteration i > 0 ends iteration i - 1 in its first backward launch
+// (states alternate between the two blocks), and one small launch ends the
+// last into block 0; this is what a chunk's graph holds.  Per-stage kernels:
+// every iteration ends in a launch of its own.
+template <typename T>
+void enqueue_iterations(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int n,
+                        TimedCursor* tc = nullptr) {
+  for (int i = 0; i < n; ++i) {
+    if (tc) tc->iter = i;
+    if (sl.segmented)
+      enqueue_iteration<T>(S, sl, d, 0, tc, i & 1, i > 0);
+    else
+      enqueue_iteration<T>(S, sl, d, 0, tc);
+  }
+  if (!sl.segmented || n < 1) return;
+  hipStream_t st = S->stream;
+  if (tc) {
+    tc->iter = -1;
+    (void)hipEventRecord(S->tev[2 * tc->next], st);
+  }
+  launch_iter_end_from(sl.d_ctl + (size_t)((n - 1) & 1) * sl.ntrees, sl.d_ctl, sl.d_hist,
+                       sl.ntrees, sl.hist_cap, st);
+  if (tc) {
+    (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
+    tc->kind.push_back(2);
+    tc->it.push_back(-1);
+    tc->next++;
+  }
 }
 
 template <typename T>
@@ -684,7 +721,7 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
     sl.graph = nullptr;
     hipGraph_t g = nullptr;
     TAPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    enqueue_iterations<T>(S, sl, d, chunk);
     TAPG_HIP(hipStreamEndCapture(st, &g));
     hipError_t e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -696,7 +733,7 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   ProgressLine progress("solve");
   const bool timed = S->time_kernels;
   if (timed) {
-    const size_t need = (size_t)2 * chunk * launches_per_iter(sl);
+    const size_t need = (size_t)2 * (chunk * launches_per_iter(sl) + 1);
     while (S->tev.size() < need) {
       hipEvent_t e;
       TAPG_HIP(hipEventCreate(&e));
@@ -739,15 +776,16 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
       launch_hold((long long)(std::min(S->hold_us, 50000.0) * S->wall_clock_mhz), st);
       const auto h0 = std::chrono::steady_clock::now();
       TimedCursor tc;
-      for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0, &tc);
+      enqueue_iterations<T>(S, sl, d, chunk, &tc);
       const double enq_us =
           std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - h0).count();
       S->hold_us = 1.5 * enq_us + 200.0;
       TAPG_HIP(hipGetLastError());
       TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
       TAPG_HIP(hipStreamSynchronize(st));
-      tc.next = std::min(tc.next, std::max(0, hc.iter - before) * launches_per_iter(sl));
+      const int ran = hc.iter - before;  // iterations that did work
       for (int k = 0; k < tc.next; ++k) {
+        if (tc.it[k] >= ran) continue;  // after the stop: a no-op
         float ms = 0.f;
         TAPG_HIP(hipEventElapsedTime(&ms, S->tev[2 * k], S->tev[2 * k + 1]));
         S->kt_ms[tc.kind[k]] += ms;
@@ -756,7 +794,7 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
     } else if (S->use_graph) {
       TAPG_HIP(hipGraphLaunch(sl.graph, st));
     } else {
-      for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+      enqueue_iterations<T>(S, sl, d, chunk);
       TAPG_HIP(hipGetLastError());
     }
     launched += chunk;
@@ -1262,7 +1300,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       }
       sl.d_u = dalloc((size_t)K * LDU);
       sl.d_x = dalloc((size_t)K * LDX);
-      sl.d_ctl = dmalloc<DevCtl>(t.ntrees);
+      sl.d_ctl = dmalloc<DevCtl>(2 * (size_t)t.ntrees);  // two blocks per tree
       sl.hist_cap = std::max(1, S->cfg.max_iter);
       sl.d_hist = dmalloc<double>((size_t)sl.hist_cap * t.ntrees);
       sl.node_offset = t.offset;
@@ -1363,7 +1401,7 @@ void ensure_graph(tapg_solver_s* S, Slot& sl, int chunk) {
   hipGraph_t g = nullptr;
   const NetDev<T>& d = net_of<T>(S);
   TAPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+  enqueue_iterations<T>(S, sl, d, chunk);
   TAPG_HIP(hipStreamEndCapture(st, &g));
   hipError_t e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -1388,7 +1426,7 @@ void run_replays(tapg_solver_s* S, Slot& sl, int iters) {
     for (int i = 0; i < iters; i += sl.graph_iters) TAPG_HIP(hipGraphLaunch(sl.graph, S->stream));
   } else {
     const NetDev<T>& d = net_of<T>(S);
-    for (int i = 0; i < iters; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    enqueue_iterations<T>(S, sl, d, iters);
     TAPG_HIP(hipGetLastError());
   }
 }
@@ -1399,7 +1437,7 @@ void run_chunk(tapg_solver_s* S, Slot& sl, int chunk) {
     TAPG_HIP(hipGraphLaunch(sl.graph, S->stream));
   } else {
     const NetDev<T>& d = net_of<T>(S);
-    for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    enqueue_iterations<T>(S, sl, d, chunk);
     TAPG_HIP(hipGetLastError());
   }
 }
@@ -1481,7 +1519,7 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
     sl.graph = nullptr;
     hipGraph_t g = nullptr;
     TAPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    enqueue_iterations<T>(S, sl, d, chunk);
     TAPG_HIP(hipStreamEndCapture(st, &g));
     hipError_t e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -1494,7 +1532,7 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
     if (S->use_graph) {
       TAPG_HIP(hipGraphLaunch(sl.graph, st));
     } else {
-      for (int i = 0; i < chunk; ++i) enqueue_iteration<T>(S, sl, d, 0);
+      enqueue_iterations<T>(S, sl, d, chunk);
       TAPG_HIP(hipGetLastError());
     }
     launched += chunk;
@@ -1790,7 +1828,7 @@ double time_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     TAPG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i) enqueue_iteration<T>(S, sl, d, 0);
+    enqueue_iterations<T>(S, sl, d, iters);
     TAPG_HIP(hipStreamEndCapture(st, &g));
     hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);

@@ -370,37 +370,19 @@ __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
     atomicMax(&ctl->res_bits, (unsigned long long)__double_as_longlong(pmax[0]));
 }
 
-// End of one APG iteration, one thread per tree of the slot (a launch of its
-// own, after the last forward launch, so that the sweep workgroups need no
-// device-wide fence): record the residual that they left in res_bits, test
-// for termination, and advance theta_{nu+1} = (sqrt(theta^4 + 4 theta^2) -
-// theta^2) / 2 and beta_{nu+1} = theta_{nu+1} (1/theta_nu - 1) (Sec. 4.3).
-__global__ void iter_end_kernel(DevCtl* ctl, double* hist, int ntrees, int hist_stride) {
+// End of one APG iteration (ctl_advance), one thread per tree of the slot, in
+// a launch of its own after the last forward launch (the sweep workgroups
+// then need no device-wide fence): from the states in prev into out.
+__global__ void iter_end_kernel(const DevCtl* prev, DevCtl* out, double* hist, int ntrees,
+                                int hist_stride) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ntrees) return;
-  DevCtl c = ctl[k];  // the whole block in one round of loads
-  if (c.done) return;
-  const double res = __longlong_as_double((long long)c.res_bits);
-  c.res_bits = 0ull;
-  hist[(size_t)k * hist_stride + c.iter] = res;
-  c.last_res = res;
-  c.iter += 1;
-  if (!(res < INFINITY)) {
-    c.numeric = 1;
-    c.done = 1;
-  } else if (c.tol > 0.0 && res <= c.tol) {
-    c.converged = 1;
-    c.done = 1;
-  } else if (c.iter >= c.max_iter) {
-    c.done = 1;
-  }
-  const double th = c.theta;
-  const double t2 = th * th;
-  const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
-  c.theta_prev = th;
-  c.theta = thn;
-  c.beta = thn * (1.0 / th - 1.0);
-  ctl[k] = c;
+  const DevCtl c = prev[k];  // the whole block in one round of loads
+  bool record;
+  double res = 0.0;
+  const DevCtl n = ctl_advance(c, &record, &res);
+  if (record) hist[(size_t)k * hist_stride + c.iter] = res;
+  out[k] = n;
 }
 
 // A bounded wait of `ticks` periods of the device's constant-rate clock (one
@@ -698,8 +680,14 @@ void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st) 
 
 
 void launch_iter_end(DevCtl* c, double* hist, int ntrees, int hist_stride, hipStream_t st) {
+  launch_iter_end_from(c, c, hist, ntrees, hist_stride, st);
+}
+
+void launch_iter_end_from(const DevCtl* prev, DevCtl* out, double* hist, int ntrees,
+                          int hist_stride, hipStream_t st) {
   const int nb = (ntrees + 63) / 64;
-  hipLaunchKernelGGL(iter_end_kernel, dim3(nb), dim3(64), 0, st, c, hist, ntrees, hist_stride);
+  hipLaunchKernelGGL(iter_end_kernel, dim3(nb), dim3(64), 0, st, prev, out, hist, ntrees,
+                     hist_stride);
 }
 
 void launch_hold(long long ticks, hipStream_t st) {
