@@ -210,7 +210,9 @@ tapg_status tapg_plan_schedule(tapg_tree tree, int precision, const char* levels
  * tapg_kernel_times returns, for the last timed solve, the summed device time
  * (ms[4]) and counts (launches[4]) of: [0] backward-sweep launches, [1]
  * forward-sweep launches (with the fused prox/dual update), [2] separate
- * end-of-iteration launches, [3] persistent-iteration launches, counted in
+ * end-of-iteration launches (per iteration with the per-stage kernels; once
+ * per chunk with the level launches, whose backward launches end the previous
+ * iteration themselves), [3] persistent-iteration launches, counted in
  * iterations (with TAPG_CHAIN=1 a single tree whose workgroups all fit on the
  * device runs every level in one cooperative launch per chunk of iterations). */
 tapg_status tapg_kernel_timing(tapg_solver solver, int enable);

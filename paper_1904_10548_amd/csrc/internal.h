@@ -92,8 +92,10 @@ struct TreeHost {
   }
 };
 
-// Device control block of one tree slot (read by every kernel, written by
-// the per-iteration end kernel).
+// Device control block of one tree (read by every kernel; advanced at the end
+// of each iteration).  The level launches keep two per tree and use them
+// alternately: an iteration's first backward launch advances the state of the
+// previous one into the other block.
 struct DevCtl {
   int iter;         // iterations completed
   int done;         // stop flag

@@ -452,8 +452,10 @@ __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
 //   x_n = A x_anc + B u_n + g_n
 //   v = w + gamma (x_n, x_n, u_n);  blocks 1, 2: r = v - gamma P_C(v/gamma),
 //   y+ = r min(1, W / |r|);  block 3: y+ = v - gamma P_U(v/gamma)
-// The product Fbar_s (W_u u_anc) is formed once per parent.  The launch of
-// the last level ends the iteration in its last workgroup to finish.
+// The product Fbar_s (W_u u_anc) is formed once per parent.  The workgroups
+// leave their residual maxima in the tree's control block; the next
+// iteration's first backward launch (or a small launch after a run of
+// iterations) ends the iteration.
 // ---------------------------------------------------------------------------
 // Forward sweep of workgroup `wg` of a level (tree `tree`) in iteration `it`
 // with the fused prox / dual update.  Returns the workgroup's residual max
