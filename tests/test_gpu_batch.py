@@ -79,12 +79,13 @@ def test_batch_fixed_iterations_matches_oracle_per_tree(scan, fwd_group):
 
 
 @pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
-def test_batch_equals_single_tree_solves_to_tolerance(precision):
+@pytest.mark.parametrize("check_every", [50, 7])
+def test_batch_equals_single_tree_solves_to_tolerance(precision, check_every):
     """Auto step size per tree and a tolerance: every tree stops at the same
     iteration as its own tapg_solve, with the same iterate; trees stop at
-    different iterations inside the batch."""
+    different iterations inside the batch (and inside runs of odd length)."""
     batch = tiny_batch(SHAPES, seed=23)
-    kw = dict(gamma=0.0, tol=1e-6, max_iter=20000, check_every=50, precision=precision)
+    kw = dict(gamma=0.0, tol=1e-6, max_iter=20000, check_every=check_every, precision=precision)
     say("batch vs single", [P.tree.K for P in batch], "prec", precision)
     with make_solver(batch[0], **kw) as S:
         trees = [add_tree(S, P) for P in batch]

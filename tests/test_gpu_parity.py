@@ -239,6 +239,35 @@ def test_small_converged_matches_oracle_iteration_count():
         assert np.abs(u - ref.u).max() <= 1e-8
 
 
+@pytest.mark.parametrize("scan,graph,check_every", [(True, True, 7), (False, True, 7),
+                                                    (True, False, 5), (True, True, 1)])
+def test_odd_chunks_and_stop_inside_a_chunk(scan, graph, check_every):
+    """Iterations in runs of odd length: the level launches end each iteration
+    in the next one's first backward launch (two control blocks used in turn)
+    and a run with one small launch.  103 fixed iterations (the last run cut
+    by max_iter) match the oracle element by element with the whole residual
+    history, and a run to a tolerance stops at the oracle's iteration."""
+    P = tiny_problem(N=7, irregular=True, seed=12, max_children=40, max_width=3000)
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 0.9 / O.lipschitz_power(P, sf, 200)
+    st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 103, check_every=check_every,
+                                                     graph=graph, scan=scan)
+    _assert_fp64_parity(P, res, u, x, y, hist, ref, 103)
+    P = tiny_problem(N=6, irregular=True, seed=5, max_children=4, max_width=60)
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 0.9 / O.lipschitz_power(P, sf, 200)
+    tol = 1e-3
+    ref2 = _oracle_run(P, gamma, 5000, tol=tol, factors=sf)
+    assert ref2.converged  # 1,516 iterations
+    with make_solver(P, gamma=gamma, tol=tol, max_iter=5000, check_every=check_every) as S:
+        t = add_tree(S, P)
+        st, u0, r2 = S.solve(t, P.p, P.q)
+        h2 = tapg.tapg_residual_history(S.h, t, r2.iters)
+    say("stop", r2.iters, "oracle", ref2.iters)
+    assert st == tapg.TAPG_OK and r2.converged and r2.iters == ref2.iters
+    assert np.allclose(h2, np.asarray(ref2.res_hist), rtol=1e-7, atol=1e-12)
+
+
 def test_factor_step_matches_oracle_stage_factors():
     P = ds.config_problem("dwn128")
     sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
