@@ -106,12 +106,14 @@ struct LdsCursor {
 
 template <typename T>
 struct BwdLds {  // a (then lambda), v (then m), G v; ranges; packed children slots
-                 // (two buffers); CSR of B', G and E'
-  size_t lam, v, gv, rg, ch, brow, bcol, bval, grow, gcol, gval, erow, ecol, eval, total;
+                 // (two buffers); per-slot sums of the boundary children (P then
+                 // lambda, up to 4 slots); CSR of B', G and E'
+  size_t lam, v, gv, rg, ch, bnd, brow, bcol, bval, grow, gcol, gval, erow, ecol, eval, total;
   __host__ __device__ explicit BwdLds(const SegArgs<T>& a) {
     LdsCursor c;
     lam = c.take(sizeof(T) * kCN * kSX);
     v = c.take(sizeof(T) * kCN * kSU);
+    bnd = c.take(sizeof(T) * 4 * (kSU + kSX));
     gv = c.take(sizeof(T) * kCN * a.ns);
     rg = c.take(sizeof(int2) * a.nst);
     ch = c.take(sizeof(int) * 2 * kCN);
@@ -213,6 +215,7 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
   T* sGv = reinterpret_cast<T*>(smem_raw + L.gv);    // [kCN][ns]: G v
   int2* sRg = reinterpret_cast<int2*>(smem_raw + L.rg);  // node range per stage
   int* sCh = reinterpret_cast<int*>(smem_raw + L.ch);    // [2][kCN]: children slots, by chunk parity
+  T* sBnd = reinterpret_cast<T*>(smem_raw + L.bnd);      // [NB][kSU] P, then [NB][kSX] lambda
   int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);  // CSR of B' (nu rows)
   int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
   T* sVal = reinterpret_cast<T*>(smem_raw + L.bval);
@@ -269,11 +272,12 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
 
   // Children of the level's last stage: the level below left their lambda and
   // P in global memory.  They are staged through LDS kCN at a time (all loads
-  // of a batch in flight together) and summed per slot, in child order, by the
-  // chain threads.
-  T bndL[NB], bndP[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) bndL[b] = bndP[b] = T(0);
+  // of a batch in flight together) and summed per slot, in child order: thread
+  // t sums the P of slot t / 128 (component t % 128) and the lambda of slot
+  // t / 64 (component t % 64), adding zero for the other slots' children
+  // (x + 0 = x: the same sums as adding each child to its slot).  The sums go
+  // to LDS for the chain threads.
+  T accL = T(0), accP = T(0);
 
   const int nchunk = (a.nst + CS - 1) / CS;
   // Inputs of one chunk: per x-element (y1, y1o, y2, y2o), per u-element (y3,
@@ -382,13 +386,16 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
 
     // lambda chain, bottom stage of the chunk first, in registers
     if (tid < kSX) {
-      T av[kCN];
+      T av[kCN], bndL[NB];
       int cr[kCN];
 #pragma unroll
       for (int q = 0; q < kCN; ++q) {
         av[q] = sLam[q * kSX + ix];
         cr[q] = __builtin_amdgcn_readfirstlane(ch[q]);
       }
+#pragma unroll
+      for (int b = 0; b < NB; ++b)  // the boundary sums (first chunk only)
+        bndL[b] = kids_below && s_hi == se ? sBnd[NB * kSU + b * kSX + ix] : T(0);
 #pragma unroll
       for (int k = CS - 1; k >= 0; --k) {
         if (k < cs) {
@@ -457,11 +464,15 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
     // chunk later
     if (tid < kSU) {
       int cr[kCN];
+      T bndP[NB];
 #pragma unroll
       for (int q = 0; q < kCN; ++q) {
         dP[q] = sV[q * kSU + iu];
         cr[q] = __builtin_amdgcn_readfirstlane(ch[q]);
       }
+#pragma unroll
+      for (int b = 0; b < NB; ++b)  // the boundary sums (first chunk only)
+        bndP[b] = kids_below && s_hi == se ? sBnd[b * kSU + iu] : T(0);
 #pragma unroll
       for (int k = CS - 1; k >= 0; --k) {
         if (k < cs) {
@@ -501,21 +512,22 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
       }
       if (tid < kCN) sCh[tid] = c0 + tid < ce ? ba - lo_l : -1;
       __syncthreads();
-      if (tid < kSU) {
+      {
+        const int sp = tid / kSU, sq = tid / kSX;
+        int bq[kCN];  // slot of child c0 + q (-1: past the last child)
+#pragma unroll
+        for (int q = 0; q < kCN; ++q) bq[q] = __builtin_amdgcn_readfirstlane(sCh[q]);
 #pragma unroll
         for (int q = 0; q < kCN; ++q) {
-          const int b = sCh[q];  // slot of child c0 + q (-1: past the last child)
           const T lv = sLam[q * kSX + ix], pv = sV[q * kSU + iu];
-#pragma unroll
-          for (int bb = 0; bb < NB; ++bb)
-            if (b == bb) {
-              bndL[bb] += lv;
-              bndP[bb] += pv;
-            }
+          accL += bq[q] == sq ? lv : T(0);
+          accP += bq[q] == sp ? pv : T(0);
         }
       }
       __syncthreads();
     }
+    if (tid / kSU < NB) sBnd[(tid / kSU) * kSU + iu] = accP;
+    if (tid / kSX < NB) sBnd[NB * kSU + (tid / kSX) * kSX + ix] = accL;
   }
 
   int c = 0;
