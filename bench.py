@@ -146,7 +146,7 @@ def main():
     lipschitz_s = time.perf_counter() - t0
     # schedule and sweep form picked by the autotuner (setup, not timed)
     t0 = time.perf_counter()
-    tune_ms, tune_nc = (None, 0) if args.no_autotune else tapg.tapg_autotune(S.h, [tree], 50)
+    tune_ms, tune_nc = (None, 0) if args.no_autotune else tapg.tapg_autotune(S.h, [tree], 100)
     tune_s = time.perf_counter() - t0
     if args.no_autotune:
         S.solve(tree, P.p, P.q)  # the slot exists once solved
