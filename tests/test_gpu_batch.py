@@ -195,3 +195,55 @@ def test_autotuned_schedule_keeps_parity():
         assert r.iters == iters and abs(r.cost - J) <= 1e-6 * max(1.0, abs(J))
     ref = O.apg(batch[2], gamma, O.StageFactors(batch[2].net, batch[2].weights.W_u, batch[2].tree), iters)
     assert np.abs(u - ref.u).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())
+
+
+def test_schedule_spec_reproduces_the_tuned_solve():
+    """The environment settings that tapg_schedule_spec reports force the tuned
+    schedule on a fresh solver: the same form and launches, and the same
+    iterate bit for bit."""
+    P = tiny_batch(SHAPES, seed=13)[4]
+    gamma = _gamma_for([P])
+    iters = 120
+    with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=40) as S:
+        t = add_tree(S, P)
+        tapg.tapg_autotune(S.h, [t], 10)
+        spec = tapg.tapg_schedule_spec(S.h, [t])
+        form = tapg.tapg_sweep_form(S.h, [t])
+        S.solve(t, P.p, P.q)
+        u1, x1 = S.primal(t)
+    say("spec", spec, form)
+    env = dict(kv.split("=") for kv in spec.split())
+    os.environ.update(env)
+    try:
+        with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=40) as S:
+            t = add_tree(S, P)
+            S.solve(t, P.p, P.q)
+            assert tapg.tapg_sweep_form(S.h, [t]) == form
+            assert tapg.tapg_schedule_spec(S.h, [t]) == spec
+            u2, x2 = S.primal(t)
+    finally:
+        for k in env:
+            os.environ.pop(k, None)
+    assert np.array_equal(u1, u2) and np.array_equal(x1, x2)
+
+
+def test_kernel_timing_and_event_pair_overhead():
+    """Timed solves count every backward and forward launch of the iterations
+    that did work, and the event-pair dispatch cost is a few microseconds."""
+    P = tiny_batch(SHAPES, seed=13)[4]
+    gamma = _gamma_for([P])
+    with make_solver(P, gamma=gamma, tol=0.0, max_iter=45, check_every=20) as S:
+        t = add_tree(S, P)
+        tapg.tapg_kernel_timing(S.h, True)
+        st, u0, r = S.solve(t, P.p, P.q)
+        kt = tapg.tapg_kernel_times(S.h)
+        tapg.tapg_kernel_timing(S.h, False)
+        form, nbwd = tapg.tapg_sweep_form(S.h, [t])
+        us = tapg.tapg_event_pair_overhead(S.h)
+    say("kernel times", kt, form, nbwd, us)
+    assert r.iters == 45
+    # the scan form's forward sweep is one launch; the segment form's one per level
+    assert kt["bwd"][1] == 45 * nbwd and kt["fwd"][1] == 45 * (1 if form == "scan" else nbwd)
+    assert kt["end"][1] == 3  # one per run of iterations (20, 20, 5 of 20)
+    assert all(v[0] > 0 for k, v in kt.items() if k != "chain")
+    assert 0.0 < us < 50.0
