@@ -134,10 +134,16 @@ def test_batch_warm_start_and_resolve():
         assert abs(r1[k].cost - single[k].cost) <= 1e-9 * max(1.0, abs(single[k].cost))
 
 
-def test_batch_of_full_size_trees_fp32():
-    """Three Barcelona-sized trees of the 64-tree configuration, FP32 sweeps:
-    each tree's cost after a fixed number of iterations within 1e-4 of the FP64
-    oracle's."""
+@pytest.mark.parametrize("scan,fwd_group", [(None, None), ("1", "2")])
+def test_batch_of_full_size_trees_fp32(scan, fwd_group):
+    """Three Barcelona-sized trees of the 64-tree configuration, FP32 sweeps
+    (the default form, and the scan form with its forward launch on pairs of
+    leaves): each tree's cost after a fixed number of iterations within 1e-4 of
+    the FP64 oracle's."""
+    if scan:
+        os.environ["TAPG_SCAN"] = scan
+    if fwd_group:
+        os.environ["TAPG_FWD_GROUP"] = fwd_group
     batch = [ds.config_problem("batch64", i) for i in range(3)]
     iters = 30
     gamma = 0.0
