@@ -1808,6 +1808,14 @@ template <typename T>
 double time_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
   hipStream_t st = S->stream;
   const int nt = t.ntrees, PQ = S->LDX + S->LDU;
+  if (sl.hist_cap < iters) {  // the timing runs record iters residuals per tree
+    TAPG_HIP(hipStreamSynchronize(st));
+    dfree(sl.d_hist);
+    sl.hist_cap = iters;
+    sl.d_hist = dmalloc<double>((size_t)sl.hist_cap * sl.ntrees);
+    if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+    sl.graph = nullptr;
+  }
   std::vector<DevCtl> c(nt);
   for (int k = 0; k < nt; ++k) {
     c[k] = DevCtl{};

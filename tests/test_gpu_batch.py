@@ -253,3 +253,22 @@ def test_kernel_timing_and_event_pair_overhead():
     assert kt["end"][1] == 3  # one per run of iterations (20, 20, 5 of 20)
     assert all(v[0] > 0 for k, v in kt.items() if k != "chain")
     assert 0.0 < us < 50.0
+
+
+def test_autotune_longer_than_max_iter():
+    """Timing runs longer than the solver's max_iter (their residual history
+    needs more room than a solve's): the solve afterwards still matches the
+    oracle with its own history."""
+    P = tiny_batch(SHAPES, seed=13)[4]
+    gamma = _gamma_for([P])
+    iters = 12
+    with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=iters) as S:
+        t = add_tree(S, P)
+        ms, nc = tapg.tapg_autotune(S.h, [t], 40)
+        st, u0, r = S.solve(t, P.p, P.q)
+        u, x = S.primal(t)
+        hist = tapg.tapg_residual_history(S.h, t, iters)
+    ref = O.apg(P, gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
+    assert ms > 0 and nc >= 1 and r.iters == iters
+    assert np.abs(u - ref.u).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())
+    assert np.allclose(hist, ref.res_hist, rtol=1e-7, atol=1e-12)
