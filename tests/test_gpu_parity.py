@@ -381,3 +381,25 @@ def test_fp32_sweeps_small_cost_error():
     J = O.primal_cost(P, ref.u, ref.x)
     assert abs(res.cost - J) <= 1e-4 * max(1.0, abs(J))
     assert res.viol_eq <= 1e-4
+
+
+def test_forward_groupings_bit_identical():
+    """The scan form's forward launch on the bottom level's workgroups or on
+    groups of 1, 2 or 4 leaves computes every node in the same order (shared
+    ancestors are recomputed, not re-associated): the iterates agree bit for
+    bit."""
+    P = ds.config_problem("dwn128")
+    gamma = 1e-6
+    out = {}
+    for fg in (0, 1, 2, 4):
+        _schedule_env(scan=True, fwd_group=fg)
+        say("dwn128 fwd group", fg)
+        with make_solver(P, gamma=gamma, tol=0.0, max_iter=30, check_every=30) as S:
+            t = add_tree(S, P)
+            st, u0, res = S.solve(t, P.p, P.q)
+            u, x = S.primal(t)
+            out[fg] = (u, x, S.dual(t), res.primal_res)
+    os.environ.pop("TAPG_FWD_GROUP", None)
+    for fg in (1, 2, 4):
+        for a, b in zip(out[0], out[fg]):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
