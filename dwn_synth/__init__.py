@@ -12,10 +12,10 @@ Data containers follow the paper's notation:
   ``x+ = A x + B u + Gd d`` and ``E u + Ed d = 0``, boxes
   ``xmin <= x <= xmax`` (soft), safety level ``xs`` (soft) and
   ``umin <= u <= umax`` (hard);
-* scenario tree (Sec. 3.3): stages ``0..N-1``, ``mu_j`` nodes per stage,
+* scenario tree (Sec. 2.3): stages ``0..N-1``, ``mu_j`` nodes per stage,
   breadth-first node numbering with contiguous children, ancestor index and
   node probability ``p``;
-* per-node demand ``d`` and electricity price (Sec. 3.2/3.3);
+* per-node demand ``d`` and electricity price (Sec. 2.2/2.3);
 * weights ``W_alpha, W_u, W_s, W_x`` (Sec. 4.1).
 """
 

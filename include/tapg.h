@@ -4,7 +4,7 @@
  * management of water distribution networks in deregulated energy markets",
  * arXiv 1904.10548).
  *
- * The problem (Sec. 3.4, problem SMPC) on a scenario tree (Sec. 3.3) with
+ * The problem (Sec. 3.2, problem SMPC) on a scenario tree (Sec. 2.3) with
  * nodes n = 0..K-1 at decision stages 0..N-1:
  *
  *   minimise  sum_n p_n [ W_alpha (alpha0 + pi_n c_E)'u_n + du_n' W_u du_n ]
@@ -101,7 +101,7 @@ tapg_status tapg_network_create(int nx, int nu, int nd, int ns, const double* A,
                                 tapg_network* out);
 void tapg_network_destroy(tapg_network net);
 
-/* Scenario tree (the paper's ScenarioTree, Sec. 3.3 and 5.1).
+/* Scenario tree (the paper's ScenarioTree, Sec. 2.3 and 5.1).
  * nodes_per_stage [N] (mu_0 = 1), ancestor [K] (ancestor[0] = -1), prob [K]
  * (prob[0] = 1, children's probabilities add up to their parent's within
  * 1e-12 relative, all > 0), demand [K*nd] (node-major), price [K] (the scalar
@@ -224,15 +224,20 @@ tapg_status tapg_kernel_times(tapg_solver solver, double* ms, long long* launche
 tapg_status tapg_event_pair_overhead(tapg_solver solver, double* us);
 
 /* Request server (the solve loop of a controller serving many requests,
- * Sec. 5's SmpcController::controlAction per request): a worker thread owns the
- * solver; each round it takes the pending requests, first come first served,
- * whose estimated device memory fits hbm_budget_bytes (at most max_batch, one
- * request per tree) and solves them with one batched solve (tapg_batch_solve);
- * requests arriving meanwhile join the next round.  A request is warm started
- * when the previous request of its session solved the same tree.  While a
- * server exists, other calls on its solver return TAPG_ESTATE; destroy the
- * server before the solver.  A submitted tree must not be modified or destroyed
- * before its ticket completes. */
+ * Sec. 5.1's SmpcController::controlAction per request), with continuous
+ * batching: a worker thread owns the solver and iterates the requests in
+ * flight (one per tree) together as one forest, one chunk of check_every
+ * iterations at a time.  Between chunks, requests whose tree stopped complete
+ * and pending requests join, first come first served, while the estimated
+ * device memory of the set fits hbm_budget_bytes (at most max_batch requests);
+ * every request's iterates are the same as in a tapg_solve of its own.  A
+ * request is warm started when the previous request of its session solved the
+ * same tree with TAPG_OK or TAPG_ENOTCONV and no request of another session has
+ * solved that tree since (a tree keeps one dual).  While a server exists,
+ * other calls on its solver return TAPG_ESTATE; destroy the server before the
+ * solver.  A submitted tree must not be modified or destroyed before its
+ * ticket completes.  If setting up or iterating a set fails, every request of
+ * the set completes with the error. */
 tapg_status tapg_server_create(tapg_solver solver, size_t hbm_budget_bytes, int max_batch,
                                tapg_server* out);
 /* Queue one request (p: nx, q: nu, copied); *ticket identifies it. */

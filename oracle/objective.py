@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE (CPU oracle).
 
-* Primal cost (problem SMPC, Sec. 3.4): the expected stage cost
+* Primal cost (problem SMPC, Sec. 3.2): the expected stage cost
   ``sum_n p_n [W_alpha (alpha0 + alpha_n)'u_n + du_n' W_u du_n]`` plus the
   unweighted soft penalties ``V_s = sum_n W_x dist(x_n | [xmin, xmax]) +
   W_s dist(x_n | [xs, inf))`` with Euclidean norms.  The hard input box is

@@ -1,4 +1,4 @@
-"""Scenario-tree bookkeeping (paper Sec. 3.3: stages, children ``child(j,i)``,
+"""Scenario-tree bookkeeping (paper Sec. 2.3: stages, children ``child(j,i)``,
 ancestor ``anc(j,i)``, node probability ``p_j^i``).
 
 Test infrastructure: part of the CPU oracle.

@@ -1,7 +1,8 @@
 """Build the tapg C-ABI library (HIP for gfx950) in-tree.
 
 ``python -m paper_1904_10548_amd.build`` compiles ``csrc/*.cpp`` and
-``csrc/*.hip`` with hipcc into ``paper_1904_10548_amd/libtapg.so``.
+``csrc/*.hip`` with hipcc (one object per source, in parallel, under
+``_build/``) and links them into ``paper_1904_10548_amd/libtapg.so``.
 """
 
 from __future__ import annotations
@@ -11,14 +12,16 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtapg.so")
+OBJ_DIR = os.path.join(ROOT, "_build", "tapg")
 
 # Packed FP32 instructions are disabled for all device code (the compiler is
 # free to form them from ordinary float code otherwise).
-HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
@@ -27,19 +30,42 @@ def sources():
     return sorted(glob.glob(os.path.join(c, "*.cpp"))) + sorted(glob.glob(os.path.join(c, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), *sources(), "-o", tmp]
+def _hipcc():
+    return os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+def _filter(stderr: str) -> str:
+    return "\n".join(line for line in stderr.splitlines()
+                     if "packed-fp32-ops" not in line and line.strip())
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+    cmd = [_hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
-    err = "\n".join(line for line in proc.stderr.splitlines()
-                    if "packed-fp32-ops" not in line and line.strip())
+    err = _filter(proc.stderr)
     if proc.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({proc.returncode}):\n{err}")
+        raise RuntimeError(f"hipcc failed on {os.path.basename(src)} ({proc.returncode}):\n{err}")
     if verbose and err:
         print(err, file=sys.stderr)
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    srcs = sources()
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    tmp = LIB + ".tmp"
+    cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"link failed ({proc.returncode}):\n{_filter(proc.stderr)}")
     os.replace(tmp, LIB)
     return LIB
 

@@ -914,7 +914,8 @@ void launch_scan(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t s
   switch (nbm) {
     case 4: launch_scan_nb<T, 4>(fwd, a, n_wg, st); break;
     case 2: launch_scan_nb<T, 2>(fwd, a, n_wg, st); break;
-    default: launch_scan_nb<T, 1>(fwd, a, n_wg, st); break;
+    case 1: launch_scan_nb<T, 1>(fwd, a, n_wg, st); break;
+    default: throw Fail{TAPG_EINVAL, "scan sweep: unsupported nodes per stage " + std::to_string(nbm)};
   }
 }
 

@@ -1038,7 +1038,8 @@ void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st
   switch (nbm) {
     case 4: launch_seg_nb<T, 4>(fwd, a, n_wg, st); break;
     case 2: launch_seg_nb<T, 2>(fwd, a, n_wg, st); break;
-    default: launch_seg_nb<T, 1>(fwd, a, n_wg, st); break;
+    case 1: launch_seg_nb<T, 1>(fwd, a, n_wg, st); break;
+    default: throw Fail{TAPG_EINVAL, "segment sweep: unsupported nodes per stage " + std::to_string(nbm)};
   }
 }
 
@@ -1048,7 +1049,8 @@ size_t seg_lds(int nbm, const SegArgs<T>& a) {
   switch (nbm) {
     case 4: return seg_lds_bytes<T, 4>(a);
     case 2: return seg_lds_bytes<T, 2>(a);
-    default: return seg_lds_bytes<T, 1>(a);
+    case 1: return seg_lds_bytes<T, 1>(a);
+    default: throw Fail{TAPG_EINVAL, "segment sweep: unsupported nodes per stage " + std::to_string(nbm)};
   }
 }
 
@@ -1064,7 +1066,8 @@ hipError_t launch_chain(int nbm, bool proj, const ChainArgs<T>& c, size_t lds, h
   switch (nbm) {
     case 4: return proj ? launch_chain_nb<T, 4, true>(c, lds, st) : launch_chain_nb<T, 4, false>(c, lds, st);
     case 2: return proj ? launch_chain_nb<T, 2, true>(c, lds, st) : launch_chain_nb<T, 2, false>(c, lds, st);
-    default: return proj ? launch_chain_nb<T, 1, true>(c, lds, st) : launch_chain_nb<T, 1, false>(c, lds, st);
+    case 1: return proj ? launch_chain_nb<T, 1, true>(c, lds, st) : launch_chain_nb<T, 1, false>(c, lds, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -1083,7 +1086,8 @@ int chain_blocks_per_cu(int nbm, bool proj, size_t lds) {
   switch (nbm) {
     case 4: return proj ? chain_occ<T, 4, true>(lds) : chain_occ<T, 4, false>(lds);
     case 2: return proj ? chain_occ<T, 2, true>(lds) : chain_occ<T, 2, false>(lds);
-    default: return proj ? chain_occ<T, 1, true>(lds) : chain_occ<T, 1, false>(lds);
+    case 1: return proj ? chain_occ<T, 1, true>(lds) : chain_occ<T, 1, false>(lds);
+    default: return 0;
   }
 }
 

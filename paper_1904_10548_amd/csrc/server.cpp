@@ -3,10 +3,12 @@
 // estimated device memory fits an HBM budget) iterating together as one
 // forest, and lets requests join and leave between chunks of iterations
 // (continuous batching).  A session's request is warm started when the
-// session's previous request solved the same tree.
+// session's previous request solved the same tree successfully and no other
+// session's request has written that tree's dual since.
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <deque>
 #include <memory>
 #include <mutex>
@@ -42,7 +44,11 @@ struct tapg_server_s {
   };
   std::deque<Req> pending;
   std::unordered_map<long long, Done> done;
-  std::unordered_map<int, uint64_t> session_tree;  // tree last solved for each session
+  // Warm starts: the tree each session last solved successfully, and the
+  // session whose request last wrote each tree's dual (its slot holds one dual
+  // per tree, so a session warm starts only from a dual it wrote itself).
+  std::unordered_map<int, uint64_t> session_tree;
+  std::unordered_map<uint64_t, int> dual_owner;
   long long next_ticket = 1;
   long long n_batches = 0, n_solved = 0;
   double busy_ms = 0.0;   // chunks of iterations
@@ -115,10 +121,20 @@ void worker_loop(tapg_server_s* srv) {
     for (auto& a : active) js.push_back(&a->lt);
     return js;
   };
+  // requests taken off the queue but not yet set up (see the admission below)
+  std::vector<tapg_server_s::Req> admitted;
+  size_t n_setup = 0;
   auto fail_all = [&](tapg_status code, const std::string& msg) {
     std::lock_guard<std::mutex> lk(srv->mu);
-    for (auto& a : active) complete(srv, a->req, code, nullptr, nullptr, msg);
+    for (auto& a : active) {
+      complete(srv, a->req, code, nullptr, nullptr, msg);
+      if (a->lt.t) srv->dual_owner.erase(a->lt.t->uid);
+    }
     active.clear();
+    for (size_t k = n_setup; k < admitted.size(); ++k)
+      complete(srv, admitted[k], code, nullptr, nullptr, msg);
+    admitted.clear();
+    n_setup = 0;
     in_forest = false;
     srv->cv_done.notify_all();
   };
@@ -139,14 +155,21 @@ void worker_loop(tapg_server_s* srv) {
       } catch (...) {
       }
       complete(srv, a->req, st, u0.data(), &a->lt.res, "");
-      srv->session_tree[a->req.session] = a->lt.t->uid;
+      // the tree's slot now holds this request's dual; a later request of the
+      // session may start from it only if it is finite
+      srv->dual_owner[a->lt.t->uid] = a->req.session;
+      if (st == TAPG_OK || st == TAPG_ENOTCONV)
+        srv->session_tree[a->req.session] = a->lt.t->uid;
+      else
+        srv->session_tree.erase(a->req.session);
       srv->n_solved++;
     }
     active.swap(keep);
     srv->cv_done.notify_all();
   };
   while (true) {
-    std::vector<tapg_server_s::Req> admitted;
+    admitted.clear();
+    n_setup = 0;
     std::vector<int> warm;
     {
       std::unique_lock<std::mutex> lk(srv->mu);
@@ -174,7 +197,11 @@ void worker_loop(tapg_server_s* srv) {
         used += b;
         trees_in.insert(t.uid);
         auto s = srv->session_tree.find(it->session);
-        warm.push_back(s != srv->session_tree.end() && s->second == t.uid ? 1 : 0);
+        auto o = srv->dual_owner.find(t.uid);
+        warm.push_back(s != srv->session_tree.end() && s->second == t.uid &&
+                               o != srv->dual_owner.end() && o->second == it->session
+                           ? 1
+                           : 0);
         admitted.push_back(std::move(*it));
         it = srv->pending.erase(it);
       }
@@ -191,8 +218,15 @@ void worker_loop(tapg_server_s* srv) {
           finish();
         }
         for (size_t k = 0; k < admitted.size(); ++k) {
-          auto a = std::make_unique<Active>();
+          // into the active set first, so that a failure below completes it
+          active.push_back(std::make_unique<Active>());
+          Active* a = active.back().get();
           a->req = std::move(admitted[k]);
+          n_setup = k + 1;
+          a->lt.t = &a->req.tree->h;
+          if (const char* f = std::getenv("TAPG_TEST_SERVER_SETUP_FAIL"))
+            if (std::atoll(f) == a->req.ticket)
+              throw Fail{TAPG_EDEVICE, "request setup failure injected for a test"};
           a->bytes = request_bytes(S, a->req.tree->h);
           a->lt.t = &a->req.tree->h;
           a->lt.own = &dev_slot(S, *a->lt.t);
@@ -201,8 +235,9 @@ void worker_loop(tapg_server_s* srv) {
           a->lt.gamma = solver_gamma(S, *a->lt.t, *a->lt.own);
           a->lt.warm = warm[k] != 0;
           dev_live_init(S, a->lt);
-          active.push_back(std::move(a));
         }
+        admitted.clear();
+        n_setup = 0;
       }
       if (active.empty()) continue;
       if (!in_forest) {

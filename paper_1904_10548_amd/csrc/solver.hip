@@ -1125,6 +1125,10 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
   hipStream_t st = S->stream;
   int wmax = 0;
   const std::vector<std::pair<int, int>> rp = level_ranges(t, B, wmax);
+  if (wmax > kSegNbMax)
+    throw Fail{TAPG_EINVAL, "scan forward launch: a workgroup would hold " + std::to_string(wmax) +
+                                " nodes of one stage (at most " + std::to_string(kSegNbMax) +
+                                "; TAPG_FWD_GROUP must be 0, 1, 2 or 4)"};
   const int N = t.N, nstB = B.s_end - B.s_begin + 1, nw = B.n_wg;
   std::vector<int2> rg((size_t)nw * N);
   std::vector<int> own((size_t)nw * N);
@@ -1255,8 +1259,10 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       sl.scan = S->scan && (ts == S->tuned_scan.end() ? S->scan_default : ts->second);
       auto tf = S->tuned_fwd.find(shape_key(t));
       const char* fg = std::getenv("TAPG_FWD_GROUP");
-      sl.fwd_group = (fg && fg[0]) ? std::max(0, std::atoi(fg))
-                                   : (tf == S->tuned_fwd.end() ? 0 : tf->second);
+      sl.fwd_group = (fg && fg[0]) ? std::atoi(fg) : (tf == S->tuned_fwd.end() ? 0 : tf->second);
+      if (sl.fwd_group != 0 && sl.fwd_group != 1 && sl.fwd_group != 2 && sl.fwd_group != 4)
+        throw Fail{TAPG_EINVAL, "TAPG_FWD_GROUP must be 0, 1, 2 or 4 (got " +
+                                    std::to_string(sl.fwd_group) + ")"};
     }
     sl.N = t.N;
     sl.elem = S->fp32 ? sizeof(float) : sizeof(double);

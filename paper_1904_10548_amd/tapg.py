@@ -360,13 +360,14 @@ def tapg_server_submit(srv, tree, p, q, session=0):
 
 
 def tapg_server_poll(srv, ticket, nu, wait_ms=-1):
-    """``(status, u0, result, latency_ms)``; status TAPG_ESTATE while pending."""
+    """``(status, u0, result, latency_ms)``; status TAPG_ESTATE while pending,
+    else the request's own status (an unknown ticket raises)."""
     u0 = np.zeros(nu)
     res = TapgResult()
     lat = np.zeros(1)
     st = lib().tapg_server_poll(srv, int(ticket), int(wait_ms), _ptr(u0), ctypes.byref(res),
                                 _ptr(lat))
-    if st not in (TAPG_OK, TAPG_ENOTCONV, TAPG_ESTATE, TAPG_ENOMEM, TAPG_ENUMERIC):
+    if st == TAPG_EINVAL:
         _check(st)
     return st, u0, res, float(lat[0])
 

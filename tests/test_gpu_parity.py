@@ -166,6 +166,8 @@ def test_wide_ragged_tree_fp64_and_fp32():
                           ("0:1,2:2,4:1", False, True, True, False, 0),
                           ("0:1,2:1,4:1,6:2,15:4", False, True, False, True, 0),
                           ("0:1,2:1,4:1,6:2,15:4", False, True, False, True, 1),
+                          ("0:1,2:1,4:1,6:1", False, True, False, True, 0),
+                          ("0:1,2:1,4:1,6:1", False, True, False, False, 0),
                           ("0:1,1:1,3:2,5:2", True, True, False, True, 0),
                           ("0:1,1:1,3:2,5:2", True, True, True, False, 0),
                           ("0:1,1:1,3:2,5:2", True, False, False, False, 0)])
@@ -200,23 +202,35 @@ def _dwn2048_reference():
     return P, gamma, iters, O.apg(P, gamma, sf, iters)
 
 
-@pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
-def test_dwn2048_cost_error_against_oracle(precision):
-    """The 2,048-scenario tree (K = 30,717): 30 iterations, cost within 1e-6
-    (FP64 sweeps) or 1e-4 (FP32 sweeps, FP64 factors and residuals) of the FP64
-    oracle's; the root input within the same relative bounds."""
+@pytest.mark.parametrize("precision,scan", [(tapg.TAPG_FP64, True), (tapg.TAPG_FP64, False),
+                                            (tapg.TAPG_FP32, True), (tapg.TAPG_FP32, False)])
+def test_dwn2048_against_oracle(precision, scan):
+    """The 2,048-scenario tree (K = 30,717), 30 iterations, in the scan form and
+    in the segment form with projector factors (the autotuner's choices for this
+    tree in FP32 and FP64): in FP64 u, x and y element by element against the
+    oracle's, cost within 1e-6; with FP32 sweeps (FP64 factors and residuals)
+    cost and root input within 1e-4 of the FP64 oracle's."""
     P, gamma, iters, ref = _dwn2048_reference()
-    say("dwn2048", P.tree.K, "prec", precision)
+    _schedule_env(scan=scan)
+    say("dwn2048", P.tree.K, "prec", precision, "scan", scan)
     with make_solver(P, gamma=gamma, tol=0.0, max_iter=iters, check_every=iters,
                      precision=precision) as S:
         t = add_tree(S, P)
         st, u0, res = S.solve(t, P.p, P.q)
+        form = tapg.tapg_sweep_form(S.h, [t])
+        if precision == tapg.TAPG_FP64:
+            u, x = S.primal(t)
+            y = S.dual(t)
+            hist = tapg.tapg_residual_history(S.h, t, iters)
+    assert form[0] == ("scan" if scan else "projector")
     J = O.primal_cost(P, ref.u, ref.x)
     rel = abs(res.cost - J) / max(1.0, abs(J))
     du = np.abs(u0 - ref.u[0]).max() / max(1.0, np.abs(ref.u[0]).max())
     say("dwn2048 cost", res.cost, "oracle", J, "rel", rel, "root du", du)
-    bound = 1e-6 if precision == tapg.TAPG_FP64 else 1e-4
-    assert res.iters == iters and rel <= bound and du <= bound * 10
+    if precision == tapg.TAPG_FP64:
+        _assert_fp64_parity(P, res, u, x, y, hist, ref, iters)
+        return
+    assert res.iters == iters and rel <= 1e-4 and du <= 1e-3
 
 
 def test_small_converged_matches_oracle_iteration_count():
@@ -403,3 +417,68 @@ def test_forward_groupings_bit_identical():
     for fg in (1, 2, 4):
         for a, b in zip(out[0], out[fg]):
             assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_max_iter_before_tolerance_is_enotconv():
+    """A tolerance the iteration cannot reach within max_iter: TAPG_ENOTCONV,
+    with the iterate of the last iteration (the same as a fixed-count run), for
+    a single tree and in a batch."""
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    iters = 57
+    ref = _oracle_run(P, gamma, iters, factors=nf)
+    with make_solver(P, gamma=gamma, tol=1e-14, max_iter=iters, check_every=10) as S:
+        t = add_tree(S, P)
+        st, u0, res = S.solve(t, P.p, P.q)
+        u, x = S.primal(t)
+        stb, u0b, rb = S.batch_solve([t], [P.p], [P.q])
+    assert st == tapg.TAPG_ENOTCONV and stb == tapg.TAPG_ENOTCONV
+    assert res.iters == iters and not res.converged and res.primal_res > 1e-14
+    assert rb[0].iters == iters and not rb[0].converged
+    assert np.abs(u - ref.u).max() <= 1e-9 * max(1.0, np.abs(ref.u).max())
+    assert np.abs(u0b - u0).max() <= 1e-12 * max(1.0, np.abs(u0).max())
+
+
+def test_diverging_step_size_is_enumeric():
+    """A step size 100 times 1/L makes the dual iterates grow until they are
+    no longer finite (the oracle's run with this step size does so at
+    iteration 373; every kernel still completes): the solve returns
+    TAPG_ENUMERIC, a single tree and a batch alike, and the solver stays
+    usable."""
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    L = O.lipschitz_dense(P, nf)
+    with np.errstate(all="ignore"):
+        ref = _oracle_run(P, 100.0 / L, 3000, tol=1e-300, factors=nf)
+    bad = np.flatnonzero(~np.isfinite(np.asarray(ref.res_hist)))
+    assert bad.size and bad[0] < 1000
+    with make_solver(P, gamma=100.0 / L, tol=1e-6, max_iter=3000, check_every=50) as S:
+        t = add_tree(S, P)
+        with pytest.raises(tapg.TapgError) as e:
+            S.solve(t, P.p, P.q)
+        assert e.value.status == tapg.TAPG_ENUMERIC
+        with pytest.raises(tapg.TapgError) as e:
+            S.batch_solve([t], [P.p], [P.q])
+        assert e.value.status == tapg.TAPG_ENUMERIC
+        r = tapg.tapg_residuals(S.h, t)
+        assert r.iters <= bad[0] + 2 and not r.converged
+    with make_solver(P, gamma=1.0 / L, tol=1e-6, max_iter=20000, check_every=50) as S:
+        t = add_tree(S, P)
+        st, u0, res = S.solve(t, P.p, P.q)
+        assert st == tapg.TAPG_OK and res.converged
+
+
+def test_forward_group_out_of_range_is_rejected():
+    """The scan form's forward launch holds at most 4 leaves per workgroup:
+    other groupings are refused with TAPG_EINVAL instead of being run."""
+    P = ds.config_problem("dwn128")
+    for fg in ("3", "5", "8"):
+        _schedule_env(scan=True)
+        os.environ["TAPG_FWD_GROUP"] = fg
+        with make_solver(P, gamma=1e-6, tol=0.0, max_iter=2, check_every=2) as S:
+            t = add_tree(S, P)
+            with pytest.raises(tapg.TapgError) as e:
+                S.solve(t, P.p, P.q)
+            assert e.value.status == tapg.TAPG_EINVAL
+    os.environ.pop("TAPG_FWD_GROUP", None)

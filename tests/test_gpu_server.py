@@ -135,3 +135,62 @@ def test_solver_forget_releases_and_resolves():
             S.primal(t)  # nothing held for the tree any more
         _, u0b, rb = S.solve(t, batch[0].p, batch[0].q)
     assert ra.iters == rb.iters and np.array_equal(u0a, u0b)
+
+
+def test_server_setup_failure_completes_every_ticket():
+    """A failure while a set of requests is set up (forced from the host for
+    one ticket) completes every request of that set with the error instead of
+    leaving its tickets pending; later requests are served normally."""
+    batch = tiny_batch(SHAPES, seed=43)
+    nu = batch[0].net.nu
+    os.environ["TAPG_TEST_SERVER_SETUP_FAIL"] = "2"
+    try:
+        with make_solver(batch[0], gamma=0.0, tol=1e-6, max_iter=20000, check_every=20) as S:
+            trees = [add_tree(S, P) for P in batch]
+            srv = tapg.tapg_server_create(S.h, 1 << 34, 64)
+            try:
+                tk = [tapg.tapg_server_submit(srv, t, P.p, P.q, session=k)
+                      for k, (t, P) in enumerate(zip(trees, batch))]
+                first = [tapg.tapg_server_poll(srv, x, nu, wait_ms=60000) for x in tk]
+                tk2 = [tapg.tapg_server_submit(srv, t, P.p, P.q, session=k)
+                       for k, (t, P) in enumerate(zip(trees, batch))]
+                second = [tapg.tapg_server_poll(srv, x, nu, wait_ms=60000) for x in tk2]
+            finally:
+                tapg.tapg_server_destroy(srv)
+    finally:
+        os.environ.pop("TAPG_TEST_SERVER_SETUP_FAIL", None)
+    say("setup failure", [o[0] for o in first], [o[0] for o in second])
+    assert all(o[0] != tapg.TAPG_ESTATE for o in first)  # nothing left pending
+    assert first[1][0] == tapg.TAPG_EDEVICE
+    assert all(o[0] == tapg.TAPG_OK and o[2].converged for o in second)
+
+
+def test_server_warm_start_only_from_the_sessions_own_dual():
+    """Two sessions request the same tree in turn: the tree keeps one dual, so
+    a session's second request is warm started only if no other session solved
+    the tree in between; otherwise it runs cold, with the cold result."""
+    batch = tiny_batch(SHAPES[:1], seed=47)
+    P = batch[0]
+    nu = P.net.nu
+    kw = dict(gamma=0.0, tol=1e-6, max_iter=20000, check_every=10)
+    pA, pB = P.p, P.p + 0.3
+    with make_solver(P, **kw) as S:
+        t = add_tree(S, P)
+        srv = tapg.tapg_server_create(S.h, 1 << 34, 64)
+        try:
+            seq = []
+            for p, sess in ((pA, 1), (pB, 2), (pA, 1), (pA, 1)):
+                x = tapg.tapg_server_submit(srv, t, p, P.q, session=sess)
+                seq.append(tapg.tapg_server_poll(srv, x, nu, wait_ms=60000))
+        finally:
+            tapg.tapg_server_destroy(srv)
+    with make_solver(P, **kw) as S:
+        t = add_tree(S, P)
+        _, u_cold, r_cold = S.solve(t, pA, P.q)
+        _, u_warm, r_warm = S.solve(t, pA, P.q, warm_start=True)
+    assert all(o[0] == tapg.TAPG_OK for o in seq)
+    # third request: session 2 wrote the tree's dual in between -> cold
+    assert seq[2][2].iters == r_cold.iters
+    assert np.abs(seq[2][1] - u_cold).max() <= 1e-12 * max(1.0, np.abs(u_cold).max())
+    # fourth request: the session's own dual -> warm, as a warm tapg_solve
+    assert seq[3][2].iters == r_warm.iters and r_warm.iters < r_cold.iters

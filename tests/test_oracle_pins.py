@@ -432,7 +432,7 @@ def test_apg_optimum_matches_slsqp(seed, p_level, price_scale):
 
 
 # ---------------------------------------------------------------------------
-# Problem size convention vs the numbers printed in the paper (Sec. 6.4)
+# Problem size convention vs the numbers printed in the paper (Sec. 6.3)
 # ---------------------------------------------------------------------------
 def test_variable_counts_match_paper():
     """One input u (nu) and one post-decision state x (nx) per node, and a
