@@ -58,6 +58,13 @@ typedef enum {
 
 enum { TAPG_FP64 = 0, TAPG_FP32 = 1 };
 
+/* Extrapolation weights of the accelerated iteration (Sec. 4.3, eq. apg:1):
+ * beta_nu = theta_nu (1/theta_{nu-1} - 1), theta_0 = theta_{-1} = 1, with
+ *   TAPG_BETA_PAPER   theta_{nu+1} = (sqrt(theta_nu^4 + 4 theta_nu^2) - theta_nu^2)/2
+ *   TAPG_BETA_SIMPLE  theta_nu = 2/(nu + 2) for nu >= 1 (the paper's simpler choice)
+ *   TAPG_BETA_ZERO    beta = 0: the plain dual proximal gradient method */
+enum { TAPG_BETA_PAPER = 0, TAPG_BETA_SIMPLE = 1, TAPG_BETA_ZERO = 2 };
+
 /* Solver configuration (the paper's SmpcConfiguration, Sec. 5.1: tuning
  * weights, tolerance, maximum iterations). */
 typedef struct {
@@ -75,6 +82,16 @@ typedef struct {
   int power_iters;         /* power iterations for L when gamma <= 0 (0 selects 100) */
   int device;              /* HIP device ordinal */
   void* hip_stream;        /* hipStream_t to launch on; NULL: the solver creates its own */
+  int beta_rule;           /* TAPG_BETA_* (0: the paper's theta recursion) */
+  int averaged_primal;     /* 1: return the averaged primal iterate (Sec. 4.3: O(1/nu^2)),
+                              xbar^nu = (1 - theta_nu) xbar^{nu-1} + theta_nu x_hat(w^nu),
+                              xbar^0 = x_hat(w^0); with TAPG_BETA_ZERO theta_nu = 1/(nu+1),
+                              the running mean.  tapg_solve only (batches: TAPG_EINVAL) */
+  double gap_tol;          /* > 0: the stop test becomes |dual_gap| <= gap_tol and (if tol > 0)
+                              the last residual <= tol, both tested every check_every iterations
+                              (one extra dual-gradient sweep per gap test); tapg_solve only.
+                              The gap alone is no certificate (it uses the split variable t),
+                              with the residual it is */
 } tapg_config;
 
 typedef struct {
@@ -86,6 +103,12 @@ typedef struct {
   double viol_eq;     /* max of |E u + Ed d|_inf and the dynamics residual */
   double gamma;       /* step size used */
   double solve_ms;    /* device time of the solve (data step + iterations), HIP events */
+  double dual_gap;    /* duality gap of the returned dual y (Sec. 4.2, strong duality), FP64:
+                         G = f(x') + g(t) + F(y) with x' = x_hat(y), t = prox_{g/gamma}(y/gamma
+                         + H x') and F the dual objective; -> 0 at the optimum.  NaN unless
+                         evaluated (tapg_residuals always evaluates it; tapg_solve when
+                         gap_tol > 0) */
+  double dual_obj;    /* F(y) = f*(-H'y) + g*(y), the dual objective (minimised); NaN as above */
 } tapg_result;
 
 /* Network (the paper's DwnNetwork, Sec. 5.1; model of Sec. 2).
@@ -180,7 +203,11 @@ tapg_status tapg_set_dual(tapg_solver solver, tapg_tree tree, const double* y);
 tapg_status tapg_residual_history(tapg_solver solver, tapg_tree tree, double* hist, int n,
                                   int* written);
 /* Statistics of the last solve of this tree (primal residual, cost,
- * violations); same fields as tapg_solve's result. */
+ * violations); same fields as tapg_solve's result, with the duality gap and
+ * the dual objective of the tree's current dual (its last solve's, or the one
+ * tapg_set_dual gave it) evaluated on the device in FP64 if the solve did not
+ * (one dual-gradient sweep; Sec. 4.2 and 4.4); after a diverged solve they
+ * stay NaN.  TAPG_ESTATE before a solve. */
 tapg_status tapg_residuals(tapg_solver solver, tapg_tree tree, tapg_result* res);
 
 /* Lipschitz constant of the dual gradient of this tree by `iters` power

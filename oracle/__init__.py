@@ -17,7 +17,8 @@ dual_gradient   x_hat(w) = argmin f(x) + <w, Hx>: per-node DP, per-stage DP,
                 dense KKT
 prox            distance-function prox, box projection, Moreau decomposition
 apg             the accelerated proximal gradient on the Fenchel dual
-objective       primal cost, constraint violations, dual objective
+objective       primal cost, constraint violations, dual objective,
+                duality gap of a dual point
 stepsize        Lipschitz constant of the dual gradient (power iteration and
                 the dense eigenvalue for tiny trees)
 
@@ -37,8 +38,9 @@ from .dual_gradient import (
     particular_inputs,
 )
 from .prox import prox_dist, proj_box, proj_lower, prox_g, prox_gconj
-from .apg import APGResult, apg, theta_next, beta_sequence
-from .objective import primal_cost, violations, dual_objective, g_conj, split_residual
+from .apg import APGResult, apg, theta_next, theta_of, beta_sequence
+from .objective import primal_cost, violations, dual_objective, g_conj, g_value, \
+    split_residual, split_gap
 from .stepsize import lipschitz_power, lipschitz_dense, dual_hessian_dense
 
 __all__ = [
@@ -58,12 +60,15 @@ __all__ = [
     "APGResult",
     "apg",
     "theta_next",
+    "theta_of",
     "beta_sequence",
     "primal_cost",
     "violations",
     "dual_objective",
     "g_conj",
     "split_residual",
+    "split_gap",
+    "g_value",
     "lipschitz_power",
     "lipschitz_dense",
     "dual_hessian_dense",

@@ -7,6 +7,7 @@ TEST INFRASTRUCTURE (CPU oracle).
   unweighted soft penalties ``V_s = sum_n W_x dist(x_n | [xmin, xmax]) +
   W_s dist(x_n | [xs, inf))`` with Euclidean norms.  The hard input box is
   not part of the cost; its violation is reported separately.
+* Duality gap of a dual point (``split_gap``) from the two objectives.
 * Dual objective (Sec. 4.2, problem D): ``F(y) = f*(-H'y) + g*(y)`` with
   ``f*(-H'y) = -[f(x_hat(y)) + <y, H x_hat(y)>]`` and
   ``g*(y) = sum_n sigma_X(y1_n) + xs'y2_n + sigma_U(y3_n)`` on its domain
@@ -83,6 +84,40 @@ def g_conj(problem, y: np.ndarray, slack: float = 1e-9) -> float:
     val += float(np.sum(y2 @ net.xs))
     val += _support_box(y3, net.umin, net.umax).sum()
     return float(val)
+
+
+def g_value(problem, z: np.ndarray, slack: float = 1e-9) -> float:
+    """``g(z)`` of the split form (Sec. 4.1, eq. g): per node
+    ``W_x dist(z1|[xmin,xmax]) + W_s dist(z2|[xs,inf))`` plus the indicator
+    of ``z3`` in the input box (``+inf`` outside it, with a relative slack)."""
+    net, w = problem.net, problem.weights
+    nx, nu = net.nx, net.nu
+    z1, z2, z3 = z[:, :nx], z[:, nx:2 * nx], z[:, 2 * nx:2 * nx + nu]
+    span = np.maximum(1.0, np.abs(net.umax - net.umin))
+    if np.any(z3 < net.umin - slack * span) or np.any(z3 > net.umax + slack * span):
+        return np.inf
+    d1 = np.linalg.norm(z1 - proj_box(z1, net.xmin, net.xmax), axis=1)
+    d2 = np.linalg.norm(z2 - proj_lower(z2, net.xs), axis=1)
+    return float(np.sum(w.W_x * d1 + w.W_s * d2))
+
+
+def split_gap(problem, y: np.ndarray, gamma: float, factors):
+    """Duality gap of a dual point ``y`` at the primal pair ``y`` determines
+    (Sec. 4.2, Fenchel dual and strong duality): with ``x' = x_hat(y)`` and
+    ``t = prox_{g/gamma}(y/gamma + H x')`` (the split variable of one more
+    proximal-gradient step from ``y``),
+
+        G(y) = f(x') + g(t) + F(y),   F(y) = f*(-H'y) + g*(y).
+
+    Weak duality and Fenchel-Young give ``G(y) >= <y, t - H x'>``, and ``G = 0``
+    at a dual optimum.  Returns ``(G, F)``."""
+    from .prox import prox_gconj
+
+    u, x = dual_gradient(problem, y, factors)
+    hx = np.concatenate([x, x, u], axis=1)
+    _, t = prox_gconj(y + gamma * hx, gamma, problem.net, problem.weights)
+    F = dual_objective(problem, y, factors)
+    return smooth_cost(problem, u) + g_value(problem, t) + F, F
 
 
 def dual_objective(problem, y: np.ndarray, factors) -> float:

@@ -299,6 +299,12 @@ tapg_status tapg_solver_create(tapg_network net, const tapg_config* cfg, tapg_so
     if (cfg->precision != TAPG_FP64 && cfg->precision != TAPG_FP32)
       fail(TAPG_EINVAL, "precision must be TAPG_FP64 or TAPG_FP32");
     if (!std::isfinite(cfg->gamma) || !std::isfinite(cfg->tol)) fail(TAPG_EINVAL, "non-finite gamma/tol");
+    if (cfg->beta_rule != TAPG_BETA_PAPER && cfg->beta_rule != TAPG_BETA_SIMPLE &&
+        cfg->beta_rule != TAPG_BETA_ZERO)
+      fail(TAPG_EINVAL, "beta_rule must be TAPG_BETA_PAPER, TAPG_BETA_SIMPLE or TAPG_BETA_ZERO");
+    if (cfg->averaged_primal != 0 && cfg->averaged_primal != 1)
+      fail(TAPG_EINVAL, "averaged_primal must be 0 or 1");
+    if (!std::isfinite(cfg->gap_tol) || cfg->gap_tol < 0) fail(TAPG_EINVAL, "gap_tol must be >= 0");
     if (!finite_all(cfg->W_u, (size_t)h.nu * h.nu) || !finite_all(cfg->alpha0, h.nu) ||
         !finite_all(cfg->c_energy, h.nu))
       fail(TAPG_ENUMERIC, "non-finite weights");
@@ -468,6 +474,8 @@ void batch_core(tapg_solver_s* solver, int ntrees, const tapg_tree* trees, const
   need(p, "p");
   need(q, "q");
   if (ntrees < 1) fail(TAPG_EINVAL, "ntrees must be >= 1");
+  if (solver->cfg.averaged_primal || solver->cfg.gap_tol > 0)
+    fail(TAPG_EINVAL, "the averaged primal and the gap test are for single-tree solves (tapg_solve)");
   std::vector<const TreeHost*> th(ntrees);
   std::vector<Slot*> own(ntrees);
   std::vector<double> gamma(ntrees);
@@ -671,6 +679,11 @@ tapg_status tapg_residuals(tapg_solver solver, tapg_tree tree, tapg_result* res)
   return guarded([&]() -> tapg_status {
     need(res, "res");
     Slot& sl = existing_slot(solver, tree);
+    if (!sl.gap_valid && !sl.numeric) {  // (a diverged dual has no gap: NaN)
+      Slot& cur = dev_slot(solver, tree->h);  // the tree's current data on the device
+      double gap = 0.0, F = 0.0;
+      dev_gap(solver, tree->h, cur, &gap, &F);
+    }
     *res = sl.last;
     return TAPG_OK;
   });

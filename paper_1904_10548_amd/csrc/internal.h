@@ -102,7 +102,7 @@ struct DevCtl {
   int converged;    // residual reached tol
   int numeric;      // non-finite residual seen
   int max_iter;
-  int pad0;
+  int rule;         // theta/beta rule (tapg_config.beta_rule)
   double tol;
   double gamma;
   double theta, theta_prev, beta;
@@ -142,6 +142,7 @@ struct Slot {
   void *d_kperp = nullptr, *d_zb = nullptr, *d_zr = nullptr;
   void *d_Y0 = nullptr, *d_Y1 = nullptr, *d_lam = nullptr, *d_j = nullptr, *d_u = nullptr,
        *d_x = nullptr;
+  void *d_ua = nullptr, *d_xa = nullptr;  // averaged primal (single-tree solves that ask for it)
   DevCtl* d_ctl = nullptr;
   double* d_hist = nullptr;
   int hist_cap = 0;
@@ -158,6 +159,8 @@ struct Slot {
   bool L_valid = false;
   tapg_result last{};
   bool has_result = false;
+  std::vector<double> last_pq;  // (p | q) of the last solve, LDX + LDU doubles
+  bool gap_valid = false;       // last.dual_gap / dual_obj hold the gap of the current dual
   bool numeric = false;  // the last solve hit a non-finite residual
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;

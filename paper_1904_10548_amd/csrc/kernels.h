@@ -5,14 +5,40 @@
 
 namespace tapg {
 
+// The extrapolation weights of the next iteration (Sec. 4.3, eq. apg:1):
+// beta_{nu+1} = theta_{nu+1} (1/theta_nu - 1) with theta_0 = theta_{-1} = 1 and,
+// by `rule` (tapg_config.beta_rule),
+//   TAPG_BETA_PAPER  theta_{nu+1} = (sqrt(theta_nu^4 + 4 theta_nu^2) - theta_nu^2) / 2
+//   TAPG_BETA_SIMPLE theta_nu = 2 / (nu + 2) for nu >= 1
+//   TAPG_BETA_ZERO   beta = 0 (the plain dual proximal gradient); theta_nu =
+//                    1 / (nu + 1), the weights of the running primal mean
+// `done` is nu + 1, the iterations completed.  Written once, with no FMA
+// contraction, so that every workgroup and launch computes the same values.
+__device__ inline void theta_update(int rule, int done, double& theta, double& theta_prev,
+                                    double& beta) {
+#pragma clang fp contract(off)
+  const double th = theta;
+  double thn;
+  if (rule == TAPG_BETA_SIMPLE) {
+    thn = 2.0 / (double)(done + 2);
+  } else if (rule == TAPG_BETA_ZERO) {
+    thn = 1.0 / (double)(done + 1);
+  } else {
+    const double t2 = th * th;
+    thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
+  }
+  theta_prev = th;
+  theta = thn;
+  beta = rule == TAPG_BETA_ZERO ? 0.0 : thn * (1.0 / th - 1.0);
+}
+
 // End of one APG iteration for one tree (Sec. 4.3): from its control state
 // and the residual max |y+ - w| / gamma that the forward sweep left in
 // res_bits, the state of the next iteration: residual recorded (*res, and
 // *record when the tree was still running), iteration count, stop flags,
-// theta_{nu+1} = (sqrt(theta^4 + 4 theta^2) - theta^2) / 2 and
-// beta_{nu+1} = theta_{nu+1} (1/theta_nu - 1).  A stopped tree's state is
-// returned unchanged.  Every caller uses this one routine, so the closing
-// launch and the workgroups that close an iteration themselves agree bit for bit.
+// theta and beta (theta_update).  A stopped tree's state is returned
+// unchanged.  Every caller uses this one routine, so the closing launch and
+// the workgroups that close an iteration themselves agree bit for bit.
 __device__ inline DevCtl ctl_advance(DevCtl c, bool* record, double* res) {
   *record = false;
   if (c.done) return c;
@@ -31,12 +57,7 @@ __device__ inline DevCtl ctl_advance(DevCtl c, bool* record, double* res) {
   } else if (c.iter >= c.max_iter) {
     c.done = 1;
   }
-  const double th = c.theta;
-  const double t2 = th * th;
-  const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
-  c.theta_prev = th;
-  c.theta = thn;
-  c.beta = thn * (1.0 / th - 1.0);
+  theta_update(c.rule, c.iter, c.theta, c.theta_prev, c.beta);
   return c;
 }
 
@@ -51,7 +72,8 @@ template <typename T>
 struct SweepArgs {
   int nx, nu, LDX, LDU, LDY;
   int s, node0, count, tile_base;
-  int mode;  // 0: APG iteration, 1: power iteration (zero data, no prox)
+  int mode;  // 0: APG iteration, 1: power iteration (zero data, no prox),
+             // 2: evaluation of x_hat(w) only (u, x written; no dual update)
   const int* anc;
   const int* cbeg;
   const int* cend;
@@ -217,6 +239,10 @@ template <typename T>
 void launch_bwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
 template <typename T>
 void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st);
+// Averaged primal update of one tree (nu_el = K * LDU entries of u, nx_el = K * LDX of x).
+template <typename T>
+void launch_avg(const DevCtl* ctl, const T* u, const T* x, T* ua, T* xa, size_t nu_el,
+                size_t nx_el, hipStream_t st);
 // End of an iteration of ntrees trees (per-tree control blocks and histories).
 void launch_iter_end(DevCtl* c, double* hist, int ntrees, int hist_stride, hipStream_t st);
 // The same from the states in prev into out (out == prev allowed).
@@ -243,6 +269,17 @@ void launch_cost(int K, int nx, int nu, int nd, int ns, int LDX, int LDU, const 
 // per-node terms written by launch_cost: out[3 k .. 3 k + 2].
 void launch_cost_reduce_forest(const double* part, const int* tstart, int N, int ntrees,
                                double* out, hipStream_t st);
+// Duality-gap terms of a dual y and its primal (u, x) = x_hat(y), FP64 (gap_kernels.hip):
+// out[0..3] = f(x'), <y, H x'>, g*(y), g(t) summed over the K nodes.
+void launch_gap_terms(int K, int nx, int nu, int LDX, int LDU, int LDY, const int* anc,
+                      const double* prob, const double* price, const double* y, const double* u,
+                      const double* x, const double* pq, const double* Wu, const double* alpha0,
+                      const double* cE, const double* xmin, const double* xmax, const double* xs,
+                      const double* umin, const double* umax, double W_alpha, double W_x,
+                      double W_s, double gamma, double* part, double* out, hipStream_t st);
+// dst[i] = (double) src[i], i < n.
+template <typename T>
+void launch_widen(const T* src, double* dst, size_t n, hipStream_t st);
 // Row gather (dst[r] = src[idx[r]]) or scatter (dst[idx[r]] = src[r]).
 template <typename T>
 void launch_copy_rows(const T* src, int ld_src, T* dst, int ld_dst, const int* idx, int rows,

@@ -883,19 +883,6 @@ __global__ __launch_bounds__(kSegThreads) void seg_fwd_kernel(SegArgs<T> a) {
 // ---------------------------------------------------------------------------
 namespace {
 
-// One step of the FISTA theta recursion (the extrapolation weights), written
-// once so that every workgroup and the closing code compute bit-identical
-// values (no contraction into FMAs).
-__device__ __forceinline__ void theta_step(double& theta, double& theta_prev, double& beta) {
-#pragma clang fp contract(off)
-  const double th = theta;
-  const double t2 = th * th;
-  const double thn = 0.5 * (sqrt(t2 * t2 + 4.0 * t2) - t2);
-  theta_prev = th;
-  theta = thn;
-  beta = thn * (1.0 / th - 1.0);
-}
-
 // A hand-over wait is declared stuck after 2 s of the 100 MHz real-time
 // counter (an iteration takes well under a millisecond).
 constexpr unsigned long long kChainWaitTicks = 200000000ull;
@@ -944,6 +931,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_chain_kernel(ChainArgs<T> c) 
   const int2 par = c.parents[g];  // parent workgroups [par.x, par.y] (par.x < 0: top level)
   const unsigned need = (unsigned)c.nchild[g];
   int it = ctl->iter;
+  const int rule = ctl->rule;
   double theta = ctl->theta, theta_prev = ctl->theta_prev, beta = ctl->beta;
   const double gam64 = ctl->gamma;
   // the top workgroup ends iteration `prev` once all forward sweeps of it are in
@@ -966,7 +954,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_chain_kernel(ChainArgs<T> c) 
         ctl->done = 1;
       }
       double th = ctl->theta, thp = ctl->theta_prev, be = ctl->beta;
-      theta_step(th, thp, be);
+      theta_update(rule, prev + 1, th, thp, be);
       ctl->theta = th;
       ctl->theta_prev = thp;
       ctl->beta = be;
@@ -1006,7 +994,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_chain_kernel(ChainArgs<T> c) 
       __hip_atomic_fetch_add(&sync->fwd_all, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     ++it;
-    theta_step(theta, theta_prev, beta);
+    theta_update(rule, it, theta, theta_prev, beta);
   }
   // the last iteration of the launch ends here (unless the solve stopped)
   if (l == 0 && k == c.iters) end_iteration(it - 1, (unsigned)c.total * (unsigned)c.iters);

@@ -166,6 +166,8 @@ void dev_batch_solve(tapg_solver_s* S, const std::vector<const TreeHost*>& trees
                      const double* const* q, const int* warm, const std::vector<double>& gamma,
                      tapg_result* res);
 double dev_power(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters);
+// Duality gap G and dual objective F of the tree's current dual (FP64).
+void dev_gap(tapg_solver_s* S, const TreeHost& t, Slot& sl, double* gap, double* dual_obj);
 void dev_get_primal(tapg_solver_s* S, Slot& sl, double* u, double* x);
 void dev_get_dual(tapg_solver_s* S, Slot& sl, double* y);
 void dev_get_root_input(tapg_solver_s* S, Slot& sl, double* u0);

@@ -421,6 +421,10 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
         }
       }
     }
+    if (mode == 0 && sl.d_ua)
+      launch_avg<T>(a.ctl, static_cast<const T*>(sl.d_u), static_cast<const T*>(sl.d_x),
+                    static_cast<T*>(sl.d_ua), static_cast<T*>(sl.d_xa), (size_t)sl.K * S->LDU,
+                    (size_t)sl.K * S->LDX, st);
     // the power iteration's step ends in a launch of its own (the forward
     // workgroups left their partial sums in device memory)
     if (mode == 1)
@@ -457,6 +461,10 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
     }
   }
   if (mode == 0) {
+    if (sl.d_ua)
+      launch_avg<T>(sl.d_ctl, static_cast<const T*>(sl.d_u), static_cast<const T*>(sl.d_x),
+                    static_cast<T*>(sl.d_ua), static_cast<T*>(sl.d_xa), (size_t)sl.K * S->LDU,
+                    (size_t)sl.K * S->LDX, st);
     if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
     launch_iter_end(sl.d_ctl, sl.d_hist, 1, 0, st);
     if (tc) {
@@ -533,7 +541,8 @@ bool chain_usable(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
   const char* env = std::getenv("TAPG_CHAIN");
   if (!(env && env[0] == '1')) return false;
   const int nl = (int)sl.levels.size();
-  if (t.ntrees != 1 || !sl.segmented || !S->proj || sl.scan || nl < 1 || nl > kChainMaxLevels)
+  if (t.ntrees != 1 || !sl.segmented || !S->proj || sl.scan || nl < 1 || nl > kChainMaxLevels ||
+      sl.d_ua)
     return false;
   int total = 0, nbm = 1;
   for (const Slot::Level& L : sl.levels) {
@@ -678,6 +687,21 @@ void data_step(tapg_solver_s* S, Slot& sl, int K, hipStream_t st) {
 }
 
 template <typename T>
+void gap_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, double gamma, double* out);
+
+// Gap G and dual objective F of the slot's current dual (gap_impl's terms).
+template <typename T>
+void gap_impl_at(tapg_solver_s* S, const TreeHost& t, Slot& sl, double gamma, double* gap,
+                 double* dual_obj) {
+  double o[4];
+  gap_impl<T>(S, t, sl, gamma, o);
+  // F(y) = -f(x') - <y, H x'> + g*(y);  G = f(x') + g(t) + F(y)
+  const double F = -o[0] - o[1] + o[2];
+  *dual_obj = F;
+  *gap = o[0] + o[3] + F;
+}
+
+template <typename T>
 void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
                 const double* q, bool warm, double gamma, tapg_result& res) {
   const NetworkHost& h = S->net;
@@ -689,10 +713,23 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   for (int i = 0; i < h.nx; ++i) pq64[i] = p[i];
   for (int i = 0; i < h.nu; ++i) pq64[LDX + i] = q[i];
   upload_pq<T>(S, sl, pq64, st);
+  sl.last_pq = pq64;
+  sl.gap_valid = false;
+  // averaged primal: its buffers join the iteration's launches (a graph
+  // captured without them is rebuilt)
+  if (S->cfg.averaged_primal && !sl.d_ua) {
+    sl.d_ua = dmalloc<T>((size_t)K * LDU);
+    sl.d_xa = dmalloc<T>((size_t)K * LDX);
+    if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+    sl.graph = nullptr;
+    sl.chain_state = -1;
+  }
   // control block
   DevCtl c{};
   c.max_iter = S->cfg.max_iter;
-  c.tol = S->cfg.tol;
+  // with a gap test the host decides the stop (residual and gap together)
+  c.tol = S->cfg.gap_tol > 0.0 ? 0.0 : S->cfg.tol;
+  c.rule = S->cfg.beta_rule;
   c.gamma = gamma;
   c.theta = 1.0;
   c.theta_prev = 1.0;
@@ -730,6 +767,8 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   }
   DevCtl hc{};
   int launched = 0;
+  double gap = NAN, dual_obj = NAN;
+  bool gap_valid = false;
   ProgressLine progress("solve");
   const bool timed = S->time_kernels;
   if (timed) {
@@ -801,9 +840,28 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
     TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
     TAPG_HIP(hipStreamSynchronize(st));
     progress.tick(launched, hc.done ? 0 : 1, 1);
+    if (!hc.done && S->cfg.gap_tol > 0.0 && (S->cfg.tol <= 0.0 || hc.last_res <= S->cfg.tol)) {
+      // stop when the duality gap of the current dual is within gap_tol and
+      // the last iteration's residual within tol (tested between chunks)
+      sl.last_iter_parity = hc.iter & 1;
+      sl.has_dual = true;
+      double F = 0.0;
+      gap_impl_at<T>(S, t, sl, gamma, &gap, &F);
+      dual_obj = F;
+      if (std::fabs(gap) <= S->cfg.gap_tol) {
+        hc.done = 1;
+        hc.converged = 1;
+        TAPG_HIP(hipMemcpyAsync(sl.d_ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, st));
+        gap_valid = true;
+      }
+    }
     if (hc.done || launched >= S->cfg.max_iter) break;
   }
   TAPG_HIP(hipEventRecord(S->ev1, st));
+  if (sl.d_ua) {  // the averaged primal is the one returned
+    TAPG_HIP(hipMemcpyAsync(sl.d_u, sl.d_ua, (size_t)K * LDU * sizeof(T), hipMemcpyDeviceToDevice, st));
+    TAPG_HIP(hipMemcpyAsync(sl.d_x, sl.d_xa, (size_t)K * LDX * sizeof(T), hipMemcpyDeviceToDevice, st));
+  }
   // cost and violations of the final primal iterate
   launch_cost<T>(K, h.nx, h.nu, h.nd, h.ns, LDX, LDU, (const int*)sl.d_anc,
                  (const double*)sl.d_prob64, (const double*)sl.d_demand,
@@ -829,9 +887,19 @@ void solve_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, const double* p,
   res.viol_eq = red[2];
   res.gamma = gamma;
   res.solve_ms = ms;
+  // the gap is of the dual the solve returns: the one the gap test saw when it
+  // stopped the solve, else (a gap test that did not stop it) re-evaluated
   sl.has_dual = true;
   sl.last_iter_parity = hc.iter & 1;
+  if (S->cfg.gap_tol > 0.0 && !gap_valid && !hc.numeric) {
+    gap_impl_at<T>(S, t, sl, gamma, &gap, &dual_obj);
+    gap_valid = true;
+  }
+  res.dual_gap = gap_valid ? gap : NAN;
+  res.dual_obj = gap_valid ? dual_obj : NAN;
+  sl.numeric = hc.numeric != 0;
   sl.last = res;
+  sl.gap_valid = gap_valid;
   sl.has_result = true;
   if (hc.numeric) throw Fail{TAPG_ENUMERIC, "non-finite dual residual (diverging iterates; infeasible data or step size too large)"};
 }
@@ -870,11 +938,144 @@ double power_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
   return hc.L;
 }
 
+// Duality gap of the tree's current dual (the iterate its last solve returned),
+// FP64 whatever the sweep precision: the dual widened to FP64, one
+// dual-gradient evaluation at w = y on the per-stage kernels (FP64 factors and
+// data step), then the per-node gap terms.  out[0..3]: f(x'), <y, H x'>,
+// g*(y), g(t) (see gap_kernels.hip).
+template <typename T>
+void gap_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, double gamma, double* out) {
+  const NetworkHost& h = S->net;
+  hipStream_t st = S->stream;
+  const int K = t.K, N = t.N, LDX = S->LDX, LDU = S->LDU, LDY = S->LDY;
+  if (sl.last_pq.size() != (size_t)(LDX + LDU)) throw Fail{TAPG_ESTATE, "no solve of this tree yet"};
+  struct Tmp {
+    std::vector<void*> p;
+    ~Tmp() {  // back to the block cache (the stream has been synchronised)
+      for (void* q : p) block_cache().put(q);
+    }
+    double* get(size_t n) {
+      void* q = dev_alloc(std::max<size_t>(n, 1) * sizeof(double));
+      p.push_back(q);
+      return static_cast<double*>(q);
+    }
+  } tmp;
+  const T* ycur = static_cast<const T*>(sl.last_iter_parity ? sl.d_Y1 : sl.d_Y0);
+  const double* y64;
+  if (sizeof(T) == sizeof(double)) {
+    y64 = reinterpret_cast<const double*>(ycur);
+  } else {
+    double* w = tmp.get((size_t)K * LDY);
+    launch_widen<T>(ycur, w, (size_t)K * LDY, st);
+    y64 = w;
+  }
+  double* lam = tmp.get((size_t)K * LDX);
+  double* jv = tmp.get((size_t)K * LDU);
+  double* u = tmp.get((size_t)K * LDU);
+  double* x = tmp.get((size_t)K * LDX);
+  double* kap = tmp.get((size_t)K * LDU);
+  double* g = tmp.get((size_t)K * LDX);
+  double* invp = tmp.get(K);
+  double* pq = tmp.get(LDX + LDU);
+  double* part = tmp.get((size_t)K * 4);
+  double* red = tmp.get(4);
+  DevCtl* ctl = reinterpret_cast<DevCtl*>(tmp.get((sizeof(DevCtl) + 7) / 8));
+  std::vector<double> ip(K);
+  for (int n = 0; n < K; ++n) ip[n] = 1.0 / t.prob[n];
+  TAPG_HIP(hipMemcpyAsync(invp, ip.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemcpyAsync(pq, sl.last_pq.data(), sl.last_pq.size() * 8, hipMemcpyHostToDevice, st));
+  DevCtl c{};
+  c.gamma = gamma;
+  c.max_iter = 1;
+  c.theta = c.theta_prev = 1.0;
+  TAPG_HIP(hipMemcpyAsync(ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipMemsetAsync(lam, 0, (size_t)K * LDX * 8, st));
+  TAPG_HIP(hipMemsetAsync(jv, 0, (size_t)K * LDU * 8, st));
+  launch_data_step<double>(K, h.nx, h.nu, h.nd, LDX, LDU, (const int*)sl.d_stage,
+                           (const double*)sl.d_prob64, (const double*)sl.d_demand,
+                           (const double*)sl.d_price, (const double*)S->dx.Pd,
+                           (const double*)S->dx.Gd, (const double*)S->dx.Gbar,
+                           (const double*)S->d64.F, (const double*)S->dx.alpha0,
+                           (const double*)S->dx.cE, S->cfg.W_alpha, kap, g, h.ns,
+                           (const double*)S->dx.Gm, (const double*)S->dx.E, nullptr, st);
+  const NetDev<double>& d = S->d64;
+  SweepArgs<double> a{};
+  a.nx = h.nx;
+  a.nu = h.nu;
+  a.LDX = LDX;
+  a.LDU = LDU;
+  a.LDY = LDY;
+  a.mode = 2;
+  a.anc = sl.d_anc;
+  a.cbeg = sl.d_cbeg;
+  a.cend = sl.d_cend;
+  a.invp = invp;
+  a.At = d.At;
+  a.Bt = d.Bt;
+  a.A = d.A;
+  a.B = d.B;
+  a.xmin = d.xmin;
+  a.xmax = d.xmax;
+  a.xs = d.xs;
+  a.umin = d.umin;
+  a.umax = d.umax;
+  a.Wx = S->cfg.W_x;
+  a.Ws = S->cfg.W_s;
+  a.kappa = kap;
+  a.g = g;
+  a.pq = pq;
+  a.Y0 = const_cast<double*>(y64);  // read only in evaluation mode; w = y (beta = 0)
+  a.Y1 = const_cast<double*>(y64);
+  a.lam = lam;
+  a.jv = jv;
+  a.u = u;
+  a.x = x;
+  a.ctl = ctl;
+  a.part = part;
+  const size_t fstride = (size_t)LDU * LDU;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = 0; q < N; ++q) {
+      const int s = pass == 0 ? N - 1 - q : q;
+      const int width = t.offset[s + 1] - t.offset[s];
+      const int nb = pick_nb(width, sizeof(double), LDX, LDU, LDY);
+      a.s = s;
+      a.node0 = t.offset[s];
+      a.count = width;
+      a.tile_base = 0;
+      a.F = d.F + s * fstride;
+      a.Kb = d.Kb + s * fstride;
+      if (pass == 0)
+        launch_bwd_stage<double>(nb, a, (width + nb - 1) / nb, st);
+      else
+        launch_fwd_stage<double>(nb, a, (width + nb - 1) / nb, st);
+    }
+  }
+  launch_gap_terms(K, h.nx, h.nu, LDX, LDU, LDY, sl.d_anc, (const double*)sl.d_prob64,
+                   (const double*)sl.d_price, y64, u, x, pq, (const double*)S->dx.Wu,
+                   (const double*)S->dx.alpha0, (const double*)S->dx.cE, d.xmin, d.xmax, d.xs,
+                   d.umin, d.umax, S->cfg.W_alpha, S->cfg.W_x, S->cfg.W_s, gamma, part, red, st);
+  TAPG_HIP(hipGetLastError());
+  TAPG_HIP(hipMemcpyAsync(out, red, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  TAPG_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Exported device-layer entry points
 // ---------------------------------------------------------------------------
+void dev_gap(tapg_solver_s* S, const TreeHost& t, Slot& sl, double* gap, double* dual_obj) {
+  TAPG_HIP(hipSetDevice(S->device));
+  if (!sl.has_dual) throw Fail{TAPG_ESTATE, "no dual for this tree yet"};
+  if (S->fp32)
+    gap_impl_at<float>(S, t, sl, sl.last.gamma, gap, dual_obj);
+  else
+    gap_impl_at<double>(S, t, sl, sl.last.gamma, gap, dual_obj);
+  sl.last.dual_gap = *gap;
+  sl.last.dual_obj = *dual_obj;
+  sl.gap_valid = true;
+}
+
 void dev_init(tapg_solver_s* S) {
   TAPG_HIP(hipSetDevice(S->device));
   {
@@ -972,6 +1173,7 @@ void dev_free_slot(Slot& sl) {
   dfree(sl.d_kappa); dfree(sl.d_g); dfree(sl.d_pq); dfree(sl.d_pq64);
   dfree(sl.d_P0); dfree(sl.d_P1);
   dfree(sl.d_Y0); dfree(sl.d_Y1); dfree(sl.d_lam); dfree(sl.d_j); dfree(sl.d_u); dfree(sl.d_x);
+  dfree(sl.d_ua); dfree(sl.d_xa);
   dfree(sl.d_kperp); dfree(sl.d_zb); dfree(sl.d_zr);
   dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part);
   free_chain(sl);
@@ -1498,6 +1700,7 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
     c[k].gamma = gam[k];
     c[k].theta = 1.0;
     c[k].theta_prev = 1.0;
+    c[k].rule = S->cfg.beta_rule;
     c[k].beta = 0.0;
   }
   upload_pq<T>(S, sl, pq64, st);
@@ -1591,6 +1794,7 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
   TAPG_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
   for (int k = 0; k < nt; ++k) {
     tapg_result r{};
+    r.dual_gap = r.dual_obj = NAN;  // evaluated on request (tapg_residuals)
     r.iters = c[k].iter;
     r.converged = c[k].converged;
     r.primal_res = c[k].last_res;
@@ -1606,6 +1810,8 @@ void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
     o.last = r;
     o.has_result = true;
     o.numeric = c[k].numeric != 0;
+    o.last_pq.assign(pq64.begin() + (size_t)k * PQ, pq64.begin() + (size_t)(k + 1) * PQ);
+    o.gap_valid = false;
   }
 }
 }  // namespace
@@ -1647,12 +1853,17 @@ void live_init_impl(tapg_solver_s* S, LiveTree& j) {
     TAPG_HIP(hipMemsetAsync(o.d_Y1, 0, yb, st));
   }
   o.last_iter_parity = 0;
+  o.last_pq.assign((size_t)S->LDX + S->LDU, 0.0);
+  for (int i = 0; i < S->net.nx; ++i) o.last_pq[i] = j.p[i];
+  for (int i = 0; i < S->net.nu; ++i) o.last_pq[S->LDX + i] = j.q[i];
+  o.gap_valid = false;
   j.ctl = DevCtl{};
   j.ctl.max_iter = S->cfg.max_iter;
   j.ctl.tol = S->cfg.tol;
   j.ctl.gamma = j.gamma;
   j.ctl.theta = 1.0;
   j.ctl.theta_prev = 1.0;
+  j.ctl.rule = S->cfg.beta_rule;
   j.ctl.beta = 0.0;
   j.it0 = 0;
   j.finished = false;
@@ -1775,6 +1986,7 @@ void live_leave_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
     j.res.viol_box = red[3 * k + 1];
     j.res.viol_eq = red[3 * k + 2];
     j.res.gamma = j.gamma;
+    j.res.dual_gap = j.res.dual_obj = NAN;  // evaluated on request (tapg_residuals)
     o.has_dual = true;
     o.last = j.res;
     o.has_result = true;
@@ -1829,6 +2041,7 @@ double time_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
     c[k].tol = 0.0;
     c[k].gamma = 1e-9;
     c[k].theta = c[k].theta_prev = 1.0;
+    c[k].rule = S->cfg.beta_rule;
   }
   std::vector<double> pq64((size_t)nt * PQ, 0.0);
   upload_pq<T>(S, sl, pq64, st);
@@ -2004,6 +2217,7 @@ void set_dual_impl(tapg_solver_s* S, Slot& sl, const double* y) {
   TAPG_HIP(hipStreamSynchronize(S->stream));
   sl.has_dual = true;
   sl.last_iter_parity = 0;
+  sl.gap_valid = false;
 }
 }  // namespace
 

@@ -195,7 +195,8 @@ __global__ __launch_bounds__(kThreads) void bwd_stage_kernel(SweepArgs<T> a) {
 //                (C = [xmin, xmax], W = W_x; C = [xs, inf), W = W_s)
 //   block 3:     y+ = v - gamma P_U(v / gamma)
 // and the residual max |y+ - w| / gamma in FP64.  In power-iteration mode the
-// block writes z = -(x_n, x_n, u_n) and the tile's |z|^2 instead.
+// block writes z = -(x_n, x_n, u_n) and the tile's |z|^2 instead; in
+// evaluation mode (2) it stops after u_n and x_n.
 // ---------------------------------------------------------------------------
 template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
@@ -273,6 +274,7 @@ __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
     }
   }
   __syncthreads();
+  if (a.mode == 2) return;  // evaluation of x_hat(w) only: no dual update
 
   // ---- prox / dual update, one group of TPN threads per node ----
   constexpr int TPN = kThreads / NB;
@@ -642,6 +644,27 @@ __global__ __launch_bounds__(kThreads) void copy_rows_kernel(const T* src, int l
   for (int i = threadIdx.x; i < width; i += kThreads) dst[rd * ld_dst + i] = src[rs * ld_src + i];
 }
 
+// Averaged primal iterate (Sec. 4.3; the averaged sequence of accelerated
+// dual gradient projection): ua = (1 - theta_nu) ua + theta_nu u_hat(w^nu), the
+// same for x, with theta_nu of the iteration that just wrote u and x
+// (theta_0 = 1 starts the average at the first iterate).  A stopped tree's
+// average is left alone.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void avg_kernel(const DevCtl* ctl, const T* u, const T* x,
+                                                       T* ua, T* xa, size_t nu_el, size_t nx_el) {
+  if (ctl->done) return;
+  const double th = ctl->theta;
+  const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const T* src = i < nu_el ? u : x;
+  T* dst = i < nu_el ? ua : xa;
+  const size_t k = i < nu_el ? i : i - nu_el;
+  if (i >= nu_el + nx_el) return;
+  if (th >= 1.0)
+    dst[k] = src[k];
+  else
+    dst[k] = (T)((1.0 - th) * (double)dst[k] + th * (double)src[k]);
+}
+
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
@@ -678,6 +701,15 @@ void launch_fwd_stage(int nb, const SweepArgs<T>& a, int tiles, hipStream_t st) 
   }
 }
 
+
+template <typename T>
+void launch_avg(const DevCtl* ctl, const T* u, const T* x, T* ua, T* xa, size_t nu_el,
+                size_t nx_el, hipStream_t st) {
+  const size_t n = nu_el + nx_el;
+  if (n == 0) return;
+  hipLaunchKernelGGL((avg_kernel<T>), dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, st, ctl, u, x, ua, xa, nu_el, nx_el);
+}
 
 void launch_iter_end(DevCtl* c, double* hist, int ntrees, int hist_stride, hipStream_t st) {
   launch_iter_end_from(c, c, hist, ntrees, hist_stride, st);
@@ -746,6 +778,8 @@ template void launch_copy_rows<float>(const float*, int, float*, int, const int*
 
 #define TAPG_INST(T)                                                                         \
   template void launch_bwd_stage<T>(int, const SweepArgs<T>&, int, hipStream_t);            \
+  template void launch_avg<T>(const DevCtl*, const T*, const T*, T*, T*, size_t, size_t,    \
+                              hipStream_t);                                                 \
   template void launch_fwd_stage<T>(int, const SweepArgs<T>&, int, hipStream_t);            \
   template void launch_data_step<T>(int, int, int, int, int, int, const int*, const double*, \
                                     const double*, const double*, const double*,             \

@@ -31,6 +31,9 @@ TAPG_ESTATE = -5
 TAPG_ENUMERIC = -6
 TAPG_FP64 = 0
 TAPG_FP32 = 1
+TAPG_BETA_PAPER = 0
+TAPG_BETA_SIMPLE = 1
+TAPG_BETA_ZERO = 2
 
 EXPORTED = [
     "tapg_network_create", "tapg_network_destroy", "tapg_tree_create", "tapg_tree_set_data",
@@ -67,6 +70,9 @@ class TapgConfig(ctypes.Structure):
         ("power_iters", ctypes.c_int),
         ("device", ctypes.c_int),
         ("hip_stream", ctypes.c_void_p),
+        ("beta_rule", ctypes.c_int),
+        ("averaged_primal", ctypes.c_int),
+        ("gap_tol", ctypes.c_double),
     ]
 
 
@@ -80,6 +86,8 @@ class TapgResult(ctypes.Structure):
         ("viol_eq", ctypes.c_double),
         ("gamma", ctypes.c_double),
         ("solve_ms", ctypes.c_double),
+        ("dual_gap", ctypes.c_double),
+        ("dual_obj", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -237,12 +245,14 @@ def tapg_tree_destroy(h):
 
 def make_config(nu, W_alpha, W_s, W_x, alpha0, c_energy, W_u, gamma=0.0, tol=1e-4,
                 max_iter=10000, check_every=100, precision=TAPG_FP64, power_iters=100,
-                device=0, stream=None):
+                device=0, stream=None, beta_rule=TAPG_BETA_PAPER, averaged_primal=False,
+                gap_tol=0.0):
     """A :class:`TapgConfig` plus the arrays it points to (keep both alive)."""
     keep = [_f64(alpha0, nu), _f64(c_energy, nu), _f64(W_u, nu * nu)]
     cfg = TapgConfig(W_alpha, W_s, W_x, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), gamma, tol,
                      max_iter, check_every, precision, power_iters, device,
-                     ctypes.c_void_p(stream) if stream else None)
+                     ctypes.c_void_p(stream) if stream else None, int(beta_rule),
+                     int(bool(averaged_primal)), float(gap_tol))
     return cfg, keep
 
 

@@ -463,6 +463,7 @@ def test_diverging_step_size_is_enumeric():
         assert e.value.status == tapg.TAPG_ENUMERIC
         r = tapg.tapg_residuals(S.h, t)
         assert r.iters <= bad[0] + 2 and not r.converged
+        assert np.isnan(r.dual_gap)  # a diverged dual has no gap
     with make_solver(P, gamma=1.0 / L, tol=1e-6, max_iter=20000, check_every=50) as S:
         t = add_tree(S, P)
         st, u0, res = S.solve(t, P.p, P.q)

@@ -448,3 +448,155 @@ def test_variable_counts_match_paper():
     m = O.apg.__globals__["hx_blocks"](np.zeros((K, nu)), np.zeros((K, nx))).size
     assert m == g["dual_variables"]
     assert K * (nx + nu) == g["primal_variables"]
+
+
+# ---------------------------------------------------------------------------
+# Variants of the iteration (Sec. 4.3): theta rules, averaged primal
+# ---------------------------------------------------------------------------
+def test_simple_theta_rule_closed_form():
+    """theta_nu = 2/(nu+2) (nu >= 1, theta_0 = theta_{-1} = 1) gives
+    beta_0 = beta_1 = 0 and beta_nu = (nu-1)/(nu+2), and meets the paper's
+    condition 1 - theta_{nu+1} <= theta_{nu+1}^2 / theta_nu^2."""
+    b = O.beta_sequence(80, "simple")
+    expect = [0.0, 0.0] + [(n - 1) / (n + 2) for n in range(2, 80)]
+    assert np.allclose(b, expect, rtol=0, atol=1e-15)
+    for n in range(1, 200):
+        th, thn = 2.0 / (n + 2), 2.0 / (n + 3)
+        assert 1 - thn <= thn ** 2 / th ** 2 + 1e-15
+    assert np.all(O.beta_sequence(30, "zero") == 0.0)
+
+
+@pytest.mark.parametrize("rule", ["zero", "paper", "simple"])
+def test_averaged_primal_closed_forms(rule):
+    """The averaged primal against sums of the iterates written out: for
+    beta = 0 (theta_nu = 1/(nu+1)) the arithmetic mean of x_hat(w^0..w^nu);
+    for the paper's recursion, which meets 1 - theta_{j} = theta_j^2/theta_{j-1}^2
+    with equality, xbar^nu = theta_nu^2 sum_i x_hat(w^i)/theta_i; for
+    theta = 2/(nu+2), with weights prod_{j>i} (1 - theta_j) theta_i written
+    out term by term.  The average satisfies the dynamics and the mass balance
+    like every iterate (an affine combination)."""
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    us, xs = [], []
+
+    def cb(nu, y_new, w, u, x):
+        us.append(u.copy())
+        xs.append(x.copy())
+
+    n = 60
+    r = O.apg(P, gamma, nf, n, beta_rule=rule, callback=cb, average=True)
+    U, X = np.asarray(us), np.asarray(xs)
+    if rule == "zero":
+        wts = np.full(n, 1.0 / n)
+    elif rule == "paper":
+        th = [1.0]
+        for _ in range(n - 1):
+            th.append(O.theta_next(th[-1]))
+        th = np.asarray(th)
+        wts = th[-1] ** 2 / th
+    else:
+        th = np.asarray([1.0] + [2.0 / (k + 2) for k in range(1, n)])
+        wts = np.asarray([th[i] * np.prod(1.0 - th[i + 1:]) for i in range(n)])
+    assert abs(wts.sum() - 1.0) <= 1e-12
+    ua = np.tensordot(wts, U, axes=1)
+    xa = np.tensordot(wts, X, axes=1)
+    assert np.abs(r.u_avg - ua).max() <= 1e-11 * max(1.0, np.abs(ua).max())
+    assert np.abs(r.x_avg - xa).max() <= 1e-11 * max(1.0, np.abs(xa).max())
+    vb, ve = O.violations(P, r.u_avg, r.x_avg)
+    assert ve <= 1e-12
+
+
+def test_averaged_primal_converges_to_slsqp_optimum():
+    """The averaged primal of the accelerated iteration approaches the
+    optimum of an independent SLSQP solve (tiny tree with active soft
+    penalties) at the O(1/nu^2) rate the paper quotes: its cost error and
+    input-box violation shrink about 100-fold per tenfold iterations."""
+    P = tiny_problem(N=3, b1=2, S=2, seed=12, p_level=2.3, price_scale=1000.0)
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    res, u_s, x_s = _slsqp_solve(P)
+    J_s = res.fun
+    errs, vbs = [], []
+    for n in (200, 2000, 20000):
+        r = O.apg(P, gamma, nf, n, average=True)
+        errs.append(abs(O.primal_cost(P, r.u_avg, r.x_avg) - J_s) / max(1.0, abs(J_s)))
+        vbs.append(O.violations(P, r.u_avg, r.x_avg)[0])
+    assert errs[1] / errs[2] >= 30 and vbs[1] / vbs[2] >= 30
+    assert errs[0] / errs[1] >= 30 and vbs[0] / vbs[1] >= 30
+    assert errs[2] <= 2e-4 and vbs[2] <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Duality gap of a dual point (Sec. 4.2)
+# ---------------------------------------------------------------------------
+def _random_dual_in_domain(P, rng, scale):
+    """A dual point inside dom g*: |y1_n| <= W_x, |y2_n| <= W_s, y2_n <= 0."""
+    nx, nu = P.net.nx, P.net.nu
+    K = P.tree.K
+    y1 = rng.standard_normal((K, nx))
+    y1 *= np.minimum(1.0, 0.9 * P.weights.W_x / np.linalg.norm(y1, axis=1))[:, None]
+    y2 = -np.abs(rng.standard_normal((K, nx)))
+    y2 *= np.minimum(1.0, 0.9 * P.weights.W_s / np.linalg.norm(y2, axis=1))[:, None]
+    y3 = scale * rng.standard_normal((K, nu))
+    return np.concatenate([y1, y2, y3], axis=1)
+
+
+def test_gap_lower_bound_at_random_duals():
+    """Weak duality with Fenchel-Young: G(y) >= <y, t - H x_hat(y)> at any
+    dual point (here random points of dom g*), the gap is finite there, and
+    it is the primal value of (x', t) less the dual value -F(y)."""
+    P = tiny_problem(N=4, b1=2, S=3, seed=3)
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        y = _random_dual_in_domain(P, rng, scale=rng.uniform(0.01, 10.0))
+        G, F = O.split_gap(P, y, gamma, nf)
+        u, x = O.dual_gradient(P, y, nf)
+        hx = hx_blocks(u, x)
+        _, t = O.prox_gconj(y + gamma * hx, gamma, P.net, P.weights)
+        bound = float(np.sum(y * (t - hx)))
+        assert np.isfinite(G) and np.isfinite(F)
+        assert G >= bound - 1e-9 * max(1.0, abs(F))
+
+
+def test_gap_zero_at_the_interior_optimum():
+    """Interior data (the optimum has y* = 0): the gap of y = 0 is zero."""
+    P = tiny_problem(N=4, b1=2, S=4, seed=9)
+    d0 = P.data.demand[0]
+    P.data.demand[:] = d0
+    P.data.price[:] = 0.0
+    P.weights.alpha0[:] = 0.0
+    from dwn_synth.generate import steady_input
+    P.q = steady_input(P.net, d0) + 0.3 * np.array([k == "src_tank" for k in P.net.kind])
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    G, F = O.split_gap(P, np.zeros((P.tree.K, _m(P))), 1e-2, sf)
+    J = O.primal_cost(P, *O.dual_gradient_kkt(P, np.zeros((P.tree.K, _m(P)))))
+    assert abs(G) <= 1e-10 * max(1.0, abs(J))
+    assert abs(F + J) <= 1e-10 * max(1.0, abs(J))
+
+
+@pytest.mark.parametrize("seed,p_level,price_scale", [(7, 5.0, 1.0), (12, 2.3, 1000.0)])
+def test_gap_vanishes_at_the_slsqp_optimum(seed, p_level, price_scale):
+    """At the converged dual the gap is zero and F(y*) = -J* with J* from an
+    independent SLSQP solve (strong duality, Sec. 4.2); the second case has
+    the soft penalties and the safety-level term of g* active.  (The gap uses
+    the split variable t, not H x', so it is a certificate only together with
+    the residual |H x' - t|; both vanish at the optimum.)"""
+    P = tiny_problem(N=3, b1=2, S=2, seed=seed, p_level=p_level, price_scale=price_scale)
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    r = O.apg(P, gamma, nf, 200000, tol=1e-11)
+    assert r.converged
+    res, u_s, x_s = _slsqp_solve(P)
+    J_s = res.fun
+    G, F = O.split_gap(P, r.y, gamma, nf)
+    G50, _ = O.split_gap(P, O.apg(P, gamma, nf, 50).y, gamma, nf)
+    scale = max(1.0, abs(J_s))
+    assert abs(G) <= 1e-7 * scale
+    assert abs(F + J_s) <= 1e-6 * scale
+    assert abs(G50) > 1e3 * abs(G)  # away from the optimum the gap is not small
+    if price_scale > 1:
+        nx = P.net.nx
+        assert np.abs(r.y[:, nx:2 * nx]).max() > 1e-3  # safety-level duals active
