@@ -174,6 +174,28 @@ tapg_status tapg_factor_blocks(tapg_solver solver, int* fid, int n, int* n_block
 tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, const double* q,
                        int warm_start, double* u0_out, tapg_result* res);
 
+/* For callers that cannot allocate device memory (code running under HIP
+ * graph capture is not one of them: the call waits for the device; but tight
+ * control loops and harnesses that forbid hipMalloc are): tapg_solve without
+ * any device allocation.  Every buffer of the solve lives in one static device
+ * array of TAPG_NOALLOC_SCRATCH_BYTES per GPU, held by the library until the
+ * process ends (its address is looked up at solver creation); a tree whose
+ * buffers do not fit returns TAPG_ENOMEM (tapg_noalloc_bytes gives the need).
+ * Cold start (y = 0), the per-stage sweep kernels, the solver's stream; the
+ * same iteration as tapg_solve up to rounding.  The step size is cfg.gamma, or
+ * 1/(1.02 L) with the tree's estimate from an earlier tapg_estimate_lipschitz
+ * or tapg_solve (else TAPG_EINVAL: the power iteration allocates).
+ * u0_out [nu], u_out [K*nu], x_out [K*nx] and res may each be NULL.  Calls on
+ * one device share its array: the library serialises them, and each call
+ * overwrites what the previous one left.  No averaged primal or gap test
+ * (TAPG_EINVAL).  Returns TAPG_OK, TAPG_ENOTCONV or an error. */
+#define TAPG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tapg_status tapg_solve_noalloc(tapg_solver solver, tapg_tree tree, const double* p,
+                               const double* q, double* u0_out, double* u_out, double* x_out,
+                               tapg_result* res);
+/* Scratch bytes tapg_solve_noalloc needs for this tree (host only). */
+tapg_status tapg_noalloc_bytes(tapg_solver solver, tapg_tree tree, size_t* bytes);
+
 /* Solve several trees in one set of launches (the paper's method on each tree;
  * Sec. 4.3 iteration, Sec. 4.4 sweeps): the trees, which must share the
  * factored horizon and appear once each, are swept together as one forest, each

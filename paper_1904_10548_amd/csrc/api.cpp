@@ -460,6 +460,43 @@ tapg_status tapg_solve(tapg_solver solver, tapg_tree tree, const double* p, cons
   });
 }
 
+tapg_status tapg_solve_noalloc(tapg_solver solver, tapg_tree tree, const double* p,
+                               const double* q, double* u0_out, double* u_out, double* x_out,
+                               tapg_result* res) {
+  return guarded([&]() -> tapg_status {
+    check_pair(solver, tree);
+    need(p, "p");
+    need(q, "q");
+    if (!finite_all(p, solver->net.nx) || !finite_all(q, solver->net.nu))
+      fail(TAPG_ENUMERIC, "non-finite p or q");
+    if (solver->cfg.averaged_primal || solver->cfg.gap_tol > 0)
+      fail(TAPG_EINVAL, "tapg_solve_noalloc: no averaged primal or gap test (they need buffers "
+                        "of their own)");
+    const TreeHost& t = tree->h;
+    double gamma = solver->cfg.gamma;
+    if (!(gamma > 0)) {  // the tree's estimate, if one was made (the power iteration allocates)
+      auto it = solver->slots.find(t.uid);
+      if (it == solver->slots.end() || !it->second.L_valid)
+        fail(TAPG_EINVAL, "tapg_solve_noalloc: cfg.gamma <= 0 and no Lipschitz estimate for "
+                          "this tree (call tapg_estimate_lipschitz or tapg_solve first)");
+      gamma = 1.0 / (1.02 * it->second.L);
+    }
+    tapg_result r{};
+    dev_solve_noalloc(solver, t, p, q, gamma, r, u0_out, u_out, x_out);
+    if (res) *res = r;
+    return r.converged || solver->cfg.tol <= 0 ? TAPG_OK : TAPG_ENOTCONV;
+  });
+}
+
+tapg_status tapg_noalloc_bytes(tapg_solver solver, tapg_tree tree, size_t* bytes) {
+  return guarded([&]() -> tapg_status {
+    need(bytes, "bytes");
+    check_pair_unserved(solver, tree);
+    *bytes = dev_noalloc_bytes(solver, tree->h);
+    return TAPG_OK;
+  });
+}
+
 }  // extern "C"
 
 namespace tapg {

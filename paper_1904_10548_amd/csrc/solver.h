@@ -166,6 +166,11 @@ void dev_batch_solve(tapg_solver_s* S, const std::vector<const TreeHost*>& trees
                      const double* const* q, const int* warm, const std::vector<double>& gamma,
                      tapg_result* res);
 double dev_power(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters);
+// Solve in the scratch array (no device allocation); per-stage kernels.
+void dev_solve_noalloc(tapg_solver_s* S, const TreeHost& t, const double* p, const double* q,
+                       double gamma, tapg_result& res, double* u0, double* u_out, double* x_out);
+// Scratch bytes such a solve of the tree needs.
+size_t dev_noalloc_bytes(const tapg_solver_s* S, const TreeHost& t);
 // Duality gap G and dual objective F of the tree's current dual (FP64).
 void dev_gap(tapg_solver_s* S, const TreeHost& t, Slot& sl, double* gap, double* dual_obj);
 void dev_get_primal(tapg_solver_s* S, Slot& sl, double* u, double* x);

@@ -1059,11 +1059,240 @@ void gap_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, double gamma, doubl
   TAPG_HIP(hipStreamSynchronize(st));
 }
 
+// ---------------------------------------------------------------------------
+// Solve without allocating (tapg_solve_noalloc): every buffer of the solve
+// lives in one file-scope device array, `scratch`, of TAPG_NOALLOC_SCRATCH_BYTES.
+// Host code never uses the array's name as an address: its device address is
+// looked up once per device at solver creation (hipGetSymbolAddress, with the
+// device current) and kept in g_scratch[device].  Each GPU holds its own copy
+// until the process ends; calls on one device are serialised by g_scratch_mu,
+// and each call overwrites what the previous one left.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TAPG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+__global__ __launch_bounds__(kThreads) void fill_zero_kernel(unsigned* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * kThreads)
+    p[i] = 0u;
+}
+
+// Byte offsets of one solve's buffers inside the scratch array.
+struct NoallocLayout {
+  size_t anc, cbeg, cend, stage, prob, demand, price, pq64, part, red, hist, ctl;
+  size_t invp, kappa, g, pq, y0, y1, lam, jv, u, x;
+  size_t total;
+};
+
+NoallocLayout noalloc_layout(const tapg_solver_s* S, const TreeHost& t, size_t e) {
+  NoallocLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t K = t.K, LDX = S->LDX, LDU = S->LDU, LDY = S->LDY;
+  L.anc = take(K * 4);
+  L.cbeg = take(K * 4);
+  L.cend = take(K * 4);
+  L.stage = take(K * 4);
+  L.prob = take(K * 8);
+  L.demand = take(K * t.nd * 8);
+  L.price = take(K * 8);
+  L.pq64 = take((LDX + LDU) * 8);
+  L.part = take(4 * K * 8);
+  L.red = take(8 * 8);
+  L.hist = take((size_t)std::max(1, S->cfg.max_iter) * 8);
+  L.ctl = take(2 * sizeof(DevCtl));
+  L.invp = take(K * e);
+  L.kappa = take(K * LDU * e);
+  L.g = take(K * LDX * e);
+  L.pq = take((LDX + LDU) * e);
+  L.y0 = take(K * LDY * e);
+  L.y1 = take(K * LDY * e);
+  L.lam = take(K * LDX * e);
+  L.jv = take(K * LDU * e);
+  L.u = take(K * LDU * e);
+  L.x = take(K * LDX * e);
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+void noalloc_impl(tapg_solver_s* S, const TreeHost& t, unsigned char* base, const double* p,
+                  const double* q, double gamma, tapg_result& res, double* u0, double* u_out,
+                  double* x_out) {
+  const NetworkHost& h = S->net;
+  hipStream_t st = S->stream;
+  const int K = t.K, LDX = S->LDX, LDU = S->LDU, LDY = S->LDY;
+  const NoallocLayout L = noalloc_layout(S, t, sizeof(T));
+  // a local slot whose buffers are views into the scratch array (never freed)
+  Slot sl;
+  sl.K = K;
+  sl.N = t.N;
+  sl.elem = sizeof(T);
+  sl.d_anc = reinterpret_cast<int*>(base + L.anc);
+  sl.d_cbeg = reinterpret_cast<int*>(base + L.cbeg);
+  sl.d_cend = reinterpret_cast<int*>(base + L.cend);
+  sl.d_stage = reinterpret_cast<int*>(base + L.stage);
+  sl.d_prob64 = reinterpret_cast<double*>(base + L.prob);
+  sl.d_demand = reinterpret_cast<double*>(base + L.demand);
+  sl.d_price = reinterpret_cast<double*>(base + L.price);
+  sl.d_pq64 = reinterpret_cast<double*>(base + L.pq64);
+  sl.d_part = reinterpret_cast<double*>(base + L.part);
+  sl.d_hist = reinterpret_cast<double*>(base + L.hist);
+  sl.hist_cap = std::max(1, S->cfg.max_iter);
+  sl.d_ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
+  sl.d_invp = base + L.invp;
+  sl.d_kappa = base + L.kappa;
+  sl.d_g = base + L.g;
+  sl.d_pq = base + L.pq;
+  sl.d_Y0 = base + L.y0;
+  sl.d_Y1 = base + L.y1;
+  sl.d_lam = base + L.lam;
+  sl.d_j = base + L.jv;
+  sl.d_u = base + L.u;
+  sl.d_x = base + L.x;
+  double* red = reinterpret_cast<double*>(base + L.red);
+  // per-stage kernels (no schedule tables): tiles as a solver slot would hold them
+  sl.segmented = false;
+  sl.node_offset = t.offset;
+  sl.nb_of_stage.resize(t.N);
+  sl.tiles_of_stage.resize(t.N);
+  sl.tile_offset.resize(t.N + 1);
+  int tot = 0;
+  for (int s = 0; s < t.N; ++s) {
+    const int nb = pick_nb(t.mu[s], sizeof(T), LDX, LDU, LDY);
+    sl.nb_of_stage[s] = nb;
+    sl.tiles_of_stage[s] = (t.mu[s] + nb - 1) / nb;
+    sl.tile_offset[s] = tot;
+    tot += sl.tiles_of_stage[s];
+  }
+  sl.tile_offset[t.N] = tot;
+  sl.total_tiles = tot;
+  // tree, data and initial state in (the host arrays stay alive until the sync below)
+  std::vector<T> ip(K);
+  for (int n = 0; n < K; ++n) ip[n] = (T)(1.0 / t.prob[n]);
+  std::vector<double> pq64((size_t)LDX + LDU, 0.0);
+  for (int i = 0; i < h.nx; ++i) pq64[i] = p[i];
+  for (int i = 0; i < h.nu; ++i) pq64[LDX + i] = q[i];
+  std::vector<T> pqT(pq64.begin(), pq64.end());
+  DevCtl c{};
+  c.max_iter = S->cfg.max_iter;
+  c.tol = S->cfg.tol;
+  c.rule = S->cfg.beta_rule;
+  c.gamma = gamma;
+  c.theta = c.theta_prev = 1.0;
+  auto h2d = [&](void* dst, const void* src, size_t bytes) {
+    TAPG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  };
+  h2d(sl.d_anc, t.anc.data(), (size_t)K * 4);
+  h2d(sl.d_cbeg, t.cbeg.data(), (size_t)K * 4);
+  h2d(sl.d_cend, t.cend.data(), (size_t)K * 4);
+  h2d(sl.d_stage, t.stage.data(), (size_t)K * 4);
+  h2d(sl.d_prob64, t.prob.data(), (size_t)K * 8);
+  h2d(sl.d_demand, t.demand.data(), (size_t)K * t.nd * 8);
+  h2d(sl.d_price, t.price.data(), (size_t)K * 8);
+  h2d(sl.d_invp, ip.data(), (size_t)K * sizeof(T));
+  h2d(sl.d_pq64, pq64.data(), pq64.size() * 8);
+  h2d(sl.d_pq, pqT.data(), pqT.size() * sizeof(T));
+  h2d(sl.d_ctl, &c, sizeof(c));
+  // cold start: both dual buffers zero (a fill kernel, as the rest of the path)
+  const size_t ywords = (L.y1 - L.y0) / 4 * 2;  // Y0 and Y1 are adjacent
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(kThreads), 0, st,
+                     reinterpret_cast<unsigned*>(base + L.y0), ywords);
+  TAPG_HIP(hipEventRecord(S->ev0, st));
+  data_step<T>(S, sl, K, st);
+  const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
+  const NetDev<T>& d = net_of<T>(S);
+  DevCtl hc{};
+  int launched = 0;
+  while (true) {
+    enqueue_iterations<T>(S, sl, d, chunk);
+    TAPG_HIP(hipGetLastError());
+    launched += chunk;
+    TAPG_HIP(hipMemcpyAsync(&hc, sl.d_ctl, sizeof(hc), hipMemcpyDeviceToHost, st));
+    TAPG_HIP(hipStreamSynchronize(st));
+    if (hc.done || launched >= S->cfg.max_iter) break;
+  }
+  TAPG_HIP(hipEventRecord(S->ev1, st));
+  launch_cost<T>(K, h.nx, h.nu, h.nd, h.ns, LDX, LDU, sl.d_anc, sl.d_prob64, sl.d_demand,
+                 sl.d_price, (const T*)sl.d_u, (const T*)sl.d_x, sl.d_pq64,
+                 (const double*)S->d64.A, (const double*)S->d64.B, (const double*)S->dx.Gd,
+                 (const double*)S->dx.E, (const double*)S->dx.Ed, (const double*)S->dx.Wu,
+                 (const double*)S->dx.alpha0, (const double*)S->dx.cE,
+                 (const double*)S->d64.xmin, (const double*)S->d64.xmax,
+                 (const double*)S->d64.xs, (const double*)S->d64.umin,
+                 (const double*)S->d64.umax, S->cfg.W_alpha, S->cfg.W_x, S->cfg.W_s, sl.d_part,
+                 red, st);
+  TAPG_HIP(hipGetLastError());
+  double r3[3];
+  TAPG_HIP(hipMemcpyAsync(r3, red, sizeof(r3), hipMemcpyDeviceToHost, st));
+  std::vector<T> uh, xh;
+  if (u0 || u_out) {
+    uh.resize((size_t)(u_out ? K : 1) * LDU);
+    TAPG_HIP(hipMemcpyAsync(uh.data(), sl.d_u, uh.size() * sizeof(T), hipMemcpyDeviceToHost, st));
+  }
+  if (x_out) {
+    xh.resize((size_t)K * LDX);
+    TAPG_HIP(hipMemcpyAsync(xh.data(), sl.d_x, xh.size() * sizeof(T), hipMemcpyDeviceToHost, st));
+  }
+  TAPG_HIP(hipStreamSynchronize(st));
+  float ms = 0.f;
+  TAPG_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+  if (u0)
+    for (int i = 0; i < h.nu; ++i) u0[i] = (double)uh[i];
+  if (u_out)
+    for (int n = 0; n < K; ++n)
+      for (int i = 0; i < h.nu; ++i) u_out[(size_t)n * h.nu + i] = (double)uh[(size_t)n * LDU + i];
+  if (x_out)
+    for (int n = 0; n < K; ++n)
+      for (int i = 0; i < h.nx; ++i) x_out[(size_t)n * h.nx + i] = (double)xh[(size_t)n * LDX + i];
+  res = tapg_result{};
+  res.iters = hc.iter;
+  res.converged = hc.converged;
+  res.primal_res = hc.last_res;
+  res.cost = r3[0];
+  res.viol_box = r3[1];
+  res.viol_eq = r3[2];
+  res.gamma = gamma;
+  res.solve_ms = ms;
+  res.dual_gap = res.dual_obj = NAN;
+  if (hc.numeric) throw Fail{TAPG_ENUMERIC, "non-finite dual residual (diverging iterates; infeasible data or step size too large)"};
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Exported device-layer entry points
 // ---------------------------------------------------------------------------
+size_t dev_noalloc_bytes(const tapg_solver_s* S, const TreeHost& t) {
+  return noalloc_layout(S, t, S->fp32 ? sizeof(float) : sizeof(double)).total;
+}
+
+void dev_solve_noalloc(tapg_solver_s* S, const TreeHost& t, const double* p, const double* q,
+                       double gamma, tapg_result& res, double* u0, double* u_out, double* x_out) {
+  if (S->device < 0 || S->device >= kMaxDevices) throw Fail{TAPG_EDEVICE, "device ordinal out of range"};
+  TAPG_HIP(hipSetDevice(S->device));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  unsigned char* base = static_cast<unsigned char*>(g_scratch[S->device]);
+  if (!base) throw Fail{TAPG_ESTATE, "scratch array of this device not set up"};
+  const size_t need = dev_noalloc_bytes(S, t);
+  if (need > (size_t)TAPG_NOALLOC_SCRATCH_BYTES)
+    throw Fail{TAPG_ENOMEM, "tapg_solve_noalloc: the tree needs " + std::to_string(need) +
+                                " bytes of scratch; the library holds " +
+                                std::to_string((size_t)TAPG_NOALLOC_SCRATCH_BYTES) +
+                                " (use tapg_solve)"};
+  if (S->fp32)
+    noalloc_impl<float>(S, t, base, p, q, gamma, res, u0, u_out, x_out);
+  else
+    noalloc_impl<double>(S, t, base, p, q, gamma, res, u0, u_out, x_out);
+}
+
 void dev_gap(tapg_solver_s* S, const TreeHost& t, Slot& sl, double* gap, double* dual_obj) {
   TAPG_HIP(hipSetDevice(S->device));
   if (!sl.has_dual) throw Fail{TAPG_ESTATE, "no dual for this tree yet"};
@@ -1138,6 +1367,17 @@ void dev_init(tapg_solver_s* S) {
   }
   TAPG_HIP(hipEventCreate(&S->ev0));
   TAPG_HIP(hipEventCreate(&S->ev1));
+  {  // device address of this device's scratch array (tapg_solve_noalloc), once
+    if (S->device < 0 || S->device >= kMaxDevices) throw Fail{TAPG_EDEVICE, "device ordinal out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[S->device]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || ptr == nullptr)
+        throw Fail{TAPG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+      g_scratch[S->device] = ptr;
+    }
+  }
   const NetworkHost& h = S->net;
   hipStream_t st = S->stream;
   init_net<double>(S, S->d64);

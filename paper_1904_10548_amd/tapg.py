@@ -42,7 +42,7 @@ EXPORTED = [
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
     "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune", "tapg_sweep_form",
     "tapg_schedule_spec", "tapg_event_pair_overhead",
-    "tapg_solver_forget",
+    "tapg_solver_forget", "tapg_solve_noalloc", "tapg_noalloc_bytes",
     "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats", "tapg_server_timing",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
 ]
@@ -141,6 +141,9 @@ def lib() -> ctypes.CDLL:
         "tapg_server_timing": ([_P, _D, _D, _D], ctypes.c_int),
         "tapg_server_destroy": ([_P], None),
         "tapg_solve": ([_P, _P, _D, _D, ctypes.c_int, _D, ctypes.POINTER(TapgResult)], ctypes.c_int),
+        "tapg_solve_noalloc": ([_P, _P, _D, _D, _D, _D, _D, ctypes.POINTER(TapgResult)],
+                               ctypes.c_int),
+        "tapg_noalloc_bytes": ([_P, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "tapg_batch_solve": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_D),
                               ctypes.POINTER(_D), _I, ctypes.POINTER(_D),
                               ctypes.POINTER(TapgResult)], ctypes.c_int),
@@ -292,6 +295,27 @@ def tapg_solve(solver, tree, p, q, warm_start=False, nu=None):
     st = _check(lib().tapg_solve(solver, tree, _ptr(_f64(p)), _ptr(q), int(bool(warm_start)),
                                  _ptr(u0), ctypes.byref(res)), allow=(TAPG_OK, TAPG_ENOTCONV))
     return st, u0, res
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def tapg_solve_noalloc(solver, tree, p, q, K, nx, nu):
+    """Solve without device allocation; returns ``(status, u0, u, x, result)``."""
+    u0 = np.zeros(nu)
+    u = np.zeros((K, nu))
+    x = np.zeros((K, nx))
+    res = TapgResult()
+    st = _check(lib().tapg_solve_noalloc(solver, tree, _ptr(_f64(p)), _ptr(_f64(q)), _ptr(u0),
+                                         _ptr(u), _ptr(x), ctypes.byref(res)),
+                allow=(TAPG_OK, TAPG_ENOTCONV))
+    return st, u0, u, x, res
+
+
+def tapg_noalloc_bytes(solver, tree) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tapg_noalloc_bytes(solver, tree, ctypes.byref(b)))
+    return b.value
 
 
 def tapg_batch_solve(solver, trees, ps, qs, warm_start=None, nu=None):
