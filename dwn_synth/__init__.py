@@ -31,6 +31,7 @@ from .generate import (
     CONFIGS,
     config_problem,
 )
+from .closed_loop import LoopInputs, make_loop_inputs
 
 __all__ = [
     "Network",
@@ -47,4 +48,6 @@ __all__ = [
     "nodes_per_stage_for",
     "CONFIGS",
     "config_problem",
+    "LoopInputs",
+    "make_loop_inputs",
 ]

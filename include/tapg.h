@@ -356,6 +356,36 @@ tapg_status tapg_sweep_form(tapg_solver solver, int ntrees, const tapg_tree* tre
  * again. */
 tapg_status tapg_solver_forget(tapg_solver solver, tapg_tree tree);
 
+/* Closed-loop receding-horizon simulation (Sec. 6.3, closed-loop
+ * simulations).  At each sampling instant k = 0..H_s-1 the library calls
+ * forecast(ctx, k, demand [K*nd], price [K]) for the tree's data at k (the
+ * root carries the demand and price observed at k, the other nodes the
+ * forecast scenarios; return 0, or nonzero to abort with TAPG_EINVAL), solves
+ * from the plant state x_k and u_{k-1} (tapg_solve; warm started from the
+ * previous dual when warm_start != 0 and k > 0), applies the root input u_k
+ * and moves the plant with the observed demand d_k (the root's):
+ *   x_{k+1} = A x_k + B u_k + Gd d_k.
+ * x0 [nx], u_prev [nu]: initial state and previous input.  Outputs (each may
+ * be NULL): x_traj [(H_s+1)*nx] (x_0..x_{H_s}), u_traj [H_s*nu], tau_ms [H_s]
+ * (host wall time of each solve), iters [H_s], and the indices of Sec. 6.3 in
+ * stats.  A solve that fails (other than TAPG_ENOTCONV) stops the loop with
+ * its status.  The tree's data are left at the last step's. */
+typedef int (*tapg_forecast_fn)(void* ctx, int k, double* demand, double* price);
+typedef struct {
+  double kpi_E;         /* (1/H_s) sum_k (alpha0 + pi_k c_E)'u_k, economic index */
+  double kpi_S;         /* sum_k |max(xs - x_{k+1}, 0)|_1, safety index */
+  double kpi_tau_ms;    /* max_k tau_k, complexity index (ms) */
+  double mean_tau_ms;   /* mean_k tau_k */
+  double max_viol_box;  /* max_k distance of u_k to [umin, umax] (inf-norm) */
+  double max_viol_eq;   /* max_k |E u_k + Ed d_k|_inf */
+  long long iters;      /* APG iterations over all steps */
+  int steps_converged;  /* steps whose solve reached tol */
+} tapg_loop_stats;
+tapg_status tapg_closed_loop(tapg_solver solver, tapg_tree tree, int H_s, const double* x0,
+                             const double* u_prev, tapg_forecast_fn forecast, void* ctx,
+                             int warm_start, double* x_traj, double* u_traj, double* tau_ms,
+                             int* iters, tapg_loop_stats* stats);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* tapg_last_error(void);
 /* Library version string. */

@@ -21,6 +21,7 @@ objective       primal cost, constraint violations, dual objective,
                 duality gap of a dual point
 stepsize        Lipschitz constant of the dual gradient (power iteration and
                 the dense eigenvalue for tiny trees)
+closed_loop     receding-horizon simulation with the paper's performance indices
 
 Every function is pinned by a ``-m "not gpu"`` test against an independent
 fact (closed forms, brute force, a textbook solver); none is "parity
@@ -42,6 +43,7 @@ from .apg import APGResult, apg, theta_next, theta_of, beta_sequence
 from .objective import primal_cost, violations, dual_objective, g_conj, g_value, \
     split_residual, split_gap
 from .stepsize import lipschitz_power, lipschitz_dense, dual_hessian_dense
+from .closed_loop import LoopResult, closed_loop
 
 __all__ = [
     "TreeIndex",
@@ -72,4 +74,6 @@ __all__ = [
     "lipschitz_power",
     "lipschitz_dense",
     "dual_hessian_dense",
+    "LoopResult",
+    "closed_loop",
 ]

@@ -42,7 +42,7 @@ EXPORTED = [
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
     "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune", "tapg_sweep_form",
     "tapg_schedule_spec", "tapg_event_pair_overhead",
-    "tapg_solver_forget", "tapg_solve_noalloc", "tapg_noalloc_bytes",
+    "tapg_solver_forget", "tapg_solve_noalloc", "tapg_noalloc_bytes", "tapg_closed_loop",
     "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats", "tapg_server_timing",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
 ]
@@ -94,6 +94,25 @@ class TapgResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TapgLoopStats(ctypes.Structure):
+    _fields_ = [
+        ("kpi_E", ctypes.c_double),
+        ("kpi_S", ctypes.c_double),
+        ("kpi_tau_ms", ctypes.c_double),
+        ("mean_tau_ms", ctypes.c_double),
+        ("max_viol_box", ctypes.c_double),
+        ("max_viol_eq", ctypes.c_double),
+        ("iters", ctypes.c_longlong),
+        ("steps_converged", ctypes.c_int),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+FORECAST_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
 _lib = None
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
@@ -144,6 +163,9 @@ def lib() -> ctypes.CDLL:
         "tapg_solve_noalloc": ([_P, _P, _D, _D, _D, _D, _D, ctypes.POINTER(TapgResult)],
                                ctypes.c_int),
         "tapg_noalloc_bytes": ([_P, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "tapg_closed_loop": ([_P, _P, ctypes.c_int, _D, _D, FORECAST_FN, ctypes.c_void_p,
+                              ctypes.c_int, _D, _D, _D, _I, ctypes.POINTER(TapgLoopStats)],
+                             ctypes.c_int),
         "tapg_batch_solve": ([_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_D),
                               ctypes.POINTER(_D), _I, ctypes.POINTER(_D),
                               ctypes.POINTER(TapgResult)], ctypes.c_int),
@@ -316,6 +338,41 @@ def tapg_noalloc_bytes(solver, tree) -> int:
     b = ctypes.c_size_t(0)
     _check(lib().tapg_noalloc_bytes(solver, tree, ctypes.byref(b)))
     return b.value
+
+
+def tapg_closed_loop(solver, tree, H_s, x0, u_prev, forecast, K, nd, warm_start=True):
+    """Closed-loop simulation; ``forecast(k) -> (demand [K, nd], price [K])``
+    supplies the tree's data at step k.  Returns ``(x_traj, u_traj, tau_ms,
+    iters, stats)``."""
+    x0, u_prev = _f64(x0), _f64(u_prev)
+    nx, nu = x0.size, u_prev.size
+    err = []
+
+    def cb(ctx, k, dptr, pptr):
+        try:
+            d, p = forecast(k)
+            d = _f64(d, K * nd)
+            p = _f64(p, K)
+            ctypes.memmove(dptr, d.ctypes.data, d.nbytes)
+            ctypes.memmove(pptr, p.ctypes.data, p.nbytes)
+            return 0
+        except Exception as e:  # reported after the call
+            err.append(e)
+            return 1
+
+    fn = FORECAST_FN(cb)
+    xt = np.zeros((H_s + 1, nx))
+    ut = np.zeros((H_s, nu))
+    tau = np.zeros(H_s)
+    its = np.zeros(H_s, dtype=np.int32)
+    st = TapgLoopStats()
+    status = lib().tapg_closed_loop(solver, tree, int(H_s), _ptr(x0), _ptr(u_prev), fn, None,
+                                    int(bool(warm_start)), _ptr(xt), _ptr(ut), _ptr(tau),
+                                    its.ctypes.data_as(_I), ctypes.byref(st))
+    if err:
+        raise err[0]
+    _check(status)
+    return xt, ut, tau, its, st
 
 
 def tapg_batch_solve(solver, trees, ps, qs, warm_start=None, nu=None):

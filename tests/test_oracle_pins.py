@@ -600,3 +600,28 @@ def test_gap_vanishes_at_the_slsqp_optimum(seed, p_level, price_scale):
     if price_scale > 1:
         nx = P.net.nx
         assert np.abs(r.y[:, nx:2 * nx]).max() > 1e-3  # safety-level duals active
+
+
+# ---------------------------------------------------------------------------
+# Closed loop (Sec. 6.3): invariants of the plant and the applied inputs
+# ---------------------------------------------------------------------------
+def test_closed_loop_invariants():
+    """The plant's next state is the solved problem's root state (the root
+    carries the observed demand, so the model and the plant agree one step
+    ahead), and every applied input meets the mass balance with the observed
+    demand."""
+    P = ds.config_problem("small")
+    nf = O.NodeFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / O.lipschitz_dense(P, nf)
+    inp = ds.make_loop_inputs(P.net, 30, seed=5, demand_model="sinusoid",
+                              price_model="uniform")
+    H = 12
+    r = O.closed_loop(P, inp, H, gamma, nf, 300)
+    assert r.x.shape == (H + 1, P.net.nx) and r.u.shape == (H, P.net.nu)
+    assert np.abs(r.x[1:] - r.root_states).max() <= 1e-12 * max(1.0, np.abs(r.x).max())
+    bal = r.u @ P.net.E.T + inp.demand[:H] @ P.net.Ed.T
+    assert np.abs(bal).max() <= 1e-12
+    d0, p0 = inp.tree_data(P.net, P.tree, 3)
+    assert np.array_equal(d0[0], inp.demand[3]) and p0[0] == inp.price[3]
+    assert r.kpi_S >= 0.0
+    assert np.all(r.iters == 300)
