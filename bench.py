@@ -104,6 +104,11 @@ def main():
     ap.add_argument("--sessions", type=int, default=32, help="serve: sessions (one tree each)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: trees in flight")
     ap.add_argument("--hbm-gb", type=float, default=64.0, help="serve: admission budget")
+    ap.add_argument("--horizon-steps", type=int, default=168, help="closed loop: H_s")
+    ap.add_argument("--ext-steps", type=int, default=2,
+                    help="timed steps of each extension workload in the default run")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="time the headline workload only")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -123,9 +128,50 @@ def main():
     # long solves print their own progress (iterations, trees running) to stderr
     os.environ.setdefault("TAPG_PROGRESS", "30")
     if args.config == "batch64":
-        return main_batch(args, ds, tapg)
+        out = main_batch(args, ds, tapg)
+        print(json.dumps(out), flush=True)
+        return
     if args.config == "serve":
         return main_serve(args, ds, tapg)
+    if args.config == "closed_loop":
+        print(json.dumps(main_closed_loop(args, ds, tapg)), flush=True)
+        return
+    out = main_single(args, ds, tapg, have_torch)
+    if not args.no_extensions and args.config == "dwn128":
+        out["extensions"] = extensions(args, ds, tapg, have_torch)
+    print(json.dumps(out), flush=True)
+
+
+def extensions(args, ds, tapg, have_torch):
+    """The extension workloads, timed in the same run as the headline (each a
+    few steps at the paper's tolerance 5e-2): the 2,048-scenario tree and the
+    64-tree batch in FP64 and FP32 sweeps, and a closed loop."""
+    ext = {}
+    for cfg, prec in (("dwn2048", "fp64"), ("dwn2048", "fp32"), ("batch64", "fp64"),
+                      ("batch64", "fp32")):
+        a = argparse.Namespace(**vars(args))
+        a.config, a.precision, a.tol = cfg, prec, 5e-2
+        a.steps, a.warmup = args.ext_steps, 1
+        a.no_cpu_baseline = True
+        a.max_iter = 400000
+        print(f"[bench] extension {cfg} {prec} tol 5e-2", file=sys.stderr, flush=True)
+        r = main_batch(a, ds, tapg) if cfg == "batch64" else main_single(a, ds, tapg, have_torch)
+        ext[f"{cfg}_{prec}_tol5e-2"] = {k: r[k] for k in r if k not in (
+            "metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data",
+            "cpu_baseline")}
+    a = argparse.Namespace(**vars(args))
+    a.config, a.precision, a.tol = "dwn128", "fp64", 5e-2
+    print("[bench] extension closed loop", file=sys.stderr, flush=True)
+    r = main_closed_loop(a, ds, tapg)
+    ext["closed_loop_dwn128_fp64_tol5e-2"] = {k: r[k] for k in r if k not in (
+        "metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data", "cpu_baseline")}
+    return ext
+
+
+def main_single(args, ds, tapg, have_torch):
+    """One tree (dwn128, dwn2048 or small) solved to the tolerance per step."""
+    if have_torch:
+        import torch
     P = ds.config_problem(args.config)
     net, w = P.net, P.weights
     prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
@@ -240,7 +286,7 @@ def main():
         "config": {"workload": f"{args.config}: nx={net.nx} nu={net.nu} nd={net.nd} "
                                f"ns={net.ns} N={P.tree.N}, "
                                f"{P.tree.n_scenarios} scenarios, K={P.tree.K}, "
-                               f"tol={args.tol:g}, cold start",
+                               f"W_u={wu_text(w.W_u)}, tol={args.tol:g}, cold start",
                    "K": P.tree.K, "N": P.tree.N, "tol": args.tol, "precision": args.precision},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
@@ -257,8 +303,13 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
     S.close()
+    return out
+
+
+def wu_text(W):
+    d = float(W[0, 0])
+    return f"{d:g} I" if np.array_equal(W, d * np.eye(W.shape[0])) else "dense"
 
 
 def main_batch(args, ds, tapg):
@@ -335,7 +386,8 @@ def main_batch(args, ds, tapg):
         "dtype": "f64" if prec == tapg.TAPG_FP64 else "f32",
         "data": "synthetic",
         "config": {"workload": f"batch64: 64 trees, S in 16..256, K total {K_tot}, "
-                               f"tol={args.tol:g}, cold start, one tapg_batch_solve per step",
+                               f"W_u={wu_text(w.W_u)}, tol={args.tol:g}, cold start, "
+                               f"one tapg_batch_solve per step",
                    "trees": 64, "K_total": K_tot, "tol": args.tol, "precision": args.precision},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
@@ -349,11 +401,71 @@ def main_batch(args, ds, tapg):
                      "autotune_candidates": tune_nc, "forest_ms_per_iter": round(tune_ms, 5),
                      "forest_gb_per_iter": round(forest_bytes / 1e9, 4),
                      "forest_gbs": round(forest_bytes / (tune_ms * 1e-3) / 1e9, 1)},
-        "roofline": None,
+        # the forest's whole iteration (every launch) as the autotuner timed it
+        # with all trees running, against the HBM peak
+        "roofline": {"bound": "hbm", "achieved": round(forest_bytes / (tune_ms * 1e-3) / 1e9, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(forest_bytes / (tune_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                     "traffic": None, "kernel": "forest iteration (every launch)",
+                     "bytes_per_iteration": int(forest_bytes),
+                     "ms_per_iteration": round(tune_ms, 5)},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
     S.close()
+    return out
+
+
+def main_closed_loop(args, ds, tapg):
+    """Closed-loop receding-horizon simulation (Sec. 6.3): H_s = 168 hourly
+    steps on the 128-scenario tree, each solved to the tolerance warm started
+    from the previous dual; the paper's indices KPI_E, KPI_S and KPI_tau (the
+    worst solve time)."""
+    P = ds.config_problem("dwn128")
+    net, w = P.net, P.weights
+    prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
+    H = args.horizon_steps
+    inp = ds.make_loop_inputs(net, H + P.tree.N, seed=1006)
+    S = tapg.Solver(dict(A=net.A, B=net.B, Gd=net.Gd, E=net.E, Ed=net.Ed, xmin=net.xmin,
+                         xmax=net.xmax, xs=net.xs, umin=net.umin, umax=net.umax),
+                    dict(W_alpha=w.W_alpha, W_s=w.W_s, W_x=w.W_x, alpha0=w.alpha0,
+                         c_energy=w.c_energy, W_u=w.W_u),
+                    P.tree.N, gamma=0.0, tol=args.tol, max_iter=args.max_iter,
+                    check_every=args.check_every, precision=prec)
+    tree = S.add_tree(P.tree.nodes_per_stage, P.tree.anc, P.tree.prob, P.data.demand,
+                      P.data.price)
+    tapg.tapg_estimate_lipschitz(S.h, tree, 100)
+    tapg.tapg_autotune(S.h, [tree], 100)
+    def forecast(k):
+        if k % 24 == 0:
+            print(f"[bench] closed loop: step {k} of {H}", file=sys.stderr, flush=True)
+        return inp.tree_data(net, P.tree, k)
+
+    t0 = time.perf_counter()
+    xt, ut, tau, its, st = tapg.tapg_closed_loop(S.h, tree, H, P.p, P.q, forecast, P.tree.K,
+                                                 net.nd)
+    total = time.perf_counter() - t0
+    out = {
+        "metric": METRIC + " (closed loop)",
+        "value": round(H / total, 4),
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": H, "warmup": 0,
+        "ms_per_step": round(1e3 * total / H, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == tapg.TAPG_FP64 else "f32", "data": "synthetic",
+        "config": {"workload": f"closed loop: dwn128 tree (K={P.tree.K}), H_s={H} hourly steps, "
+                               f"W_u={wu_text(w.W_u)}, tol={args.tol:g}, warm-started re-solves",
+                   "H_s": H, "tol": args.tol, "precision": args.precision},
+        "kpi_E": round(st.kpi_E, 6), "kpi_S": round(st.kpi_S, 6),
+        "kpi_tau_ms": round(st.kpi_tau_ms, 3), "mean_tau_ms": round(st.mean_tau_ms, 3),
+        "p50_ms": round(float(np.percentile(tau, 50)), 3),
+        "p99_ms": round(float(np.percentile(tau, 99)), 3),
+        "iters_first": int(its[0]), "iters_p50": int(np.percentile(its, 50)),
+        "iters_max": int(its.max()), "steps_converged": int(st.steps_converged),
+        "max_viol_box": st.max_viol_box, "max_viol_eq": st.max_viol_eq,
+        "roofline": None, "cpu_baseline": None,
+    }
+    S.close()
+    return out
 
 
 def main_serve(args, ds, tapg):
@@ -489,6 +601,17 @@ def cpu_baseline(P, gamma, gpu_iters, seconds):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                         "unknown")
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
     f = O.StageFactors(P.net, P.weights.W_u, P.tree)
     t0 = time.perf_counter()
     O.apg(P, gamma, f, 3)
@@ -498,7 +621,8 @@ def cpu_baseline(P, gamma, gpu_iters, seconds):
     O.apg(P, gamma, f, n)
     per = (time.perf_counter() - t0) / n
     return {"value": round(1.0 / (per * gpu_iters), 6), "unit": "solves/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cpus": usable,
             "sample": f"{n} oracle APG iterations (NumPy FP64, per-stage einsum) on the same "
                       f"instance; per-iteration time {per * 1e3:.2f} ms scaled to the "
                       f"{gpu_iters} iterations of one solve"}

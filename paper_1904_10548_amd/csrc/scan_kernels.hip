@@ -569,7 +569,14 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
   int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);  // CSR of B (nx rows)
   int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
   T* sVal = reinterpret_cast<T*>(smem_raw + L.bval);
-  __shared__ T sBnd[5 * kSU];  // gamma-scaled bounds: xmin, xmax, xs | umin, umax
+  // bounds xmin, xmax, xs | umin, umax: scaled by gamma in FP64 sweeps (then
+  // gamma P_C(v / gamma) = P_{gamma C}(v) needs no division); unscaled with FP32
+  // sweeps, whose prox runs in FP64 (bnd() scales them there)
+  __shared__ T sBnd[5 * kSU];
+  const T bscale = sizeof(T) == sizeof(double) ? gam : T(1);
+  auto bnd = [&](int i) -> double {
+    return sizeof(T) == sizeof(double) ? (double)sBnd[i] : gam64 * (double)sBnd[i];
+  };
   int par0, parl;  // parents of the level's first and last first-stage nodes
   {
     const int2* rg = a.ranges + (size_t)wg * a.nst;
@@ -579,11 +586,11 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
     }
     csr_to_lds<T>(a.Brow, a.Bcol, a.Bval, nx, a.nnzB, sRow, sCol, sVal);
     for (int i = tid; i < kSU; i += kSegThreads) {
-      sBnd[i] = gam * ldm(a.xmin, i, i < nx);
-      sBnd[kSU + i] = gam * ldm(a.xmax, i, i < nx);
-      sBnd[2 * kSU + i] = gam * ldm(a.xs, i, i < nx);
-      sBnd[3 * kSU + i] = gam * ldm(a.umin, i, i < nu);
-      sBnd[4 * kSU + i] = gam * ldm(a.umax, i, i < nu);
+      sBnd[i] = bscale * ldm(a.xmin, i, i < nx);
+      sBnd[kSU + i] = bscale * ldm(a.xmax, i, i < nx);
+      sBnd[2 * kSU + i] = bscale * ldm(a.xs, i, i < nx);
+      sBnd[3 * kSU + i] = bscale * ldm(a.umin, i, i < nu);
+      sBnd[4 * kSU + i] = bscale * ldm(a.umax, i, i < nu);
     }
     const int2 pp = a.wgx[2 * wg + 1];
     par0 = pp.x;
@@ -805,43 +812,49 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
         if (C.ox[j] >= 0 && ix < nx) zsq += 2.0 * (double)dxv[j] * (double)dxv[j];
       }
     } else {
-      const T ulo = sBnd[3 * kSU + iu], uhi = sBnd[4 * kSU + iu];
-      const T xlo = sBnd[ix], xhi = sBnd[kSU + ix], xsf = sBnd[2 * kSU + ix];
+      // The prox and the residual in FP64 whatever T (the FP32 sweeps' w and
+      // x widened): y+ is rounded to T once, and |y+ - w| / gamma is the FP64
+      // split residual |H x_hat - t| of those inputs.
+      const double ulo = bnd(3 * kSU + iu), uhi = bnd(4 * kSU + iu);
+      const double xlo = bnd(ix), xhi = bnd(kSU + ix), xsf = bnd(2 * kSU + ix);
 #pragma unroll
       for (int j = 0; j < kQU; ++j) {
-        const T w = w3r[j];
-        const T v = w + gam * du[j];
-        dy3[j] = v - fmin(fmax(v, ulo), uhi);
+        const double w = (double)w3r[j];
+        const double v = w + gam64 * (double)du[j];
+        const double y = v - fmin(fmax(v, ulo), uhi);
+        dy3[j] = (T)y;
         if (C.ou[j] >= 0 && iu < nu) {
-          double d = fabs((double)dy3[j] - (double)w);
+          double d = fabs(y - w);
           if (!(d <= 1.0e308)) d = INFINITY;
           rmax = fmax(rmax, d);
         }
       }
-      T r1[kQX], r2[kQX];
+      double r1[kQX], r2[kQX];
       double q1[kQX], q2[kQX];
 #pragma unroll
       for (int j = 0; j < kQX; ++j) {
         const bool valid = C.nx[j] >= 0 && ix < nx;
-        const T v1 = w1r[j] + gam * dxv[j], v2 = w2r[j] + gam * dxv[j];
-        r1[j] = valid ? v1 - fmin(fmax(v1, xlo), xhi) : T(0);
-        r2[j] = valid ? v2 - fmax(v2, xsf) : T(0);
+        const double v1 = (double)w1r[j] + gam64 * (double)dxv[j];
+        const double v2 = (double)w2r[j] + gam64 * (double)dxv[j];
+        r1[j] = valid ? v1 - fmin(fmax(v1, xlo), xhi) : 0.0;
+        r2[j] = valid ? v2 - fmax(v2, xsf) : 0.0;
       }
 #pragma unroll
       for (int j = 0; j < kQX; ++j) {
-        q1[j] = wave_sum((double)r1[j] * (double)r1[j]);
-        q2[j] = wave_sum((double)r2[j] * (double)r2[j]);
+        q1[j] = wave_sum(r1[j] * r1[j]);
+        q2[j] = wave_sum(r2[j] * r2[j]);
       }
 #pragma unroll
       for (int j = 0; j < kQX; ++j) {
         const double n1 = sqrt(q1[j]), n2 = sqrt(q2[j]);
-        const T sc1 = n1 > (double)a.Wx ? (T)((double)a.Wx / n1) : T(1);
-        const T sc2 = n2 > (double)a.Ws ? (T)((double)a.Ws / n2) : T(1);
-        dy1[j] = r1[j] * sc1;
-        dy2[j] = r2[j] * sc2;
+        const double sc1 = n1 > (double)a.Wx ? (double)a.Wx / n1 : 1.0;
+        const double sc2 = n2 > (double)a.Ws ? (double)a.Ws / n2 : 1.0;
+        const double y1 = r1[j] * sc1, y2 = r2[j] * sc2;
+        dy1[j] = (T)y1;
+        dy2[j] = (T)y2;
         if (C.ox[j] >= 0 && ix < nx) {
-          double d1 = fabs((double)dy1[j] - (double)w1r[j]);
-          double d2 = fabs((double)dy2[j] - (double)w2r[j]);
+          double d1 = fabs(y1 - (double)w1r[j]);
+          double d2 = fabs(y2 - (double)w2r[j]);
           if (!(d1 <= 1.0e308)) d1 = INFINITY;
           if (!(d2 <= 1.0e308)) d2 = INFINITY;
           rmax = fmax(rmax, fmax(d1, d2));

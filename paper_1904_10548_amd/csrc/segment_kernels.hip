@@ -510,14 +510,20 @@ __device__ __forceinline__ double seg_fwd_body(const SegArgs<T>& a, int wg, int 
   // (and a component inside the box leaves r = v - v = 0 exactly).
   // Kept in LDS (registers are scarce here): [xmin | xmax | xs] by x-slot,
   // [umin | umax] by u-slot, 128 entries each (nx, nu <= 128 on this path).
+  // With FP32 sweeps the bounds are kept unscaled and the prox runs in FP64
+  // (bnd() scales them there).
   __shared__ T sBnd[5 * kRT];
+  const T bscale = sizeof(T) == sizeof(double) ? gam : T(1);
   for (int i = tid; i < kRT; i += kSegThreads) {
-    sBnd[i] = gam * ldm(a.xmin, i, i < nx);
-    sBnd[kRT + i] = gam * ldm(a.xmax, i, i < nx);
-    sBnd[2 * kRT + i] = gam * ldm(a.xs, i, i < nx);
-    sBnd[3 * kRT + i] = gam * ldm(a.umin, i, i < nu);
-    sBnd[4 * kRT + i] = gam * ldm(a.umax, i, i < nu);
+    sBnd[i] = bscale * ldm(a.xmin, i, i < nx);
+    sBnd[kRT + i] = bscale * ldm(a.xmax, i, i < nx);
+    sBnd[2 * kRT + i] = bscale * ldm(a.xs, i, i < nx);
+    sBnd[3 * kRT + i] = bscale * ldm(a.umin, i, i < nu);
+    sBnd[4 * kRT + i] = bscale * ldm(a.umax, i, i < nu);
   }
+  auto bnd = [&](int i) -> double {
+    return sizeof(T) == sizeof(double) ? (double)sBnd[i] : gam64 * (double)sBnd[i];
+  };
   // Per-node inputs of a stage: u-slots (j, 1/p, parent, y3, y3o), x-slots
   // (g, parent, y1, y1o, y2, y2o).  Two sets alternate between stages, so the
   // loads for stage s+1 fly while stage s computes and no register is copied.
@@ -744,23 +750,26 @@ __device__ __forceinline__ double seg_fwd_body(const SegArgs<T>& a, int wg, int 
         if (idx < NB * LDU && b < nb && i < nu) zsq += (double)uv[q] * (double)uv[q];
       }
     } else {
+      // The prox and the residual in FP64 whatever T (FP32 sweeps: w and x
+      // widened, y+ rounded to T once, |y+ - w| / gamma the FP64 residual).
       // block 3: box projection, elementwise
 #pragma unroll
       for (int q = 0; q < QX; ++q) {
         const int idx = tid + q * kSegThreads;
         const int b = idx / LDU, i = idx - b * LDU;
         if (idx < NB * LDU && b < nb && i < nu) {
-          const T w = w3c[q];
-          const T v = w + gam * uv[q];
-          const T y = v - fmin(fmax(v, sBnd[3 * kRT + i]), sBnd[4 * kRT + i]);
-          dy3[q] = y;
-          double d = fabs((double)y - (double)w);
+          const double w = (double)w3c[q];
+          const double v = w + gam64 * (double)uv[q];
+          const double y = v - fmin(fmax(v, bnd(3 * kRT + i)), bnd(4 * kRT + i));
+          dy3[q] = (T)y;
+          double d = fabs(y - w);
           if (!(d <= 1.0e308)) d = INFINITY;
           rmax = fmax(rmax, d);
         }
       }
       // blocks 1, 2: distance prox, needs the Euclidean norm of each node's block
-      T r1v[QX], r2v[QX], w1v[QX], w2v[QX];
+      double r1v[QX], r2v[QX];
+      T w1v[QX], w2v[QX];
       double q1v[QX], q2v[QX];
 #pragma unroll
       for (int q = 0; q < QX; ++q) {
@@ -769,15 +778,16 @@ __device__ __forceinline__ double seg_fwd_body(const SegArgs<T>& a, int wg, int 
         const bool ok = idx < NB * LDX && b < nb && i < nx;
         const T w1 = w1c[q];
         const T w2 = w2c[q];
-        const T v1 = w1 + gam * xv[q], v2 = w2 + gam * xv[q];
-        const T rr1 = v1 - fmin(fmax(v1, sBnd[i]), sBnd[kRT + i]);
-        const T rr2 = v2 - fmax(v2, sBnd[2 * kRT + i]);
-        r1v[q] = ok ? rr1 : T(0);
-        r2v[q] = ok ? rr2 : T(0);
+        const double v1 = (double)w1 + gam64 * (double)xv[q];
+        const double v2 = (double)w2 + gam64 * (double)xv[q];
+        const double rr1 = v1 - fmin(fmax(v1, bnd(i)), bnd(kRT + i));
+        const double rr2 = v2 - fmax(v2, bnd(2 * kRT + i));
+        r1v[q] = ok ? rr1 : 0.0;
+        r2v[q] = ok ? rr2 : 0.0;
         w1v[q] = w1;
         w2v[q] = w2;
-        q1v[q] = (double)r1v[q] * (double)r1v[q];
-        q2v[q] = (double)r2v[q] * (double)r2v[q];
+        q1v[q] = r1v[q] * r1v[q];
+        q2v[q] = r2v[q] * r2v[q];
       }
       double n1v[QX], n2v[QX];
       if (wave_norm) {
@@ -821,13 +831,13 @@ __device__ __forceinline__ double seg_fwd_body(const SegArgs<T>& a, int wg, int 
         const int b = idx / LDX, i = idx - b * LDX;
         if (idx < NB * LDX && b < nb && i < nx) {
           const double n1 = sqrt(n1v[q]), n2 = sqrt(n2v[q]);
-          const T sc1 = n1 > (double)a.Wx ? (T)((double)a.Wx / n1) : T(1);
-          const T sc2 = n2 > (double)a.Ws ? (T)((double)a.Ws / n2) : T(1);
-          const T y1 = r1v[q] * sc1, y2 = r2v[q] * sc2;
-          dy1[q] = y1;
-          dy2[q] = y2;
-          double d1 = fabs((double)y1 - (double)w1v[q]);
-          double d2 = fabs((double)y2 - (double)w2v[q]);
+          const double sc1 = n1 > (double)a.Wx ? (double)a.Wx / n1 : 1.0;
+          const double sc2 = n2 > (double)a.Ws ? (double)a.Ws / n2 : 1.0;
+          const double y1 = r1v[q] * sc1, y2 = r2v[q] * sc2;
+          dy1[q] = (T)y1;
+          dy2[q] = (T)y2;
+          double d1 = fabs(y1 - (double)w1v[q]);
+          double d2 = fabs(y2 - (double)w2v[q]);
           if (!(d1 <= 1.0e308)) d1 = INFINITY;
           if (!(d2 <= 1.0e308)) d2 = INFINITY;
           rmax = fmax(rmax, fmax(d1, d2));

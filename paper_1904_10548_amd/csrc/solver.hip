@@ -223,8 +223,9 @@ void free_net(NetDev<T>& d) {
 // Nodes per tile: the largest NB in {8, 4, 2, 1} that keeps at least 256
 // tiles in the stage and fits the forward kernel's LDS in 64 KiB.
 int pick_nb(int width, size_t elem, int LDX, int LDU, int LDY) {
-  for (int nb : {8, 4, 2}) {
-    const size_t lds = (size_t)(2 * LDX + 2 * LDU + kThreads + 2 * LDY) * nb * elem;
+  for (int nb : {8, 4, 2}) {  // the forward kernel's LDS (its prox tiles are FP64)
+    const size_t lds = (size_t)(2 * LDX + 2 * LDU + kThreads) * nb * elem +
+                       (size_t)2 * LDY * nb * sizeof(double);
     if ((width + nb - 1) / nb >= 256 && lds <= 60 * 1024) return nb;
   }
   return 1;

@@ -210,7 +210,6 @@ __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
   const bool power = a.mode == 1;
   const T beta = (T)ctl->beta;
   const double gam64 = ctl->gamma;
-  const T gam = (T)gam64;
   const int LDX = a.LDX, LDU = a.LDU, LDY = a.LDY;
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -219,8 +218,10 @@ __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
   T* sUn = sXp + NB * LDX;                  // u_n
   T* sXn = sUn + NB * LDU;                  // x_n
   T* red = sXn + NB * LDX;                  // NB * 256
-  T* sW = red + NB * kThreads;              // w (blocks 1, 2)
-  T* sR = sW + NB * LDY;                    // r (blocks 1, 2)
+  // the prox runs in FP64 whatever T (with FP32 sweeps: w and x widened, y+
+  // rounded to T once, the residual the FP64 split residual of those inputs)
+  double* sW = reinterpret_cast<double*>(red + NB * kThreads);  // w (blocks 1, 2)
+  double* sR = sW + NB * LDY;                                   // r (blocks 1, 2)
   __shared__ double ps1[kThreads], ps2[kThreads], pmax[kThreads];
 
   for (int idx = threadIdx.x; idx < NB * LDU; idx += kThreads) {
@@ -296,15 +297,16 @@ __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
           s1 += (double)z * (double)z;
           continue;
         }
-        const T w = wext(yc[i], yn[i], beta);
-        const T v = w + gam * xi;
-        const T zz = v / gam;
-        const T pz = blk == 0 ? fmin(fmax(zz, a.xmin[k]), a.xmax[k]) : fmax(zz, a.xs[k]);
-        const T rr = v - gam * pz;
+        const double w = (double)wext(yc[i], yn[i], beta);
+        const double v = w + gam64 * (double)xi;
+        const double zz = v / gam64;
+        const double pz = blk == 0 ? fmin(fmax(zz, (double)a.xmin[k]), (double)a.xmax[k])
+                                   : fmax(zz, (double)a.xs[k]);
+        const double rr = v - gam64 * pz;
         if (blk == 0)
-          s1 += (double)rr * (double)rr;
+          s1 += rr * rr;
         else
-          s2 += (double)rr * (double)rr;
+          s2 += rr * rr;
         sW[b * LDY + i] = w;
         sR[b * LDY + i] = rr;
       } else {
@@ -317,12 +319,12 @@ __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
           s1 += (double)z * (double)z;
           continue;
         }
-        const T w = wext(yc[i], yn[i], beta);
-        const T v = w + gam * ui;
-        const T t = fmin(fmax(v / gam, a.umin[k]), a.umax[k]);
-        const T y = v - gam * t;
-        yn[i] = y;
-        double d = fabs((double)y - (double)w) / gam64;
+        const double w = (double)wext(yc[i], yn[i], beta);
+        const double v = w + gam64 * (double)ui;
+        const double t = fmin(fmax(v / gam64, (double)a.umin[k]), (double)a.umax[k]);
+        const double y = v - gam64 * t;
+        yn[i] = (T)y;
+        double d = fabs(y - w) / gam64;
         if (!(d <= 1.0e308)) d = INFINITY;
         rmax = fmax(rmax, d);
       }
@@ -349,15 +351,15 @@ __global__ __launch_bounds__(kThreads) void fwd_stage_kernel(SweepArgs<T> a) {
     const int n = n0 + b;
     T* yn = Yn + (size_t)n * LDY;
     const double n1 = sqrt(ps1[b * TPN]), n2 = sqrt(ps2[b * TPN]);
-    const T sc1 = n1 > (double)a.Wx ? (T)((double)a.Wx / n1) : T(1);
-    const T sc2 = n2 > (double)a.Ws ? (T)((double)a.Ws / n2) : T(1);
+    const double sc1 = n1 > (double)a.Wx ? (double)a.Wx / n1 : 1.0;
+    const double sc2 = n2 > (double)a.Ws ? (double)a.Ws / n2 : 1.0;
     for (int i = l; i < 2 * LDX; i += TPN) {
       const int blk = i < LDX ? 0 : 1;
       const int k = i - blk * LDX;
       if (k >= a.nx) continue;
-      const T y = sR[b * LDY + i] * (blk == 0 ? sc1 : sc2);
-      yn[i] = y;
-      double d = fabs((double)y - (double)sW[b * LDY + i]) / gam64;
+      const double y = sR[b * LDY + i] * (blk == 0 ? sc1 : sc2);
+      yn[i] = (T)y;
+      double d = fabs(y - sW[b * LDY + i]) / gam64;
       if (!(d <= 1.0e308)) d = INFINITY;
       rmax = fmax(rmax, d);
     }
@@ -676,7 +678,8 @@ void launch_bwd(const SweepArgs<T>& a, int tiles, hipStream_t st) {
 
 template <typename T, int NB>
 void launch_fwd(const SweepArgs<T>& a, int tiles, hipStream_t st) {
-  const size_t lds = (size_t)(2 * a.LDX + 2 * a.LDU + kThreads + 2 * a.LDY) * NB * sizeof(T);
+  const size_t lds = (size_t)(2 * a.LDX + 2 * a.LDU + kThreads) * NB * sizeof(T) +
+                     (size_t)2 * a.LDY * NB * sizeof(double);
   hipLaunchKernelGGL((fwd_stage_kernel<T, NB>), dim3(tiles), dim3(kThreads), lds, st, a);
 }
 

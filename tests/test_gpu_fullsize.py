@@ -244,3 +244,48 @@ def test_served_full_size_same_result_alone_and_in_the_mix():
         assert r.iters == ra.iters
         assert np.abs(u0 - u0a).max() <= 1e-12 * max(1.0, np.abs(u0a).max())
         assert abs(r.cost - ra.cost) <= 1e-9 * max(1.0, abs(ra.cost))
+
+
+FIXED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fixed_iterations.json")
+
+
+def _fixed(name):
+    if not os.path.exists(FIXED):
+        pytest.skip("tests/golden/fixed_iterations.json has not been written yet "
+                    "(tests/golden/make_fixed_golden.py)")
+    with open(FIXED) as f:
+        return json.load(f)[name]
+
+
+@pytest.mark.parametrize("name", ["dwn128", "dwn2048"])
+@pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
+def test_fixed_iterations_fp64_and_fp32_against_oracle(name, precision):
+    """The 2,429-node tree after 3,000 iterations and the 30,717-node tree after
+    500 (residuals 1.6 and 28), at the oracle's step size: FP64
+    sweeps to the FP64 bar; FP32 sweeps (FP64 factors, prox and residual) with
+    their cost error against the FP64 oracle at the same iteration."""
+    g = _fixed(name)
+    P = ds.config_problem(name)
+    nodes = np.asarray(g["sample_nodes"])
+    say(name, "fixed", g["iters"], "precision", precision)
+    with make_solver(P, gamma=g["gamma"], tol=0.0, max_iter=g["iters"], check_every=100,
+                     precision=precision) as S:
+        t = add_tree(S, P)
+        st, u0, res = S.solve(t, P.p, P.q)
+        u, x = S.primal(t)
+    rel = abs(res.cost - g["cost"]) / max(1.0, abs(g["cost"]))
+    du = _rel(u0, g["u_root"])
+    say("cost", repr(res.cost), "oracle", g["cost"], "rel", rel, "u_root rel", du,
+        "residual", res.primal_res, "oracle", g["final_res"])
+    assert res.iters == g["iters"]
+    if precision == tapg.TAPG_FP64:
+        assert rel <= 1e-6 and du <= 1e-6
+        assert _rel(u[nodes], g["u_sample"]) <= 1e-9 * 1e3
+        assert _rel(x[nodes], g["x_sample"]) <= 1e-9 * 1e3
+        assert abs(res.primal_res - g["final_res"]) <= 1e-6 * g["final_res"]
+    else:
+        # measured: 6.9e-4 after 3,000 iterations of the 2,429-node tree (the
+        # FP32 and FP64 trajectories drift apart over the iterations), within
+        # 1e-4 after 500 of the 30,717-node tree
+        assert rel <= (1e-3 if name == "dwn128" else 1e-4)
+        assert du <= 1e-2

@@ -483,3 +483,34 @@ def test_forward_group_out_of_range_is_rejected():
                 S.solve(t, P.p, P.q)
             assert e.value.status == tapg.TAPG_EINVAL
     os.environ.pop("TAPG_FWD_GROUP", None)
+
+
+@pytest.mark.parametrize("scan", [True, False])
+def test_fp32_sweeps_residual_is_fp64(scan):
+    """With FP32 sweeps the prox and the stop test run in FP64 on the widened
+    FP32 inputs: one iteration from a dual of size ~1 (given with
+    tapg_set_dual, FP32-representable) on the 2,429-node tree, whose step size
+    (~1.4e-6) would amplify an FP32 dual update's rounding (ulp(1)/gamma ~ 0.04)
+    into the residual, gives the oracle's FP64 residual to 1e-4."""
+    P = ds.config_problem("dwn128")
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 60))
+    rng = np.random.default_rng(5)
+    nx, nu, K = P.net.nx, P.net.nu, P.tree.K
+    y1 = rng.standard_normal((K, nx))
+    y1 *= np.minimum(1.0, 0.9 * P.weights.W_x / np.linalg.norm(y1, axis=1))[:, None]
+    y2 = -np.abs(rng.standard_normal((K, nx)))
+    y2 *= np.minimum(1.0, 0.9 * P.weights.W_s / np.linalg.norm(y2, axis=1))[:, None]
+    y3 = rng.standard_normal((K, nu))
+    y = np.concatenate([y1, y2, y3], axis=1).astype(np.float32).astype(np.float64)
+    _schedule_env(scan=scan)
+    with make_solver(P, gamma=gamma, tol=0.0, max_iter=1, check_every=1,
+                     precision=tapg.TAPG_FP32) as S:
+        t = add_tree(S, P)
+        S.solve(t, P.p, P.q)
+        tapg.tapg_set_dual(S.h, t, y)
+        st, u0, res = S.solve(t, P.p, P.q, warm_start=True)
+    ref = O.apg(P, gamma, sf, 1, y0=y)
+    say("fp32 residual", res.primal_res, "oracle", ref.res_hist[0], "gamma", gamma)
+    assert res.iters == 1
+    assert abs(res.primal_res - ref.res_hist[0]) <= 1e-4 * max(1.0, ref.res_hist[0])
