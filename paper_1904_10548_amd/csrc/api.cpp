@@ -609,6 +609,7 @@ tapg_status tapg_schedule_spec(tapg_solver solver, int ntrees, const tapg_tree* 
         s += (l ? "," : "") + std::to_string(sl.plans[l].s_begin) + ":" +
              std::to_string(sl.plans[l].group);
       if (sl.scan) s += " TAPG_FWD_GROUP=" + std::to_string(sl.fwd_group);
+      if (sl.scan && sl.top_light) s += " TAPG_TOP=1";
     }
     if ((int)s.size() + 1 > cap) fail(TAPG_EINVAL, "buffer too small for the schedule");
     std::memcpy(buf, s.c_str(), s.size() + 1);
@@ -624,7 +625,8 @@ tapg_status tapg_sweep_form(tapg_solver solver, int ntrees, const tapg_tree* tre
     int f = TAPG_FORM_STAGES;
     if (sl.segmented) f = sl.scan ? TAPG_FORM_SCAN : solver->proj ? TAPG_FORM_PROJECTOR : TAPG_FORM_SEGMENT;
     if (form) *form = f;
-    if (bwd_launches) *bwd_launches = sl.segmented ? (int)sl.levels.size() : sl.N;
+    if (bwd_launches)
+      *bwd_launches = sl.segmented ? (int)sl.levels.size() : sl.N;
     return TAPG_OK;
   });
 }

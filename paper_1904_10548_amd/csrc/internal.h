@@ -171,6 +171,7 @@ struct Slot {
     int2* d_ranges;
     int* d_wgtree;  // tree of each workgroup (forests only)
     int2* d_wgx = nullptr;  // children of the last stage, parents of the first
+    int nw = 0;             // light upper level: most nodes of one workgroup (all stages)
   };
   std::vector<Level> levels;
   // Scan form: the forward sweep in one launch over stages 0..N-1, each
@@ -181,6 +182,11 @@ struct Slot {
   Level fwd_full{0, -1, 0, 1, 0, nullptr, nullptr};
   int* d_own = nullptr;
   int fwd_group = 0;
+  // Light upper levels (scan form, one tree): the levels above the bottom one
+  // run scan_top_kernel on local parts that n_loc extra workgroups of the
+  // bottom level's launch compute for the loc_count nodes above it.
+  bool top_light = false;
+  int n_loc = 0, loc_count = 0;
   std::vector<LevelPlan> plans;  // the plan the levels were built from
   bool segmented = false;
   bool scan = false;  // sweeps in scan form (the solver allows it; the autotuner may choose)

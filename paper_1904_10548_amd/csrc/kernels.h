@@ -185,6 +185,16 @@ struct SegArgs {
   // first node the workgroup owns; nodes before it (ancestors shared with a
   // lower-numbered workgroup) are computed but not written (nullptr: all owned)
   const int* own;
+  // Light upper levels (scan form, one tree).  With n_main > 0, the first
+  // backward launch (the bottom level, n_main workgroups) has more
+  // workgroups after those, each writing, for 4 of the loc_count nodes above
+  // the bottom level (nodes 0 .. loc_count - 1), a_n = w1_n + w2_n to lam and
+  // the local part of m_n, Pi (kappa_n - (w3_n + B' a_n) / (2 w)), to jv; the
+  // levels above then run scan_top_kernel, which only sums the children into
+  // lambda_n = a_n + sum_c lambda_c and P_n = local_n - Pi B' (sum_c lambda_c)
+  // / (2 w) + sum_c P_c (the same values by the linearity of Pi and B').
+  int n_main, loc_count;
+  int top_nodes;  // scan_top_kernel: most nodes of one workgroup over its stages
 };
 
 // Persistent iteration of one tree: every workgroup of every level in one
@@ -223,6 +233,11 @@ template <typename T>
 size_t scan_lds(int nbm, const SegArgs<T>& a);
 template <typename T>
 void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st);
+// A light upper level (scan form, one tree; see SegArgs::n_main) and its dynamic LDS.
+template <typename T>
+void launch_scan_top(const SegArgs<T>& a, int n_wg, hipStream_t st);
+template <typename T>
+size_t scan_top_lds(const SegArgs<T>& a);
 template <typename T>
 size_t seg_lds(int nbm, const SegArgs<T>& a);
 // Cooperative launch of the persistent iteration (NB: widest level's

@@ -541,6 +541,263 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
 }
 
 // ---------------------------------------------------------------------------
+// Local part of the backward recursion for the nodes above the bottom level
+// (light upper levels): workgroup k of this role takes nodes 4k .. 4k+3 of
+// the loc_count nodes above the bottom level, one node per 128 threads, and
+// writes a_n = w1_n + w2_n (to lam) and Pi (kappa_n - (w3_n + B' a_n) / (2 w))
+// (to jv).  It runs in the bottom level's launch, beside that level's
+// workgroups, and uses the same dynamic LDS layout.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void scan_local_body(const SegArgs<T>& a, int k, int it, T beta,
+                                                T scale) {
+  const bool power = a.mode == 1;  // w = scale y, no data terms
+  constexpr int LN = kSegThreads / kSU;  // nodes per workgroup
+  const int tid = threadIdx.x;
+  const T* Yc = (it & 1) ? a.Y1 : a.Y0;
+  const T* Yo = (it & 1) ? a.Y0 : a.Y1;
+  const int nx = a.nx, nu = a.nu, LDX = a.LDX, LDY = a.LDY, ns = a.ns;
+  const T hw = T(0.5) * a.winv;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BwdLds<T> L(a);
+  T* sA = reinterpret_cast<T*>(smem_raw + L.lam);  // [LN][kSX]
+  T* sV = reinterpret_cast<T*>(smem_raw + L.v);    // [LN][kSU]
+  T* sGv = reinterpret_cast<T*>(smem_raw + L.gv);  // [LN][ns]
+  int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);
+  int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
+  T* sVal = reinterpret_cast<T*>(smem_raw + L.bval);
+  int* gRow = reinterpret_cast<int*>(smem_raw + L.grow);
+  int* gCol = reinterpret_cast<int*>(smem_raw + L.gcol);
+  T* gVal = reinterpret_cast<T*>(smem_raw + L.gval);
+  int* eRow = reinterpret_cast<int*>(smem_raw + L.erow);
+  int* eCol = reinterpret_cast<int*>(smem_raw + L.ecol);
+  T* eVal = reinterpret_cast<T*>(smem_raw + L.eval);
+  const int b = tid / kSU, i = tid % kSU;
+  const int n = k * LN + b;
+  const bool node_ok = n < a.loc_count;
+  // inputs (issued before the CSR copies complete)
+  T ax = T(0), w3 = T(0), kap = T(0);
+  if (node_ok && i < nx) {
+    const size_t o = (size_t)n * LDY + i;
+    ax = power ? scale * (Yc[o] + Yc[o + LDX])
+               : wext(Yc[o], Yo[o], beta) + wext(Yc[o + LDX], Yo[o + LDX], beta);
+  }
+  if (node_ok && i < nu) {
+    const size_t o = (size_t)n * LDY + 2 * LDX + i;
+    w3 = power ? scale * Yc[o] : wext(Yc[o], Yo[o], beta);
+    kap = power ? T(0) : a.kappa[(size_t)n * kSU + i];
+  }
+  csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
+  csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, ns, a.nnzG, gRow, gCol, gVal);
+  csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
+  if (i < kSX) sA[b * kSX + i] = ax;
+  __syncthreads();
+  {  // v = kappa - (w3 + B' a) / (2 w)
+    T t = w3;
+    if (i < nu)
+      for (int p = sRow[i]; p < sRow[i + 1]; ++p) t += sVal[p] * sA[b * kSX + sCol[p]];
+    sV[b * kSU + i] = node_ok && i < nu ? kap - hw * t : T(0);
+  }
+  __syncthreads();
+  for (int e = tid; e < LN * ns; e += kSegThreads) {  // G v
+    const int bb = e / ns, r = e - bb * ns;
+    T acc = T(0);
+    for (int p = gRow[r]; p < gRow[r + 1]; ++p) acc += gVal[p] * sV[bb * kSU + gCol[p]];
+    sGv[bb * ns + r] = acc;
+  }
+  __syncthreads();
+  if (node_ok && i < nu) {  // Pi v = v - E'(G v)
+    T acc = T(0);
+    for (int p = eRow[i]; p < eRow[i + 1]; ++p) acc += eVal[p] * sGv[b * ns + eCol[p]];
+    a.jv[(size_t)n * kSU + i] = sV[b * kSU + i] - acc;
+  }
+  if (node_ok && i < nx) a.lam[(size_t)n * LDX + i] = ax;
+}
+
+// ---------------------------------------------------------------------------
+// A light upper level (one tree): workgroup wg holds its nodes of every stage
+// of the level (the level's node ranges), whose a_n and local part of m_n the
+// bottom level's launch left in lam and jv, and the children of its last
+// stage, which the level below left (lambda at that level's first stage, P
+// everywhere).  Stage by stage from the last: the children's sums, lambda_n
+// = a_n + sum lambda_c, the correction Pi B' (sum lambda_c) / (2 w), P_n =
+// local_n + sum P_c - correction.  Writes P_n for its nodes and lambda_n for
+// its first stage.  All of a workgroup's inputs are loaded at once.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TopLds {
+  size_t rg, off, cb, ce, lam, p, sl, t, g, bl, bp, brow, bcol, bval, grow, gcol, gval, erow,
+      ecol, eval, total;
+  __host__ __device__ explicit TopLds(const SegArgs<T>& a) {
+    LdsCursor c;
+    const size_t nw = (size_t)a.top_nodes, nch = (size_t)(a.nch > 0 ? a.nch : 1);
+    rg = c.take(sizeof(int2) * a.nst);
+    off = c.take(sizeof(int) * (a.nst + 1));
+    cb = c.take(sizeof(int) * nw);
+    ce = c.take(sizeof(int) * nw);
+    lam = c.take(sizeof(T) * nw * kSX);
+    p = c.take(sizeof(T) * nw * kSU);
+    sl = c.take(sizeof(T) * nw * kSX);
+    t = c.take(sizeof(T) * nw * kSU);
+    g = c.take(sizeof(T) * nw * (a.ns > 0 ? a.ns : 1));
+    bl = c.take(sizeof(T) * nch * kSX);
+    bp = c.take(sizeof(T) * nch * kSU);
+    brow = c.take(sizeof(int) * (a.nu + 1));
+    bcol = c.take(sizeof(int) * a.nnzB);
+    bval = c.take(sizeof(T) * a.nnzB);
+    grow = c.take(sizeof(int) * (a.ns + 1));
+    gcol = c.take(sizeof(int) * a.nnzG);
+    gval = c.take(sizeof(T) * a.nnzG);
+    erow = c.take(sizeof(int) * (a.nu + 1));
+    ecol = c.take(sizeof(int) * a.nnzE);
+    eval = c.take(sizeof(T) * a.nnzE);
+    total = c.off;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kSegThreads) void scan_top_kernel(SegArgs<T> a) {
+  if (a.ctl[0].done) return;
+  const int tid = threadIdx.x, wg = blockIdx.x;
+  const int nx = a.nx, nu = a.nu, LDX = a.LDX, ns = a.ns, nst = a.nst;
+  const int sb = a.s_begin, se = a.s_end;
+  const T hw = T(0.5) * a.winv;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TopLds<T> L(a);
+  int2* sRg = reinterpret_cast<int2*>(smem_raw + L.rg);
+  int* sOff = reinterpret_cast<int*>(smem_raw + L.off);
+  int* sCb = reinterpret_cast<int*>(smem_raw + L.cb);
+  int* sCe = reinterpret_cast<int*>(smem_raw + L.ce);
+  T* sL = reinterpret_cast<T*>(smem_raw + L.lam);   // [nw][kSX]: a, then lambda
+  T* sP = reinterpret_cast<T*>(smem_raw + L.p);     // [nw][kSU]: local part, then P
+  T* sS = reinterpret_cast<T*>(smem_raw + L.sl);    // [nw][kSX]: sum of children's lambda
+  T* sT = reinterpret_cast<T*>(smem_raw + L.t);     // [nw][kSU]: B' sum
+  T* sG = reinterpret_cast<T*>(smem_raw + L.g);     // [nw][ns]: G B' sum
+  T* sBL = reinterpret_cast<T*>(smem_raw + L.bl);   // [nch][kSX]: lambda of the level below
+  T* sBP = reinterpret_cast<T*>(smem_raw + L.bp);   // [nch][kSU]: P of the level below
+  int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);
+  int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
+  T* sVal = reinterpret_cast<T*>(smem_raw + L.bval);
+  int* gRow = reinterpret_cast<int*>(smem_raw + L.grow);
+  int* gCol = reinterpret_cast<int*>(smem_raw + L.gcol);
+  T* gVal = reinterpret_cast<T*>(smem_raw + L.gval);
+  int* eRow = reinterpret_cast<int*>(smem_raw + L.erow);
+  int* eCol = reinterpret_cast<int*>(smem_raw + L.ecol);
+  T* eVal = reinterpret_cast<T*>(smem_raw + L.eval);
+  const bool kids_below = se + 1 < a.N;
+  int cb = 0, ce = 0;
+  if (kids_below) {
+    const int2 kc = a.wgx[2 * wg];
+    cb = kc.x;
+    ce = kc.y;
+  }
+  for (int i = tid; i < nst; i += kSegThreads) sRg[i] = a.ranges[(size_t)wg * nst + i];
+  csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
+  csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, ns, a.nnzG, gRow, gCol, gVal);
+  csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
+  // the children of the last stage, from the level below
+  const int nchl = ce - cb;
+  for (int e = tid; e < nchl * kSX; e += kSegThreads) {
+    const int c = e / kSX, i = e - c * kSX;
+    sBL[e] = i < nx ? a.lam[(size_t)(cb + c) * LDX + i] : T(0);
+  }
+  for (int e = tid; e < nchl * kSU; e += kSegThreads) {
+    const int c = e / kSU, i = e - c * kSU;
+    sBP[e] = i < nu ? a.jv[(size_t)(cb + c) * kSU + i] : T(0);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int o = 0;
+    for (int q = 0; q < nst; ++q) {
+      sOff[q] = o;
+      o += sRg[q].y - sRg[q].x;
+    }
+    sOff[nst] = o;
+  }
+  __syncthreads();
+  const int nw = sOff[nst];
+  auto node_of = [&](int k) {  // local index -> (stage index, node)
+    int q = 0;
+    while (q + 1 < nst && sOff[q + 1] <= k) ++q;
+    return make_int2(q, sRg[q].x + (k - sOff[q]));
+  };
+  for (int e = tid; e < nw * kSX; e += kSegThreads) {
+    const int k = e / kSX, i = e - k * kSX;
+    const int n = node_of(k).y;
+    sL[e] = i < nx ? a.lam[(size_t)n * LDX + i] : T(0);
+  }
+  for (int e = tid; e < nw * kSU; e += kSegThreads) {
+    const int k = e / kSU, i = e - k * kSU;
+    const int n = node_of(k).y;
+    sP[e] = i < nu ? a.jv[(size_t)n * kSU + i] : T(0);
+  }
+  for (int k = tid; k < nw; k += kSegThreads) {
+    const int n = node_of(k).y;
+    sCb[k] = a.cbeg[n];
+    sCe[k] = a.cend[n];
+  }
+  __syncthreads();
+  for (int q = nst - 1; q >= 0; --q) {
+    const int k0 = sOff[q], kw = sOff[q + 1] - k0;
+    const bool last = q == nst - 1;
+    const int cfirst = last ? cb : sRg[q + 1].x;  // first child of the stage below
+    const int cbase = last ? 0 : sOff[q + 1];     // its local index
+    const T* CL = last ? sBL : sL;
+    const T* CP = last ? sBP : sP;
+    // children's sums: lambda_n = a_n + sum, P_n = local_n + sum
+    for (int e = tid; e < kw * kSX; e += kSegThreads) {
+      const int k = k0 + e / kSX, i = e % kSX;
+      T acc = T(0);
+      if (!(last && !kids_below))
+        for (int c = sCb[k]; c < sCe[k]; ++c) acc += CL[(cbase + c - cfirst) * kSX + i];
+      sS[k * kSX + i] = acc;
+      sL[k * kSX + i] += acc;
+    }
+    for (int e = tid; e < kw * kSU; e += kSegThreads) {
+      const int k = k0 + e / kSU, i = e % kSU;
+      T acc = T(0);
+      if (!(last && !kids_below))
+        for (int c = sCb[k]; c < sCe[k]; ++c) acc += CP[(cbase + c - cfirst) * kSU + i];
+      sP[k * kSU + i] += acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < kw * kSU; e += kSegThreads) {  // B' (sum lambda)
+      const int k = k0 + e / kSU, i = e % kSU;
+      T acc = T(0);
+      if (i < nu)
+        for (int p = sRow[i]; p < sRow[i + 1]; ++p) acc += sVal[p] * sS[k * kSX + sCol[p]];
+      sT[k * kSU + i] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < kw * ns; e += kSegThreads) {  // G B' (sum lambda)
+      const int k = k0 + e / ns, r = e % ns;
+      T acc = T(0);
+      for (int p = gRow[r]; p < gRow[r + 1]; ++p) acc += gVal[p] * sT[k * kSU + gCol[p]];
+      sG[k * ns + r] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < kw * kSU; e += kSegThreads) {  // P_n -= Pi B' (sum lambda) / (2 w)
+      const int k = k0 + e / kSU, i = e % kSU;
+      if (i < nu) {
+        T acc = T(0);
+        for (int p = eRow[i]; p < eRow[i + 1]; ++p) acc += eVal[p] * sG[k * ns + eCol[p]];
+        sP[k * kSU + i] -= hw * (sT[k * kSU + i] - acc);
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nw * kSU; e += kSegThreads) {
+    const int k = e / kSU, i = e - k * kSU;
+    if (i < nu) a.jv[(size_t)node_of(k).y * kSU + i] = sP[e];
+  }
+  if (sb > 0)  // the level above reads the first stage's lambda
+    for (int e = tid; e < sOff[1] * kSX; e += kSegThreads) {
+      const int k = e / kSX, i = e - k * kSX;
+      if (i < nx) a.lam[(size_t)(sRg[0].x + k) * LDX + i] = sL[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Forward sweep of workgroup `wg` (tree `tree`) over its level, stages
 // s_begin up to s_end, in iteration `it`, with the fused prox / dual update
 // (as in the segment form).  Returns the workgroup's max |y+ - w| / gamma
@@ -891,6 +1148,12 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
 
 template <typename T, int NB>
 __global__ __launch_bounds__(kSegThreads) void scan_bwd_kernel(SegArgs<T> a) {
+  if (a.n_main > 0 && (int)blockIdx.x >= a.n_main) {  // light upper levels' local parts
+    const DevCtl c = a.close ? bwd_ctl_peek(a) : a.ctl[0];
+    if (c.done) return;
+    scan_local_body<T>(a, blockIdx.x - a.n_main, c.iter, (T)c.beta, (T)c.pw_scale);
+    return;
+  }
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
   const DevCtl c = bwd_ctl(a, tree);
   if (c.done) return;
@@ -933,6 +1196,16 @@ void launch_scan(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t s
 }
 
 template <typename T>
+size_t scan_top_lds(const SegArgs<T>& a) {
+  return (TopLds<T>(a).total + 15) & ~(size_t)15;
+}
+
+template <typename T>
+void launch_scan_top(const SegArgs<T>& a, int n_wg, hipStream_t st) {
+  hipLaunchKernelGGL((scan_top_kernel<T>), dim3(n_wg), dim3(kSegThreads), scan_top_lds<T>(a), st, a);
+}
+
+template <typename T>
 size_t scan_lds(int, const SegArgs<T>& a) {
   const size_t f = scan_lds_bytes<T>(a, true), b = scan_lds_bytes<T>(a, false);
   return f > b ? f : b;
@@ -942,5 +1215,9 @@ template void launch_scan<double>(bool, int, const SegArgs<double>&, int, hipStr
 template void launch_scan<float>(bool, int, const SegArgs<float>&, int, hipStream_t);
 template size_t scan_lds<double>(int, const SegArgs<double>&);
 template size_t scan_lds<float>(int, const SegArgs<float>&);
+template void launch_scan_top<double>(const SegArgs<double>&, int, hipStream_t);
+template void launch_scan_top<float>(const SegArgs<float>&, int, hipStream_t);
+template size_t scan_top_lds<double>(const SegArgs<double>&);
+template size_t scan_top_lds<float>(const SegArgs<float>&);
 
 }  // namespace tapg

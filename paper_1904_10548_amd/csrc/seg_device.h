@@ -28,6 +28,16 @@ __device__ inline DevCtl bwd_ctl(const SegArgs<T>& a, int tree) {
   return n;
 }
 
+// The state of a single tree's first backward launch as every workgroup
+// advances it (bwd_ctl without the write: for workgroups that are not the
+// tree's first).
+template <typename T>
+__device__ inline DevCtl bwd_ctl_peek(const SegArgs<T>& a) {
+  bool record;
+  double res = 0.0;
+  return ctl_advance(a.ctl_prev[0], &record, &res);
+}
+
 template <typename T>
 __device__ __forceinline__ T wext(T y, T yp, T beta) {
   return y + beta * (y - yp);

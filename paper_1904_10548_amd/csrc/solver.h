@@ -74,6 +74,7 @@ struct tapg_solver_s {
   std::map<std::string, std::vector<tapg::LevelPlan>> tuned;  // autotuned schedule per tree shape
   std::map<std::string, bool> tuned_scan;  // autotuned sweep form per tree shape
   std::map<std::string, int> tuned_fwd;    // autotuned forward grouping (scan form)
+  std::map<std::string, bool> tuned_top;   // autotuned light upper levels (scan form, one tree)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool use_graph = true;
   // structure of the network and weights (detected at creation)

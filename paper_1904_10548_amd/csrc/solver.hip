@@ -412,8 +412,21 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
           a.part_total = L.n_wg;
         }
         a.close = (close && mode == 0 && pass == 0 && q == 0) ? 1 : 0;
+        const bool light = sl.top_light && pass == 0;
+        a.n_main = 0;
+        a.loc_count = 0;
+        a.top_nodes = 0;
         if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
-        launch_seg<T>(pass == 1, L.nbm, a, L.n_wg, st);
+        if (light && l == nl - 1) {  // bottom level and the upper nodes' local parts
+          a.n_main = L.n_wg;
+          a.loc_count = sl.loc_count;
+          launch_seg<T>(false, L.nbm, a, L.n_wg + sl.n_loc, st);
+        } else if (light) {
+          a.top_nodes = L.nw;
+          launch_scan_top<T>(a, L.n_wg, st);
+        } else {
+          launch_seg<T>(pass == 1, L.nbm, a, L.n_wg, st);
+        }
         if (tc) {
           (void)hipEventRecord(S->tev[2 * tc->next + 1], st);
           tc->kind.push_back(pass);
@@ -1619,6 +1632,69 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
   sl.fwd_full = L;
 }
 
+template <typename T>
+size_t top_lds_probe(tapg_solver_s* S, int nst, int nw, int nch) {
+  SegArgs<T> probe{};
+  probe.nst = nst;
+  probe.top_nodes = nw;
+  probe.nch = nch;
+  probe.nu = S->net.nu;
+  probe.ns = S->net.ns;
+  probe.nnzB = S->nnzB;
+  probe.nnzG = S->nnzG;
+  probe.nnzE = S->nnzE;
+  return scan_top_lds<T>(probe);
+}
+
+// Light upper levels, where they apply (scan form, one tree, two levels or
+// more, and each upper level's workgroup inputs fit the LDS): per upper level
+// the most nodes one workgroup holds; the nodes above the bottom level and the
+// workgroups that compute their local parts.  Otherwise the slot runs every
+// level with the full kernel.
+void setup_top_light(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
+  sl.n_loc = sl.loc_count = 0;
+  const int nl = (int)sl.levels.size();
+  // a plan whose upper levels are wider than the full kernels take needs them
+  auto wide = [&] {
+    for (int l = 0; l + 1 < nl; ++l)
+      if (sl.levels[l].nbm > kSegNbMax) return true;
+    return false;
+  };
+  auto refuse = [&](const char* why) {
+    sl.top_light = false;
+    if (wide())
+      throw Fail{TAPG_EINVAL, std::string("schedule: upper levels wider than ") +
+                                  std::to_string(kSegNbMax) + " nodes per stage need light "
+                                  "upper levels, which do not apply here (" + why + ")"};
+  };
+  if (!sl.top_light || !sl.scan || t.ntrees != 1 || nl < 2) {
+    refuse("scan form, one tree, two levels or more");
+    return;
+  }
+  for (int l = 0; l + 1 < nl; ++l) {
+    Slot::Level& L = sl.levels[l];
+    const LevelPlan& P = sl.plans[l];
+    int wmax = 0;
+    const std::vector<std::pair<int, int>> rp = level_ranges(t, P, wmax);
+    const int nst = P.s_end - P.s_begin + 1;
+    int nw = 0;
+    for (int w = 0; w < P.n_wg; ++w) {
+      int c = 0;
+      for (int q = 0; q < nst; ++q) c += rp[(size_t)w * nst + q].second - rp[(size_t)w * nst + q].first;
+      nw = std::max(nw, c);
+    }
+    L.nw = nw;
+    const size_t lds = S->fp32 ? top_lds_probe<float>(S, nst, nw, L.nch)
+                               : top_lds_probe<double>(S, nst, nw, L.nch);
+    if (lds > S->lds_limit) {
+      refuse("LDS");
+      return;
+    }
+  }
+  sl.loc_count = t.offset[sl.levels.back().s_begin];
+  sl.n_loc = (sl.loc_count + 3) / 4;
+}
+
 // (Re)build the level launches of a slot from a plan.
 void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vector<LevelPlan>& plans) {
   hipStream_t st = S->stream;
@@ -1631,7 +1707,10 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
       std::vector<std::pair<int, int>> rp = level_ranges(t, P, wmax);
       std::vector<int2> rg(rp.size());
       for (size_t k = 0; k < rp.size(); ++k) rg[k] = make_int2(rp[k].first, rp[k].second);
-      if (wmax > nbmax)
+      // (light upper levels hold any number: their kernel takes a stage's
+      // nodes one after another; setup_top_light checks that they apply)
+      const bool upper_light = sl.top_light && sl.scan && &P != &plans.back();
+      if (wmax > nbmax && !upper_light)
         throw Fail{TAPG_EINVAL, "segment schedule: a workgroup would hold more than " +
                                     std::to_string(nbmax) + " nodes of one stage"};
       const int nst = P.s_end - P.s_begin + 1;
@@ -1679,6 +1758,7 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
   }
   sl.levels = std::move(levels);
   sl.plans = plans;
+  setup_top_light(S, t, sl);
   free_fwd_full(sl);
   if (sl.scan)
     build_fwd_full(S, t, sl, sl.fwd_group > 0 ? stage_plan(t, t.N - 1, sl.fwd_group) : plans.back());
@@ -1706,6 +1786,9 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       if (sl.fwd_group != 0 && sl.fwd_group != 1 && sl.fwd_group != 2 && sl.fwd_group != 4)
         throw Fail{TAPG_EINVAL, "TAPG_FWD_GROUP must be 0, 1, 2 or 4 (got " +
                                     std::to_string(sl.fwd_group) + ")"};
+      auto tt = S->tuned_top.find(shape_key(t));
+      const char* te = std::getenv("TAPG_TOP");
+      sl.top_light = (te && te[0]) ? te[0] == '1' : (tt != S->tuned_top.end() && tt->second);
     }
     sl.N = t.N;
     sl.elem = S->fp32 ? sizeof(float) : sizeof(double);
@@ -2318,6 +2401,10 @@ double time_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters) {
 template <typename T>
 double autotune_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters, int* ncand) {
   std::vector<std::vector<LevelPlan>> cands = candidate_plans(t, kSegNbMax, seg_node_us(S));
+  const char* te = std::getenv("TAPG_TOP");
+  const bool top_forced = te && te[0];
+  const bool top_env = top_forced && te[0] == '1';
+  sl.top_light = top_env;
   // both sweep forms where the scan form applies: it wins on narrow trees
   // (fewer launches, shorter chains), the segment form on wide forests (two
   // workgroups per compute unit against one)
@@ -2357,10 +2444,29 @@ double autotune_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters, i
     }
   }
   sl.fwd_group = bfg;
+  // light upper levels (scan form, one tree): they change what the levels
+  // above the bottom one cost, so every plan is timed again with them
+  bool btop = top_env;
+  if (bscan && t.ntrees == 1 && !top_forced) {
+    for (size_t i = 0; i < cands.size(); ++i) {
+      sl.top_light = true;
+      build_levels(S, t, sl, cands[i]);
+      if (!sl.top_light) continue;  // does not apply to this plan
+      const double ms = time_levels<T>(S, t, sl, iters);
+      if (ncand) ++*ncand;
+      if (ms < best) {
+        best = ms;
+        bi = i;
+        btop = true;
+      }
+    }
+  }
+  sl.top_light = btop;
   build_levels(S, t, sl, cands[bi]);
   S->tuned[shape_key(t)] = cands[bi];
   S->tuned_scan[shape_key(t)] = bscan;
   S->tuned_fwd[shape_key(t)] = bfg;
+  if (!top_forced) S->tuned_top[shape_key(t)] = sl.top_light;
   sl.has_dual = false;  // the timing runs overwrote the iterates
   sl.has_result = false;
   return best;

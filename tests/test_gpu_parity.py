@@ -514,3 +514,65 @@ def test_fp32_sweeps_residual_is_fp64(scan):
     say("fp32 residual", res.primal_res, "oracle", ref.res_hist[0], "gamma", gamma)
     assert res.iters == 1
     assert abs(res.primal_res - ref.res_hist[0]) <= 1e-4 * max(1.0, ref.res_hist[0])
+
+
+@pytest.mark.parametrize("levels", [None, "0:1,2:1,4:1,6:1", "0:1,2:2,4:1", "0:1,1:1,3:2,5:2",
+                                    "0:1,2:1,4:1,6:2,15:4"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_light_upper_levels_dwn128(levels, fp32):
+    """Light upper levels (TAPG_TOP=1): the levels above the bottom one sum
+    local parts that the bottom level's launch computed for their nodes; the
+    same iterates as the oracle, element by element (FP64), or its cost to
+    1e-4 (FP32), on several level sets."""
+    P = ds.config_problem("dwn128")
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 1.0 / (1.02 * O.lipschitz_power(P, sf, 60))
+    os.environ["TAPG_TOP"] = "1"
+    try:
+        prec = tapg.TAPG_FP32 if fp32 else tapg.TAPG_FP64
+        st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 40, check_every=13,
+                                                         precision=prec, levels=levels)
+    finally:
+        os.environ.pop("TAPG_TOP", None)
+    if fp32:
+        J = O.primal_cost(P, ref.u, ref.x)
+        assert abs(res.cost - J) <= 1e-4 * max(1.0, abs(J))
+        return
+    _assert_fp64_parity(P, res, u, x, y, hist, ref, 40)
+
+
+@pytest.mark.parametrize("seed,fwd_group", [(12, 0), (12, 1), (5, 0), (5, 1)])
+def test_light_upper_levels_irregular(seed, fwd_group):
+    """Light upper levels on irregular trees (up to 40 children per node,
+    ragged node ranges), with the forward launch on the bottom level's
+    workgroups or on single leaves."""
+    P = tiny_problem(N=7, irregular=True, seed=seed, max_children=40, max_width=3000)
+    sf = O.StageFactors(P.net, P.weights.W_u, P.tree)
+    gamma = 0.9 / O.lipschitz_power(P, sf, 200)
+    os.environ["TAPG_TOP"] = "1"
+    try:
+        st, u0, res, u, x, y, hist, ref = _compare_fixed(P, gamma, 80, check_every=9,
+                                                         fwd_group=fwd_group)
+    finally:
+        os.environ.pop("TAPG_TOP", None)
+    _assert_fp64_parity(P, res, u, x, y, hist, ref, 80)
+
+
+
+def test_light_upper_levels_power_iteration():
+    """The power iteration (the linear part of the dual gradient, no data)
+    also runs on light upper levels: the same Lipschitz estimate as with the
+    full kernels, from the same start and number of steps."""
+    P = ds.config_problem("dwn128")
+    out = {}
+    for top in ("0", "1"):
+        _schedule_env(scan=True, levels="0:1,2:1,4:1,6:1")
+        os.environ["TAPG_TOP"] = top
+        try:
+            with make_solver(P, gamma=1e-6, tol=0.0, max_iter=1) as S:
+                t = add_tree(S, P)
+                out[top] = tapg.tapg_estimate_lipschitz(S.h, t, 60)
+        finally:
+            os.environ.pop("TAPG_TOP", None)
+    say("power", out)
+    assert abs(out["1"] - out["0"]) <= 1e-9 * out["0"]
