@@ -32,6 +32,7 @@ from .generate import (
     config_problem,
 )
 from .closed_loop import LoopInputs, make_loop_inputs
+from .scenarios import make_error_paths
 
 __all__ = [
     "Network",
@@ -50,4 +51,5 @@ __all__ = [
     "config_problem",
     "LoopInputs",
     "make_loop_inputs",
+    "make_error_paths",
 ]

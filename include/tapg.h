@@ -386,6 +386,33 @@ tapg_status tapg_closed_loop(tapg_solver solver, tapg_tree tree, int H_s, const 
                              int warm_start, double* x_traj, double* u_traj, double* tau_ms,
                              int* iters, tapg_loop_stats* stats);
 
+/* Scenario tree from sampled prediction-error paths (Sec. 2.3 and 6.2: the
+ * paper reduces 10^4 Monte-Carlo paths to a tree by the forward scenario
+ * reduction of Heitsch and Roemisch), on the GPU, stage by stage: the root
+ * holds every path; at stage t every node of stage t-1 splits its cluster of
+ * paths by forward selection of min(branching[t], cluster size)
+ * representatives (greedy minimisation of the transport cost
+ * sum_k p_k min_r |x_k - x_r|_2 over the paths' stage-t values; ties go to the
+ * lowest position), each path joining its nearest representative (ties: the
+ * one picked first); each representative becomes a child, in the order
+ * picked, carrying its stage-t value and its members' summed probability.
+ * samples [M*H*d] (path-major, then stage, then component; stage 0 is the
+ * root's, normally zero), prob [M] (NULL: uniform; must add up to 1),
+ * branching [H] (entry 0 ignored; >= 1).  Outputs (capacity cap nodes): the
+ * tree in breadth-first order with contiguous children: nodes_per_stage [H],
+ * ancestor [K] (-1 at the root), node_prob [K], node_value [K*d] (may be
+ * NULL), rep [K] (the path whose value each node carries; may be NULL), *K_out.
+ * All arrays are caller-owned host memory; the call allocates and frees its
+ * own device buffers and returns when the tree is complete.  FP64 throughout.
+ * Errors (outputs then untouched): TAPG_EINVAL (M, H < 1, d outside 1..128,
+ * a NULL required array, cap < 1, a branching entry < 1, probabilities
+ * negative or not adding up to 1), TAPG_ENUMERIC (a non-finite sample),
+ * TAPG_EDIM (more than cap nodes), TAPG_ENOMEM, TAPG_EDEVICE. */
+tapg_status tapg_tree_build(int M, int H, int d, const double* samples, const double* prob,
+                            const int* branching, int device, int cap, int* nodes_per_stage,
+                            int* ancestor, double* node_prob, double* node_value, int* rep,
+                            int* K_out);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* tapg_last_error(void);
 /* Library version string. */

@@ -22,6 +22,7 @@ objective       primal cost, constraint violations, dual objective,
 stepsize        Lipschitz constant of the dual gradient (power iteration and
                 the dense eigenvalue for tiny trees)
 closed_loop     receding-horizon simulation with the paper's performance indices
+tree_build      scenario tree from sampled error paths by forward selection
 
 Every function is pinned by a ``-m "not gpu"`` test against an independent
 fact (closed forms, brute force, a textbook solver); none is "parity
@@ -44,6 +45,7 @@ from .objective import primal_cost, violations, dual_objective, g_conj, g_value,
     split_residual, split_gap
 from .stepsize import lipschitz_power, lipschitz_dense, dual_hessian_dense
 from .closed_loop import LoopResult, closed_loop
+from .tree_build import BuiltTree, build_tree, forward_selection
 
 __all__ = [
     "TreeIndex",
@@ -76,4 +78,7 @@ __all__ = [
     "dual_hessian_dense",
     "LoopResult",
     "closed_loop",
+    "BuiltTree",
+    "build_tree",
+    "forward_selection",
 ]

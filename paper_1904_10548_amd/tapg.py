@@ -42,7 +42,7 @@ EXPORTED = [
     "tapg_set_dual", "tapg_residual_history", "tapg_residuals", "tapg_estimate_lipschitz",
     "tapg_kernel_timing", "tapg_kernel_times", "tapg_plan_schedule", "tapg_autotune", "tapg_sweep_form",
     "tapg_schedule_spec", "tapg_event_pair_overhead",
-    "tapg_solver_forget", "tapg_solve_noalloc", "tapg_noalloc_bytes", "tapg_closed_loop",
+    "tapg_solver_forget", "tapg_solve_noalloc", "tapg_noalloc_bytes", "tapg_closed_loop", "tapg_tree_build",
     "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats", "tapg_server_timing",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
 ]
@@ -163,6 +163,8 @@ def lib() -> ctypes.CDLL:
         "tapg_solve_noalloc": ([_P, _P, _D, _D, _D, _D, _D, ctypes.POINTER(TapgResult)],
                                ctypes.c_int),
         "tapg_noalloc_bytes": ([_P, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "tapg_tree_build": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D, _I, ctypes.c_int,
+                             ctypes.c_int, _I, _I, _D, _D, _I, _I], ctypes.c_int),
         "tapg_closed_loop": ([_P, _P, ctypes.c_int, _D, _D, FORECAST_FN, ctypes.c_void_p,
                               ctypes.c_int, _D, _D, _D, _I, ctypes.POINTER(TapgLoopStats)],
                              ctypes.c_int),
@@ -338,6 +340,34 @@ def tapg_noalloc_bytes(solver, tree) -> int:
     b = ctypes.c_size_t(0)
     _check(lib().tapg_noalloc_bytes(solver, tree, ctypes.byref(b)))
     return b.value
+
+
+def tapg_tree_build(samples, branching, prob=None, device=0, cap=None):
+    """Scenario tree from sample paths ``samples`` (M, H, d) with ``branching``
+    (H,).  Returns a dict: nodes_per_stage, anc, prob, value (K, d), rep."""
+    S = _f64(samples)
+    M, H, d = S.shape
+    br = np.ascontiguousarray(branching, dtype=np.int32)
+    if br.size != H:
+        raise ValueError("branching must have H entries")
+    if cap is None:  # stage t has at most min(M, b_1 ... b_t) nodes
+        cap, width = 1, 1
+        for t in range(1, H):
+            width = min(M, width * max(int(br[t]), 1))
+            cap += width
+    mu = np.zeros(H, dtype=np.int32)
+    anc = np.zeros(cap, dtype=np.int32)
+    pr = np.zeros(cap)
+    val = np.zeros((cap, d))
+    rep = np.zeros(cap, dtype=np.int32)
+    K = ctypes.c_int(0)
+    pp = None if prob is None else _f64(prob, M)
+    _check(lib().tapg_tree_build(M, H, d, _ptr(S), _ptr(pp), br.ctypes.data_as(_I), int(device),
+                                 int(cap), mu.ctypes.data_as(_I), anc.ctypes.data_as(_I), _ptr(pr),
+                                 _ptr(val), rep.ctypes.data_as(_I), ctypes.byref(K)))
+    k = K.value
+    return {"nodes_per_stage": mu, "anc": anc[:k], "prob": pr[:k], "value": val[:k],
+            "rep": rep[:k]}
 
 
 def tapg_closed_loop(solver, tree, H_s, x0, u_prev, forecast, K, nd, warm_start=True):

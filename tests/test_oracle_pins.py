@@ -625,3 +625,74 @@ def test_closed_loop_invariants():
     assert np.array_equal(d0[0], inp.demand[3]) and p0[0] == inp.price[3]
     assert r.kpi_S >= 0.0
     assert np.all(r.iters == 300)
+
+
+# ---------------------------------------------------------------------------
+# Scenario-tree construction (Sec. 2.3, 6.2): forward selection and the tree
+# ---------------------------------------------------------------------------
+def test_forward_selection_each_pick_is_the_best_single_addition():
+    """Every greedy pick minimises, over all unpicked points, the transport
+    cost of the picked set plus that point, each cost summed here by explicit
+    loops over the points; the costs after each pick do not increase."""
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((13, 3))
+    p = rng.uniform(0.5, 1.5, 13)
+    p /= p.sum()
+    chosen, costs = O.forward_selection(x, p, 5)
+
+    def cost(sel):
+        tot = 0.0
+        for k in range(len(x)):
+            best = min(float(np.linalg.norm(x[k] - x[s])) for s in sel)
+            tot += p[k] * best
+        return tot
+
+    for j in range(5):
+        cand = [u for u in range(13) if u not in chosen[:j]]
+        vals = [cost(chosen[:j] + [u]) for u in cand]
+        assert abs(cost(chosen[:j + 1]) - min(vals)) <= 1e-12
+        assert abs(costs[j] - cost(chosen[:j + 1])) <= 1e-12
+    assert all(b <= a + 1e-15 for a, b in zip(costs, costs[1:]))
+
+
+def test_tree_build_structure_and_probabilities():
+    """Built trees: breadth-first with contiguous children, every node's
+    children's probabilities add up to its own, every member path in exactly
+    one node per stage, node values the representatives' stage values, and
+    the children of a node at most its branching; with branching at least the
+    number of paths the tree is the fan of the paths themselves."""
+    paths = ds.make_error_paths(60, 5, 3, seed=4)
+    prob = np.full(60, 1.0 / 60)
+    T = O.build_tree(paths, prob, [1, 3, 2, 2, 1])
+    off = np.concatenate([[0], np.cumsum(T.nodes_per_stage)])
+    assert T.anc[0] == -1 and np.all(np.diff(T.anc[1:]) >= 0)
+    for s in range(1, 5):
+        nodes = range(off[s], off[s + 1])
+        members = np.sort(np.concatenate([T.members[n] for n in nodes]))
+        assert np.array_equal(members, np.arange(60))
+        for v in range(off[s - 1], off[s]):
+            kids = [n for n in nodes if T.anc[n] == v]
+            assert abs(sum(T.prob[n] for n in kids) - T.prob[v]) <= 1e-14
+            assert len(kids) <= [1, 3, 2, 2, 1][s]
+        for n in nodes:
+            assert np.array_equal(T.value[n], paths[T.rep[n], s])
+            assert T.rep[n] in T.members[n]
+    assert list(T.nodes_per_stage) == [1, 3, 6, 12, 12]
+    F = O.build_tree(paths[:7], np.full(7, 1 / 7), [1, 7, 7, 7, 7])
+    assert list(F.nodes_per_stage) == [1, 7, 7, 7, 7]
+    leaves = range(F.nodes_per_stage[:-1].sum(), F.nodes_per_stage.sum())
+    assert sorted(int(F.rep[n]) for n in leaves) == list(range(7))
+    assert np.allclose(F.prob[1:], 1 / 7)
+
+
+def test_tree_build_merges_identical_paths():
+    """Duplicated paths end in one node whose probability is their sum."""
+    base = ds.make_error_paths(5, 4, 2, seed=9)
+    paths = np.concatenate([base, base[:2]], axis=0)  # paths 5, 6 repeat 0, 1
+    prob = np.full(7, 1.0 / 7)
+    T = O.build_tree(paths, prob, [1, 5, 1, 1])
+    last = range(T.nodes_per_stage[:-1].sum(), T.nodes_per_stage.sum())
+    assert len(last) == 5
+    for n in last:
+        if 0 in T.members[n]:
+            assert 5 in T.members[n] and abs(T.prob[n] - 2 / 7) <= 1e-15
