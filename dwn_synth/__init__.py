@@ -16,7 +16,7 @@ Data containers follow the paper's notation:
   breadth-first node numbering with contiguous children, ancestor index and
   node probability ``p``;
 * per-node demand ``d`` and electricity price (Sec. 2.2/2.3);
-* weights ``W_alpha, W_u, W_s, W_x`` (Sec. 4.1).
+* weights ``W_alpha, W_u, W_s, W_x`` (Sec. 3.1).
 """
 
 from .problem import Network, ScenarioTree, NodeData, Weights, Problem
@@ -33,6 +33,7 @@ from .generate import (
 )
 from .closed_loop import LoopInputs, make_loop_inputs
 from .scenarios import make_error_paths
+from . import json_files
 
 __all__ = [
     "Network",

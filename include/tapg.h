@@ -123,6 +123,7 @@ tapg_status tapg_network_create(int nx, int nu, int nd, int ns, const double* A,
                                 const double* xs, const double* umin, const double* umax,
                                 tapg_network* out);
 void tapg_network_destroy(tapg_network net);
+tapg_status tapg_network_dims(tapg_network net, int* nx, int* nu, int* nd, int* ns);
 
 /* Scenario tree (the paper's ScenarioTree, Sec. 2.3 and 5.1).
  * nodes_per_stage [N] (mu_0 = 1), ancestor [K] (ancestor[0] = -1), prob [K]
@@ -138,6 +139,9 @@ tapg_status tapg_tree_create(int N, const int* nodes_per_stage, const int* ances
 tapg_status tapg_tree_set_data(tapg_tree tree, const double* demand, const double* price);
 /* K of a tree (number of nodes), or -1 for a null handle. */
 int tapg_tree_num_nodes(tapg_tree tree);
+/* Sizes of a tree (stages N, nodes K, demands per node nd) and of a network;
+ * any output pointer may be NULL.  TAPG_EINVAL for a NULL handle. */
+tapg_status tapg_tree_dims(tapg_tree tree, int* N, int* K, int* nd);
 void tapg_tree_destroy(tapg_tree tree);
 
 /* Solver bound to one network and one device (the paper's SmpcController with
@@ -412,6 +416,76 @@ tapg_status tapg_tree_build(int M, int H, int d, const double* samples, const do
                             const int* branching, int device, int cap, int* nodes_per_stage,
                             int* ancestor, double* node_prob, double* node_value, int* rep,
                             int* K_out);
+
+/* ------------------------------------------------------------------------
+ * JSON front-end (Sec. 5.1: the network, the scenario tree, the forecaster,
+ * the controller configuration and the control output live in JSON files;
+ * the plant state x_k may too).  The paper names the files, not their
+ * fields; the formats below are this library's.  Each file holds one JSON
+ * object; matrices are arrays of rows; every number must be finite; keys not
+ * listed are errors (a misspelt key is never ignored), except "name" and
+ * "description", which every file may carry.  Errors: TAPG_EINVAL (file not
+ * readable, syntax error with line:column, unknown or missing key, wrong
+ * type), TAPG_EDIM (shapes), TAPG_ENUMERIC (a non-finite number), and the
+ * errors of the array entry point each reader ends in.
+ * ------------------------------------------------------------------------ */
+
+/* network.json (the paper's DwnNetwork):
+ *   {"A": nx x nx, "B": nx x nu, "Gd": nx x nd, "E": ns x nu, "Ed": ns x nd,
+ *    "xmin", "xmax", "xs": [nx], "umin", "umax": [nu],
+ *    optional "nx", "nu", "nd", "ns" (checked against the matrices)}
+ * ns = 0 is "E": [], "Ed": [].  Validated like tapg_network_create. */
+tapg_status tapg_network_from_json(const char* path, tapg_network* out);
+
+/* scenarioTree.json (the paper's ScenarioTree):
+ *   {"nodes_per_stage": [N], "ancestor": [K] (-1 at the root),
+ *    "probability": [K], optional "N", optional "children" (one list per node
+ *    or per non-leaf node, checked against "ancestor"), and the node data as
+ *    either  "demand": K x nd, "price": [K]  (node values; no forecaster) or
+ *    "demand_error": K x nd, "price_error": [K]  (prediction errors of
+ *    Sec. 2.2, eq. prediction-error; zero at the root), then with
+ * forecaster.json (the paper's Forecaster output):
+ *   {"demand": N x nd, "price": [N]}  (nominal forecasts per stage; stage 0
+ *    is the current instant), a node's data being forecast + error at its
+ *    stage.  forecaster_path is NULL for a tree of node values.  Validated like
+ *    tapg_tree_create. */
+tapg_status tapg_tree_from_json(const char* tree_path, const char* forecaster_path,
+                                tapg_tree* out);
+/* The node data that tapg_tree_from_json would build, into caller arrays
+ * demand [K*nd] and price [K] (for tapg_tree_set_data in a receding-horizon
+ * loop with a new forecaster file per step).  TAPG_EDIM unless the tree file
+ * has K nodes and nd demands. */
+tapg_status tapg_tree_data_from_json(const char* tree_path, const char* forecaster_path, int K,
+                                     int nd, double* demand, double* price);
+
+/* controllerconfig.json (the paper's SmpcConfiguration):
+ *   {"W_alpha", "W_s", "W_x": numbers, "alpha0", "c_energy": [nu],
+ *    "W_u": nu x nu or a number w (meaning w I), "tol": number,
+ *    "max_iter": integer, optional "gamma" (0: automatic), "check_every" (100),
+ *    "precision" ("fp64" | "fp32"), "power_iters" (100), "device" (0),
+ *    "beta_rule" ("paper" | "simple" | "zero"), "averaged_primal" (false),
+ *    "gap_tol" (0)}
+ * Fills *cfg (hip_stream NULL); its alpha0, c_energy and W_u point to the
+ * caller's arrays alpha0 [nu], c_energy [nu] and W_u [nu*nu], which this
+ * call fills and which must outlive the config.  Values are range-checked by
+ * tapg_solver_create. */
+tapg_status tapg_config_from_json(const char* path, int nu, tapg_config* cfg, double* alpha0,
+                                  double* c_energy, double* W_u);
+
+/* Plant state file: {"x": [nx] (x_k), "u_prev": [nu] (u_{k-1}), optional "k"}
+ * into caller arrays x [nx] and u_prev [nu]. */
+tapg_status tapg_state_from_json(const char* path, int nx, int nu, double* x, double* u_prev);
+
+/* controlOutput.json (the paper's SmpcController output): writes
+ *   {"status": "ok" | "not_converged" | ..., "u": [nu] (the control action
+ *    u_0 to apply), "iters", "converged", "primal_res", "cost", "viol_box",
+ *    "viol_eq", "gamma", "solve_ms", "dual_gap", "dual_obj"}
+ * from a solve's root input u0 [nu], its result and its status.  Doubles are
+ * written with 17 significant digits (they read back exactly); NaN and
+ * infinities as null.  The file is written under path + ".tmp" and renamed,
+ * so a reader never sees half a file. */
+tapg_status tapg_control_output_write(const char* path, int nu, const double* u0,
+                                      const tapg_result* res, tapg_status solve_status);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* tapg_last_error(void);

@@ -2,7 +2,9 @@
 
 ``python -m paper_1904_10548_amd.build`` compiles ``csrc/*.cpp`` and
 ``csrc/*.hip`` with hipcc (one object per source, in parallel, under
-``_build/``) and links them into ``paper_1904_10548_amd/libtapg.so``.
+``_build/``) and links them into ``paper_1904_10548_amd/libtapg.so``, then
+builds the command-line front-end ``paper_1904_10548_amd/tapg_control`` from
+``csrc/app/`` against that library.
 """
 
 from __future__ import annotations
@@ -17,6 +19,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtapg.so")
+CLI = os.path.join(PKG, "tapg_control")
 OBJ_DIR = os.path.join(ROOT, "_build", "tapg")
 
 # Packed FP32 instructions are disabled for all device code (the compiler is
@@ -67,7 +70,23 @@ def build(verbose: bool = False) -> str:
     if proc.returncode != 0:
         raise RuntimeError(f"link failed ({proc.returncode}):\n{_filter(proc.stderr)}")
     os.replace(tmp, LIB)
+    _build_cli(verbose)
     return LIB
+
+
+def _build_cli(verbose: bool) -> str:
+    """The front-end executable: host code only, linked to libtapg.so next to it."""
+    src = os.path.join(PKG, "csrc", "app", "tapg_control.cpp")
+    tmp = CLI + ".tmp"
+    cmd = [_hipcc(), "-O2", "-std=c++17", "-x", "c++", "-I", os.path.join(ROOT, "include"), src,
+           "-x", "none", "-L", PKG, "-l:libtapg.so", "-Wl,-rpath,$ORIGIN", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"tapg_control build failed ({proc.returncode}):\n{_filter(proc.stderr)}")
+    os.replace(tmp, CLI)
+    return CLI
 
 
 if __name__ == "__main__":

@@ -280,6 +280,27 @@ tapg_status tapg_tree_set_data(tapg_tree tree, const double* demand, const doubl
 
 int tapg_tree_num_nodes(tapg_tree tree) { return tree ? tree->h.K : -1; }
 
+tapg_status tapg_tree_dims(tapg_tree tree, int* N, int* K, int* nd) {
+  return guarded([&]() -> tapg_status {
+    need(tree, "tree");
+    if (N) *N = tree->h.N;
+    if (K) *K = tree->h.K;
+    if (nd) *nd = tree->h.nd;
+    return TAPG_OK;
+  });
+}
+
+tapg_status tapg_network_dims(tapg_network net, int* nx, int* nu, int* nd, int* ns) {
+  return guarded([&]() -> tapg_status {
+    need(net, "net");
+    if (nx) *nx = net->h.nx;
+    if (nu) *nu = net->h.nu;
+    if (nd) *nd = net->h.nd;
+    if (ns) *ns = net->h.ns;
+    return TAPG_OK;
+  });
+}
+
 void tapg_tree_destroy(tapg_tree tree) { delete tree; }
 
 tapg_status tapg_solver_create(tapg_network net, const tapg_config* cfg, tapg_solver* out) {

@@ -45,6 +45,9 @@ EXPORTED = [
     "tapg_solver_forget", "tapg_solve_noalloc", "tapg_noalloc_bytes", "tapg_closed_loop", "tapg_tree_build",
     "tapg_server_create", "tapg_server_submit", "tapg_server_poll", "tapg_server_stats", "tapg_server_timing",
     "tapg_server_destroy", "tapg_last_error", "tapg_version",
+    "tapg_tree_dims", "tapg_network_dims", "tapg_network_from_json", "tapg_tree_from_json",
+    "tapg_tree_data_from_json", "tapg_config_from_json", "tapg_state_from_json",
+    "tapg_control_output_write",
 ]
 
 
@@ -181,6 +184,19 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_int),
         "tapg_kernel_timing": ([_P, ctypes.c_int], ctypes.c_int),
         "tapg_kernel_times": ([_P, _D, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+        "tapg_tree_dims": ([_P, _I, _I, _I], ctypes.c_int),
+        "tapg_network_dims": ([_P, _I, _I, _I, _I], ctypes.c_int),
+        "tapg_network_from_json": ([ctypes.c_char_p, ctypes.POINTER(_P)], ctypes.c_int),
+        "tapg_tree_from_json": ([ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_P)],
+                                ctypes.c_int),
+        "tapg_tree_data_from_json": ([ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int,
+                                      ctypes.c_int, _D, _D], ctypes.c_int),
+        "tapg_config_from_json": ([ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(TapgConfig), _D,
+                                   _D, _D], ctypes.c_int),
+        "tapg_state_from_json": ([ctypes.c_char_p, ctypes.c_int, ctypes.c_int, _D, _D],
+                                 ctypes.c_int),
+        "tapg_control_output_write": ([ctypes.c_char_p, ctypes.c_int, _D,
+                                       ctypes.POINTER(TapgResult), ctypes.c_int], ctypes.c_int),
         "tapg_last_error": ([], ctypes.c_char_p),
         "tapg_version": ([], ctypes.c_char_p),
     }
@@ -268,6 +284,65 @@ def tapg_tree_num_nodes(tree) -> int:
 
 def tapg_tree_destroy(h):
     lib().tapg_tree_destroy(h)
+
+
+def tapg_tree_dims(tree):
+    """(N, K, nd) of a tree."""
+    v = [ctypes.c_int(0) for _ in range(3)]
+    _check(lib().tapg_tree_dims(tree, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def tapg_network_dims(net):
+    """(nx, nu, nd, ns) of a network."""
+    v = [ctypes.c_int(0) for _ in range(4)]
+    _check(lib().tapg_network_dims(net, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def _path(p):
+    return None if p is None else os.fsencode(p)
+
+
+def tapg_network_from_json(path):
+    out = _P()
+    _check(lib().tapg_network_from_json(_path(path), ctypes.byref(out)))
+    return out
+
+
+def tapg_tree_from_json(tree_path, forecaster_path=None):
+    out = _P()
+    _check(lib().tapg_tree_from_json(_path(tree_path), _path(forecaster_path), ctypes.byref(out)))
+    return out
+
+
+def tapg_tree_data_from_json(tree_path, forecaster_path, K, nd):
+    """(demand [K, nd], price [K]) as the tree built from these files holds."""
+    dem, pr = np.zeros((K, nd)), np.zeros(K)
+    _check(lib().tapg_tree_data_from_json(_path(tree_path), _path(forecaster_path), int(K),
+                                          int(nd), _ptr(dem), _ptr(pr)))
+    return dem, pr
+
+
+def tapg_config_from_json(path, nu):
+    """A :class:`TapgConfig` plus the arrays it points to (keep both alive)."""
+    keep = [np.zeros(nu), np.zeros(nu), np.zeros(nu * nu)]
+    cfg = TapgConfig()
+    _check(lib().tapg_config_from_json(_path(path), int(nu), ctypes.byref(cfg), _ptr(keep[0]),
+                                       _ptr(keep[1]), _ptr(keep[2])))
+    return cfg, keep
+
+
+def tapg_state_from_json(path, nx, nu):
+    x, u = np.zeros(nx), np.zeros(nu)
+    _check(lib().tapg_state_from_json(_path(path), int(nx), int(nu), _ptr(x), _ptr(u)))
+    return x, u
+
+
+def tapg_control_output_write(path, u0, result, status=TAPG_OK):
+    u = _f64(u0)
+    _check(lib().tapg_control_output_write(_path(path), u.size, _ptr(u), ctypes.byref(result),
+                                           int(status)))
 
 
 def make_config(nu, W_alpha, W_s, W_x, alpha0, c_energy, W_u, gamma=0.0, tol=1e-4,
