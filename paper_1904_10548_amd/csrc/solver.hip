@@ -1480,30 +1480,6 @@ void dev_upload_factors(tapg_solver_s* S) {
               (T)src[(size_t)s * nu * nu + (size_t)r * nu + k];
     return out;
   };
-  // factor ids: stage s shares the block of stage s+1's representative when
-  // the two Fbar agree to 16 ulp of the representative's largest entry
-  S->fid.assign(N, 0);
-  S->n_factor_blocks = N > 0 ? 1 : 0;
-  for (int s = N - 1; s >= 0; --s) {
-    if (s == N - 1) {
-      S->fid[s] = s;
-      continue;
-    }
-    const int rep = S->fid[s + 1];
-    const double* Fr = S->Fbar.data() + (size_t)rep * nu * nu;
-    const double* Fs = S->Fbar.data() + (size_t)s * nu * nu;
-    double mx = 0.0, d = 0.0;
-    for (size_t i = 0; i < (size_t)nu * nu; ++i) {
-      mx = std::max(mx, std::fabs(Fr[i]));
-      d = std::max(d, std::fabs(Fs[i] - Fr[i]));
-    }
-    if (d <= 16.0 * 2.220446049250313e-16 * mx) {
-      S->fid[s] = rep;
-    } else {
-      S->fid[s] = s;
-      S->n_factor_blocks++;
-    }
-  }
   dfree(S->d_fid);
   S->d_fid = upload(S->fid, st);
   dfree(S->d64.F); dfree(S->d64.Kb); dfree(S->dx.Gbar);
