@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's schedule and the default sweep form (profiling runs)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests/s")
+    ap.add_argument("--rates", default="", help="serve: comma-separated offered rates (load curve)")
     ap.add_argument("--requests", type=int, default=400, help="serve: timed requests")
     ap.add_argument("--sessions", type=int, default=32, help="serve: sessions (one tree each)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: trees in flight")
@@ -475,7 +476,9 @@ def main_serve(args, ds, tapg):
     started when its session's previous request solved the same tree, and is
     admitted into the running set by HBM budget (continuous batching).
     Value: requests completed per second over the timed requests; latency is
-    submit to completion."""
+    submit to completion.  With --rates r1,r2,... the same server is driven at
+    each offered rate in turn (a load curve); the line's value is the last
+    rate's."""
     import threading
     n_sess = args.sessions
     sess = [ds.config_problem("serve", i) for i in range(n_sess)]
@@ -490,100 +493,121 @@ def main_serve(args, ds, tapg):
                     check_every=args.check_every, precision=prec)
     trees = [S.add_tree(P.tree.nodes_per_stage, P.tree.anc, P.tree.prob, P.data.demand,
                         P.data.price) for P in sess]
+    K_of = [int(P.tree.K) for P in sess]
     t0 = time.perf_counter()
     for t in trees:
         tapg.tapg_estimate_lipschitz(S.h, t, 100)
-    print(f"[bench] serve: {n_sess} sessions, K {min(P.tree.K for P in sess)}.."
-          f"{max(P.tree.K for P in sess)}, power {time.perf_counter() - t0:.2f}s",
-          file=sys.stderr, flush=True)
+    print(f"[bench] serve: {n_sess} sessions, K {min(K_of)}..{max(K_of)}, "
+          f"power {time.perf_counter() - t0:.2f}s", file=sys.stderr, flush=True)
     srv = tapg.tapg_server_create(S.h, int(args.hbm_gb * 2**30), args.max_batch)
     rng = np.random.default_rng(np.random.SeedSequence([1004, 17]))
-    n_warm = n_sess  # one request per session before the timed ones
-    total = n_warm + args.requests
-    gaps = rng.exponential(1.0 / args.rate, size=total)
-    drift = rng.normal(0.0, 0.05, size=(total, net.nx))
     last_q = [P.q.copy() for P in sess]
     last_p = [P.p.copy() for P in sess]
     lock = threading.Lock()
-    tickets, results = [None] * total, [None] * total
-    submit_t = [0.0] * total
-    done_t = [0.0] * total
 
-    def collector():
-        for i in range(total):
-            while tickets[i] is None:
-                time.sleep(0.0005)
-            st, u0, r, lat = tapg.tapg_server_poll(srv, tickets[i], net.nu, -1)
-            done_t[i] = time.perf_counter()
+    def run(reqs, rate):
+        """Submit `reqs` requests (Poisson at `rate`, or all at once if rate is
+        None) round-robin over the sessions; returns per-request results."""
+        gaps = rng.exponential(1.0 / rate, size=reqs) if rate else np.zeros(reqs)
+        drift = rng.normal(0.0, 0.05, size=(reqs, net.nx))
+        tickets, results = [None] * reqs, [None] * reqs
+        submit_t, done_t = [0.0] * reqs, [0.0] * reqs
+
+        def collector():
+            for i in range(reqs):
+                while tickets[i] is None:
+                    time.sleep(0.0005)
+                st, u0, r, lat = tapg.tapg_server_poll(srv, tickets[i], net.nu, -1)
+                done_t[i] = time.perf_counter()
+                k = i % n_sess
+                with lock:
+                    if st in (tapg.TAPG_OK, tapg.TAPG_ENOTCONV):
+                        last_q[k] = np.clip(u0, net.umin, net.umax)
+                results[i] = (st, r, lat)
+
+        th = threading.Thread(target=collector)
+        th.start()
+        t_next = time.perf_counter()
+        for i in range(reqs):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
             k = i % n_sess
             with lock:
-                if st in (tapg.TAPG_OK, tapg.TAPG_ENOTCONV):
-                    last_q[k] = np.clip(u0, net.umin, net.umax)
-            results[i] = (st, r, lat)
+                if rate:
+                    last_p[k] = np.clip(last_p[k] + drift[i], net.xmin + 0.5, net.xmax - 0.5)
+                p, q = last_p[k].copy(), last_q[k].copy()
+            submit_t[i] = time.perf_counter()
+            tickets[i] = tapg.tapg_server_submit(srv, trees[k], p, q, session=k)
+        th.join()
+        return results, submit_t, done_t
 
-    th = threading.Thread(target=collector)
-    th.start()
     # the first (cold) request of every session completes before the timed
-    # arrivals start, so the timed window sees the warm-started re-solves only
-    for i in range(n_warm):
-        k = i % n_sess
-        submit_t[i] = time.perf_counter()
-        tickets[i] = tapg.tapg_server_submit(srv, trees[k], last_p[k], last_q[k], session=k)
-    while any(results[i] is None for i in range(n_warm)):
-        time.sleep(0.002)
-    print(f"[bench] serve: {n_warm} cold requests done", file=sys.stderr, flush=True)
-    stats0, timing0 = tapg.tapg_server_stats(srv), tapg.tapg_server_timing(srv)
-    t_next = time.perf_counter()
-    for i in range(n_warm, total):
-        t_next += gaps[i]
-        while time.perf_counter() < t_next:
-            time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
-        k = i % n_sess
-        with lock:
-            p = np.clip(last_p[k] + drift[i], net.xmin + 0.5, net.xmax - 0.5)
-            last_p[k] = p
-            q = last_q[k].copy()
-        submit_t[i] = time.perf_counter()
-        tickets[i] = tapg.tapg_server_submit(srv, trees[k], p, q, session=k)
-    th.join()
-    stats = tapg.tapg_server_stats(srv)
-    timing = tapg.tapg_server_timing(srv)
+    # arrivals start, so the timed windows see the warm-started re-solves only
+    run(n_sess, None)
+    # and one untimed round of re-solves at once: the first re-solve after a
+    # cold solve moves q the most and needs the most iterations
+    run(n_sess, 1e6)
+    print(f"[bench] serve: {n_sess} cold requests and one re-solve each done", file=sys.stderr,
+          flush=True)
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
+    curve = []
+    for rate in rates:
+        stats0, timing0 = tapg.tapg_server_stats(srv), tapg.tapg_server_timing(srv)
+        results, submit_t, done_t = run(args.requests, rate)
+        stats, timing = tapg.tapg_server_stats(srv), tapg.tapg_server_timing(srv)
+        stats = {k: stats[k] - stats0[k] for k in ("batches", "solved", "busy_ms")}
+        timing = {k: timing[k] - timing0[k] for k in timing}
+        lat_ms = np.array([r[2] for r in results])
+        iters = np.array([r[1].iters for r in results])
+        node_iters = float(sum(r[1].iters * K_of[i % n_sess] for i, r in enumerate(results)))
+        window = max(done_t) - min(submit_t)
+        done_rate = args.requests / window
+        point = {
+            "offered_rate": rate, "completed_rate": round(done_rate, 2),
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+            "mean_ms": round(float(lat_ms.mean()), 2),
+            # Little's law: requests in the system on average
+            "mean_in_system": round(done_rate * float(lat_ms.mean()) / 1e3, 2),
+            "completed_ok": int(sum(r[0] in (tapg.TAPG_OK, tapg.TAPG_ENOTCONV) for r in results)),
+            "converged": int(sum(bool(r[1].converged) for r in results)),
+            "iters_p50": int(np.percentile(iters, 50)), "iters_mean": round(float(iters.mean()), 1),
+            "iters_max": int(iters.max()),
+            # device work: node-iterations of the requests, and their rate while
+            # the worker ran chunks (the forest's throughput on this mix)
+            "node_iters_per_request": round(node_iters / args.requests),
+            "node_iters_per_chunk_s": round(node_iters / (stats["busy_ms"] / 1e3))
+            if stats["busy_ms"] > 0 else None,
+            "forests_formed": stats["batches"],
+            "worker_ms": {k: round(v, 1) for k, v in timing.items()},
+            "worker_busy_frac": round(sum(timing.values()) / (1e3 * window), 3),
+        }
+        curve.append(point)
+        print(f"[bench] serve: {json.dumps(point)}", file=sys.stderr, flush=True)
     tapg.tapg_server_destroy(srv)
-    # the timed phase only
-    stats = {k: stats[k] - stats0[k] for k in ("batches", "solved", "busy_ms")}
-    timing = {k: timing[k] - timing0[k] for k in timing}
-    timed = range(n_warm, total)
-    lat_ms = np.array([results[i][2] for i in timed])
-    ok = sum(results[i][0] in (tapg.TAPG_OK, tapg.TAPG_ENOTCONV) for i in timed)
-    conv = sum(bool(results[i][1].converged) for i in timed)
-    window = max(done_t[i] for i in timed) - min(submit_t[i] for i in timed)
-    iters = np.array([results[i][1].iters for i in timed])
+    last = curve[-1]
     out = {
         "metric": METRIC + " (serving)",
-        "value": round(args.requests / window, 4),
+        "value": last["completed_rate"],
         "unit": "requests/s",
         "n_gpus": 1,
         "steps": args.requests,
-        "warmup": n_warm,
-        "ms_per_step": round(1e3 * window / args.requests, 3),
+        "warmup": n_sess,
+        "ms_per_step": round(1e3 / last["completed_rate"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == tapg.TAPG_FP64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"serve: Poisson {args.rate:g} req/s offered, {n_sess} sessions, "
+        "config": {"workload": f"serve: Poisson {rates[-1]:g} req/s offered, {n_sess} sessions, "
                                f"S in 32..512, tol={args.tol:g}, warm-started re-solves, "
                                f"continuous batching (max {args.max_batch} in flight, "
                                f"{args.hbm_gb:g} GB admission budget)",
-                   "offered_rate": args.rate, "requests": args.requests, "sessions": n_sess,
+                   "offered_rate": rates[-1], "requests": args.requests, "sessions": n_sess,
                    "tol": args.tol, "precision": args.precision},
-        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-        "completed_ok": int(ok), "converged": int(conv),
-        "iters_p50": int(np.percentile(iters, 50)), "iters_max": int(iters.max()),
-        "forests_formed": stats["batches"],
-        "worker_busy_ms": round(stats["busy_ms"], 1),
-        "worker_ms": {k: round(v, 1) for k, v in timing.items()},
+        "p50_ms": last["p50_ms"], "p99_ms": last["p99_ms"],
+        "curve": curve,
         "roofline": None,
         "cpu_baseline": None,
     }
