@@ -183,10 +183,18 @@ struct Slot {
   int* d_own = nullptr;
   int fwd_group = 0;
   // Light upper levels (scan form, one tree): the levels above the bottom one
-  // run scan_top_kernel on local parts that n_loc extra workgroups of the
-  // bottom level's launch compute for the loc_count nodes above it.
+  // run inside the bottom level's backward launch, which has n_up more
+  // workgroups for their nodes' local parts.  d_up_par: per workgroup (bottom
+  // ones, then upper ones numbered from the lowest upper level) the upper
+  // workgroups above it; d_up_need: arrivals that complete an upper
+  // workgroup; d_up_cnt: its arrival counter (zero between launches).
   bool top_light = false;
-  int n_loc = 0, loc_count = 0;
+  int n_up = 0;
+  int* d_up_plan = nullptr;  // static table of each upper workgroup (see SegArgs)
+  int up_plan_stride = 0, up_nw = 0, up_nch = 0;
+  int2* d_up_par = nullptr;
+  int* d_up_need = nullptr;
+  unsigned* d_up_cnt = nullptr;
   std::vector<LevelPlan> plans;  // the plan the levels were built from
   bool segmented = false;
   bool scan = false;  // sweeps in scan form (the solver allows it; the autotuner may choose)

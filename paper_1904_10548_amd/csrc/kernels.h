@@ -67,6 +67,23 @@ constexpr int kSegThreads = 512;  // segment kernels
 // out of the per-workgroup limit when the dynamic part is checked
 constexpr int kSegStaticLds = 16 * 1024;
 
+// Light upper levels (SegArgs::n_main): the static table of one upper
+// workgroup, up_plan_stride ints: its nodes (stage by stage), where their
+// children are and which upper workgroups are above it.
+enum {
+  kPlanNw = 0,  // nodes
+  kPlanNst,     // stages
+  kPlanCb,      // first child of its last stage's nodes (in the level below)
+  kPlanNch,     // children of its last stage's nodes
+  kPlanSb,      // first stage
+  kPlanPar0,    // upper workgroups above it: first, last (-1: none)
+  kPlanPar1,
+  kPlanOff      // nst + 1 entries: first local index per stage; then node[nw],
+                // clo[nw], chi[nw]: a node's children as local indices (stages
+                // but the last) or as indices from cb (last stage)
+};
+constexpr int kUpStack = 64;  // pending arrivals of one workgroup (the host checks the bound)
+
 // Arguments of the per-stage sweep kernels.
 template <typename T>
 struct SweepArgs {
@@ -185,16 +202,27 @@ struct SegArgs {
   // first node the workgroup owns; nodes before it (ancestors shared with a
   // lower-numbered workgroup) are computed but not written (nullptr: all owned)
   const int* own;
-  // Light upper levels (scan form, one tree).  With n_main > 0, the first
-  // backward launch (the bottom level, n_main workgroups) has more
-  // workgroups after those, each writing, for 4 of the loc_count nodes above
-  // the bottom level (nodes 0 .. loc_count - 1), a_n = w1_n + w2_n to lam and
-  // the local part of m_n, Pi (kappa_n - (w3_n + B' a_n) / (2 w)), to jv; the
-  // levels above then run scan_top_kernel, which only sums the children into
-  // lambda_n = a_n + sum_c lambda_c and P_n = local_n - Pi B' (sum_c lambda_c)
-  // / (2 w) + sum_c P_c (the same values by the linearity of Pi and B').
-  int n_main, loc_count;
-  int top_nodes;  // scan_top_kernel: most nodes of one workgroup over its stages
+  // Light upper levels (scan form, one tree): the whole backward sweep in the
+  // bottom level's launch.  With n_main > 0 that launch has n_main bottom
+  // workgroups and then n_up more, one per upper workgroup j (all levels above
+  // the bottom one, numbered from the lowest level up), each writing for the
+  // nodes of upper workgroup j a_n = w1_n + w2_n to lam and the local part of
+  // m_n, Pi (kappa_n - (w3_n + B' a_n) / (2 w)), to jv.  The upper workgroups'
+  // own work (summing the children into lambda_n = a_n + sum_c lambda_c and
+  // P_n = local_n - Pi B' (sum_c lambda_c) / (2 w) + sum_c P_c, the same
+  // values by the linearity of Pi and B') is run by whichever workgroup of
+  // the launch completes its inputs: every bottom or upper workgroup, once
+  // done, counts one arrival at each upper workgroup above it (up_par for a
+  // bottom workgroup, its table for an upper one) and the local-part
+  // workgroup j one at j; the arrival that reaches up_need[u]
+  // runs upper workgroup u (and resets its counter), then arrives above it in
+  // turn.  No workgroup waits for another.
+  int n_main, n_up;
+  const int* up_plan;  // [n_up][up_plan_stride] static tables
+  int up_plan_stride, up_nw, up_nch;  // most nodes and children below of one upper workgroup
+  const int2* up_par;  // [n_main]: upper workgroups above each bottom workgroup
+  const int* up_need;  // [n_up]
+  unsigned* up_cnt;    // [n_up], zero between launches
 };
 
 // Persistent iteration of one tree: every workgroup of every level in one
@@ -233,11 +261,11 @@ template <typename T>
 size_t scan_lds(int nbm, const SegArgs<T>& a);
 template <typename T>
 void launch_seg(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t st);
-// A light upper level (scan form, one tree; see SegArgs::n_main) and its dynamic LDS.
+// Dynamic LDS of the work of an upper workgroup (light upper levels, see
+// SegArgs::n_main): a table of plan_ints ints, at most nw nodes and nch
+// children below.
 template <typename T>
-void launch_scan_top(const SegArgs<T>& a, int n_wg, hipStream_t st);
-template <typename T>
-size_t scan_top_lds(const SegArgs<T>& a);
+size_t scan_up_lds(int plan_ints, int nw, int nch, int nu, int ns, int nnzB, int nnzG, int nnzE);
 template <typename T>
 size_t seg_lds(int nbm, const SegArgs<T>& a);
 // Cooperative launch of the persistent iteration (NB: widest level's

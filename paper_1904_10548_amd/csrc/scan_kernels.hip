@@ -104,28 +104,39 @@ struct LdsCursor {
   }
 };
 
+// The CSR of B', G and E' open a backward launch's dynamic LDS, at the same
+// offsets for every role of the launch (bottom level, local parts, upper
+// levels), so that a workgroup going on to an upper level keeps them.
 template <typename T>
-struct BwdLds {  // a (then lambda), v (then m), G v; ranges; packed children slots
-                 // (two buffers); per-slot sums of the boundary children (P then
-                 // lambda, up to 4 slots); CSR of B', G and E'
-  size_t lam, v, gv, rg, ch, bnd, brow, bcol, bval, grow, gcol, gval, erow, ecol, eval, total;
+struct CsrLds {
+  size_t brow, bcol, bval, grow, gcol, gval, erow, ecol, eval;
+  __host__ __device__ void take(LdsCursor& c, int nu, int ns, int nnzB, int nnzG, int nnzE) {
+    brow = c.take(sizeof(int) * (nu + 1));
+    bcol = c.take(sizeof(int) * nnzB);
+    bval = c.take(sizeof(T) * nnzB);
+    grow = c.take(sizeof(int) * (ns + 1));
+    gcol = c.take(sizeof(int) * nnzG);
+    gval = c.take(sizeof(T) * nnzG);
+    erow = c.take(sizeof(int) * (nu + 1));
+    ecol = c.take(sizeof(int) * nnzE);
+    eval = c.take(sizeof(T) * nnzE);
+  }
+};
+
+template <typename T>
+struct BwdLds : CsrLds<T> {  // CSR of B', G and E'; a (then lambda), v (then m), G v;
+                             // ranges; packed children slots (two buffers); per-slot
+                             // sums of the boundary children (P then lambda, up to 4 slots)
+  size_t lam, v, gv, rg, ch, bnd, total;
   __host__ __device__ explicit BwdLds(const SegArgs<T>& a) {
     LdsCursor c;
+    this->take(c, a.nu, a.ns, a.nnzB, a.nnzG, a.nnzE);
     lam = c.take(sizeof(T) * kCN * kSX);
     v = c.take(sizeof(T) * kCN * kSU);
     bnd = c.take(sizeof(T) * 4 * (kSU + kSX));
     gv = c.take(sizeof(T) * kCN * a.ns);
     rg = c.take(sizeof(int2) * a.nst);
     ch = c.take(sizeof(int) * 2 * kCN);
-    brow = c.take(sizeof(int) * (a.nu + 1));
-    bcol = c.take(sizeof(int) * a.nnzB);
-    bval = c.take(sizeof(T) * a.nnzB);
-    grow = c.take(sizeof(int) * (a.ns + 1));
-    gcol = c.take(sizeof(int) * a.nnzG);
-    gval = c.take(sizeof(T) * a.nnzG);
-    erow = c.take(sizeof(int) * (a.nu + 1));
-    ecol = c.take(sizeof(int) * a.nnzE);
-    eval = c.take(sizeof(T) * a.nnzE);
     total = c.off;
   }
 };
@@ -184,6 +195,18 @@ struct FixRow {
     return acc;
   }
 };
+
+// Values handed from one workgroup to another inside a launch (light upper
+// levels): agent-scope atomic stores and loads, coherent across the compute
+// dies' L2 caches without writing back or invalidating whole caches.
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Children slot range (c0, c1) of a node-stage packed into one int.
 __device__ __forceinline__ int pack_ch(int c0, int c1) { return c0 | (c1 << 16); }
@@ -338,7 +361,11 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
           const int2 rr = sRg[ps_lo + k - sb];
 #pragma unroll
           for (int b = 0; b < NB; ++b)
-            if (b < rr.y - rr.x) a.jv[(size_t)(rr.x + b) * kSU + iu] = dP[k * NB + b];
+            if (b < rr.y - rr.x) {
+              T* dst = a.jv + (size_t)(rr.x + b) * kSU + iu;
+              if (ps_lo + k == sb) st_agent(dst, dP[k * NB + b]);  // read by the level above
+              else *dst = dP[k * NB + b];
+            }
         }
       }
     }
@@ -415,7 +442,7 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
         const int2 rr = sRg[0];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          if (b < rr.y - rr.x && ix < nx) a.lam[(size_t)(rr.x + b) * LDX + ix] = av[b];
+          if (b < rr.y - rr.x && ix < nx) st_agent(a.lam + (size_t)(rr.x + b) * LDX + ix, av[b]);
       }
     }
     __syncthreads();
@@ -541,18 +568,18 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
 }
 
 // ---------------------------------------------------------------------------
-// Local part of the backward recursion for the nodes above the bottom level
-// (light upper levels): workgroup k of this role takes nodes 4k .. 4k+3 of
-// the loc_count nodes above the bottom level, one node per 128 threads, and
-// writes a_n = w1_n + w2_n (to lam) and Pi (kappa_n - (w3_n + B' a_n) / (2 w))
-// (to jv).  It runs in the bottom level's launch, beside that level's
-// workgroups, and uses the same dynamic LDS layout.
+// Light upper levels: the whole backward sweep of one tree in the bottom
+// level's launch (SegArgs::n_main).
 // ---------------------------------------------------------------------------
+
+// Local parts for the nodes of upper workgroup j (from its table), 4 nodes
+// per pass (one per 128 threads): a_n = w1_n + w2_n to lam and Pi (kappa_n -
+// (w3_n + B' a_n) / (2 w)) to jv.  Uses the bottom launch's dynamic LDS layout.
 template <typename T>
-__device__ __forceinline__ void scan_local_body(const SegArgs<T>& a, int k, int it, T beta,
-                                                T scale) {
+__device__ __forceinline__ void scan_local_up(const SegArgs<T>& a, int j, int it, T beta,
+                                              T scale) {
   const bool power = a.mode == 1;  // w = scale y, no data terms
-  constexpr int LN = kSegThreads / kSU;  // nodes per workgroup
+  constexpr int LN = kSegThreads / kSU;  // nodes per pass
   const int tid = threadIdx.x;
   const T* Yc = (it & 1) ? a.Y1 : a.Y0;
   const T* Yo = (it & 1) ? a.Y0 : a.Y1;
@@ -572,229 +599,296 @@ __device__ __forceinline__ void scan_local_body(const SegArgs<T>& a, int k, int 
   int* eRow = reinterpret_cast<int*>(smem_raw + L.erow);
   int* eCol = reinterpret_cast<int*>(smem_raw + L.ecol);
   T* eVal = reinterpret_cast<T*>(smem_raw + L.eval);
-  const int b = tid / kSU, i = tid % kSU;
-  const int n = k * LN + b;
-  const bool node_ok = n < a.loc_count;
-  // inputs (issued before the CSR copies complete)
-  T ax = T(0), w3 = T(0), kap = T(0);
-  if (node_ok && i < nx) {
-    const size_t o = (size_t)n * LDY + i;
-    ax = power ? scale * (Yc[o] + Yc[o + LDX])
-               : wext(Yc[o], Yo[o], beta) + wext(Yc[o + LDX], Yo[o + LDX], beta);
-  }
-  if (node_ok && i < nu) {
-    const size_t o = (size_t)n * LDY + 2 * LDX + i;
-    w3 = power ? scale * Yc[o] : wext(Yc[o], Yo[o], beta);
-    kap = power ? T(0) : a.kappa[(size_t)n * kSU + i];
-  }
+  const int* plan = a.up_plan + (size_t)j * a.up_plan_stride;
+  const int nw = plan[kPlanNw];
+  const int* node = plan + kPlanOff + plan[kPlanNst] + 1;
   csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
   csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, ns, a.nnzG, gRow, gCol, gVal);
   csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
-  if (i < kSX) sA[b * kSX + i] = ax;
-  __syncthreads();
-  {  // v = kappa - (w3 + B' a) / (2 w)
-    T t = w3;
-    if (i < nu)
-      for (int p = sRow[i]; p < sRow[i + 1]; ++p) t += sVal[p] * sA[b * kSX + sCol[p]];
-    sV[b * kSU + i] = node_ok && i < nu ? kap - hw * t : T(0);
+  const int b = tid / kSU, i = tid % kSU;
+  for (int k0 = 0; k0 < nw; k0 += LN) {
+    const bool node_ok = k0 + b < nw;
+    const int n = node_ok ? node[k0 + b] : 0;
+    T ax = T(0), w3 = T(0), kap = T(0);
+    if (node_ok && i < nx) {
+      const size_t o = (size_t)n * LDY + i;
+      ax = power ? scale * (Yc[o] + Yc[o + LDX])
+                 : wext(Yc[o], Yo[o], beta) + wext(Yc[o + LDX], Yo[o + LDX], beta);
+    }
+    if (node_ok && i < nu) {
+      const size_t o = (size_t)n * LDY + 2 * LDX + i;
+      w3 = power ? scale * Yc[o] : wext(Yc[o], Yo[o], beta);
+      kap = power ? T(0) : a.kappa[(size_t)n * kSU + i];
+    }
+    if (i < kSX) sA[b * kSX + i] = ax;
+    __syncthreads();
+    {  // v = kappa - (w3 + B' a) / (2 w)
+      T t = w3;
+      if (i < nu)
+        for (int p = sRow[i]; p < sRow[i + 1]; ++p) t += sVal[p] * sA[b * kSX + sCol[p]];
+      sV[b * kSU + i] = node_ok && i < nu ? kap - hw * t : T(0);
+    }
+    __syncthreads();
+    for (int e = tid; e < LN * ns; e += kSegThreads) {  // G v
+      const int bb = e / ns, r = e - bb * ns;
+      T acc = T(0);
+      for (int p = gRow[r]; p < gRow[r + 1]; ++p) acc += gVal[p] * sV[bb * kSU + gCol[p]];
+      sGv[bb * ns + r] = acc;
+    }
+    __syncthreads();
+    if (node_ok && i < nu) {  // Pi v = v - E'(G v)
+      T acc = T(0);
+      for (int p = eRow[i]; p < eRow[i + 1]; ++p) acc += eVal[p] * sGv[b * ns + eCol[p]];
+      st_agent(a.jv + (size_t)n * kSU + i, sV[b * kSU + i] - acc);
+    }
+    if (node_ok && i < nx) st_agent(a.lam + (size_t)n * LDX + i, ax);
   }
-  __syncthreads();
-  for (int e = tid; e < LN * ns; e += kSegThreads) {  // G v
-    const int bb = e / ns, r = e - bb * ns;
-    T acc = T(0);
-    for (int p = gRow[r]; p < gRow[r + 1]; ++p) acc += gVal[p] * sV[bb * kSU + gCol[p]];
-    sGv[bb * ns + r] = acc;
-  }
-  __syncthreads();
-  if (node_ok && i < nu) {  // Pi v = v - E'(G v)
-    T acc = T(0);
-    for (int p = eRow[i]; p < eRow[i + 1]; ++p) acc += eVal[p] * sGv[b * ns + eCol[p]];
-    a.jv[(size_t)n * kSU + i] = sV[b * kSU + i] - acc;
-  }
-  if (node_ok && i < nx) a.lam[(size_t)n * LDX + i] = ax;
 }
 
-// ---------------------------------------------------------------------------
-// A light upper level (one tree): workgroup wg holds its nodes of every stage
-// of the level (the level's node ranges), whose a_n and local part of m_n the
-// bottom level's launch left in lam and jv, and the children of its last
-// stage, which the level below left (lambda at that level's first stage, P
-// everywhere).  Stage by stage from the last: the children's sums, lambda_n
-// = a_n + sum lambda_c, the correction Pi B' (sum lambda_c) / (2 w), P_n =
-// local_n + sum P_c - correction.  Writes P_n for its nodes and lambda_n for
-// its first stage.  All of a workgroup's inputs are loaded at once.
-// ---------------------------------------------------------------------------
+// Dynamic LDS of an upper workgroup's work: the CSR (as in the backward
+// layout), its table, per node lambda, P, the children's lambda sum, B' of
+// it and G B' of it, and the children below (lambda and P).
 template <typename T>
-struct TopLds {
-  size_t rg, off, cb, ce, lam, p, sl, t, g, bl, bp, brow, bcol, bval, grow, gcol, gval, erow,
-      ecol, eval, total;
-  __host__ __device__ explicit TopLds(const SegArgs<T>& a) {
+struct TopLds : CsrLds<T> {
+  size_t plan, lam, p, sl, t, g, bl, bp, total;
+  __host__ __device__ TopLds(int plan_ints, int nw_, int nch_, int nu, int ns, int nnzB,
+                             int nnzG, int nnzE) {
     LdsCursor c;
-    const size_t nw = (size_t)a.top_nodes, nch = (size_t)(a.nch > 0 ? a.nch : 1);
-    rg = c.take(sizeof(int2) * a.nst);
-    off = c.take(sizeof(int) * (a.nst + 1));
-    cb = c.take(sizeof(int) * nw);
-    ce = c.take(sizeof(int) * nw);
+    this->take(c, nu, ns, nnzB, nnzG, nnzE);
+    const size_t nw = (size_t)(nw_ > 0 ? nw_ : 1), nch = (size_t)(nch_ > 0 ? nch_ : 1);
+    plan = c.take(sizeof(int) * plan_ints);
     lam = c.take(sizeof(T) * nw * kSX);
     p = c.take(sizeof(T) * nw * kSU);
     sl = c.take(sizeof(T) * nw * kSX);
     t = c.take(sizeof(T) * nw * kSU);
-    g = c.take(sizeof(T) * nw * (a.ns > 0 ? a.ns : 1));
+    g = c.take(sizeof(T) * nw * (ns > 0 ? ns : 1));
     bl = c.take(sizeof(T) * nch * kSX);
     bp = c.take(sizeof(T) * nch * kSU);
-    brow = c.take(sizeof(int) * (a.nu + 1));
-    bcol = c.take(sizeof(int) * a.nnzB);
-    bval = c.take(sizeof(T) * a.nnzB);
-    grow = c.take(sizeof(int) * (a.ns + 1));
-    gcol = c.take(sizeof(int) * a.nnzG);
-    gval = c.take(sizeof(T) * a.nnzG);
-    erow = c.take(sizeof(int) * (a.nu + 1));
-    ecol = c.take(sizeof(int) * a.nnzE);
-    eval = c.take(sizeof(T) * a.nnzE);
     total = c.off;
   }
 };
 
+// The work of the upper workgroup whose table is in LDS: its nodes' a_n and
+// local part of m_n are in lam and jv, and so are the children below its last
+// stage (lambda at their stage, P), which the workgroups below left there.
+// One batch of loads gathers them all.  The recursions are component-wise,
+// so one thread per component walks the stages from the last: lambda_n = a_n
+// + sum lambda_c; then the corrections Pi B' (sum lambda_c) / (2 w) of all
+// nodes at once; then P_n = (local_n - correction_n) + sum P_c.  Writes P_n
+// for its nodes and lambda_n for its first stage.  The CSR of B', G and E'
+// are in LDS.
 template <typename T>
-__global__ __launch_bounds__(kSegThreads) void scan_top_kernel(SegArgs<T> a) {
-  if (a.ctl[0].done) return;
-  const int tid = threadIdx.x, wg = blockIdx.x;
-  const int nx = a.nx, nu = a.nu, LDX = a.LDX, ns = a.ns, nst = a.nst;
-  const int sb = a.s_begin, se = a.s_end;
+__device__ void scan_top_body(const SegArgs<T>& a) {
+  const int tid = threadIdx.x;
+  const int nx = a.nx, nu = a.nu, LDX = a.LDX, ns = a.ns;
   const T hw = T(0.5) * a.winv;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const TopLds<T> L(a);
-  int2* sRg = reinterpret_cast<int2*>(smem_raw + L.rg);
-  int* sOff = reinterpret_cast<int*>(smem_raw + L.off);
-  int* sCb = reinterpret_cast<int*>(smem_raw + L.cb);
-  int* sCe = reinterpret_cast<int*>(smem_raw + L.ce);
+  const TopLds<T> L(a.up_plan_stride, a.up_nw, a.up_nch, nu, ns, a.nnzB, a.nnzG, a.nnzE);
+  const int* P = reinterpret_cast<const int*>(smem_raw + L.plan);
   T* sL = reinterpret_cast<T*>(smem_raw + L.lam);   // [nw][kSX]: a, then lambda
   T* sP = reinterpret_cast<T*>(smem_raw + L.p);     // [nw][kSU]: local part, then P
   T* sS = reinterpret_cast<T*>(smem_raw + L.sl);    // [nw][kSX]: sum of children's lambda
   T* sT = reinterpret_cast<T*>(smem_raw + L.t);     // [nw][kSU]: B' sum
   T* sG = reinterpret_cast<T*>(smem_raw + L.g);     // [nw][ns]: G B' sum
-  T* sBL = reinterpret_cast<T*>(smem_raw + L.bl);   // [nch][kSX]: lambda of the level below
-  T* sBP = reinterpret_cast<T*>(smem_raw + L.bp);   // [nch][kSU]: P of the level below
-  int* sRow = reinterpret_cast<int*>(smem_raw + L.brow);
-  int* sCol = reinterpret_cast<int*>(smem_raw + L.bcol);
-  T* sVal = reinterpret_cast<T*>(smem_raw + L.bval);
-  int* gRow = reinterpret_cast<int*>(smem_raw + L.grow);
-  int* gCol = reinterpret_cast<int*>(smem_raw + L.gcol);
-  T* gVal = reinterpret_cast<T*>(smem_raw + L.gval);
-  int* eRow = reinterpret_cast<int*>(smem_raw + L.erow);
-  int* eCol = reinterpret_cast<int*>(smem_raw + L.ecol);
-  T* eVal = reinterpret_cast<T*>(smem_raw + L.eval);
-  const bool kids_below = se + 1 < a.N;
-  int cb = 0, ce = 0;
-  if (kids_below) {
-    const int2 kc = a.wgx[2 * wg];
-    cb = kc.x;
-    ce = kc.y;
-  }
-  for (int i = tid; i < nst; i += kSegThreads) sRg[i] = a.ranges[(size_t)wg * nst + i];
-  csr_to_lds<T>(a.Btrow, a.Btcol, a.Btval, nu, a.nnzB, sRow, sCol, sVal);
-  csr_to_lds<T>(a.Grow, a.Gcol, a.Gval, ns, a.nnzG, gRow, gCol, gVal);
-  csr_to_lds<T>(a.Etrow, a.Etcol, a.Etval, nu, a.nnzE, eRow, eCol, eVal);
-  // the children of the last stage, from the level below
-  const int nchl = ce - cb;
-  for (int e = tid; e < nchl * kSX; e += kSegThreads) {
-    const int c = e / kSX, i = e - c * kSX;
-    sBL[e] = i < nx ? a.lam[(size_t)(cb + c) * LDX + i] : T(0);
-  }
-  for (int e = tid; e < nchl * kSU; e += kSegThreads) {
-    const int c = e / kSU, i = e - c * kSU;
-    sBP[e] = i < nu ? a.jv[(size_t)(cb + c) * kSU + i] : T(0);
+  T* sBL = reinterpret_cast<T*>(smem_raw + L.bl);   // [nch][kSX]: lambda of the children below
+  T* sBP = reinterpret_cast<T*>(smem_raw + L.bp);   // [nch][kSU]: P of the children below
+  const int* sRow = reinterpret_cast<const int*>(smem_raw + L.brow);
+  const int* sCol = reinterpret_cast<const int*>(smem_raw + L.bcol);
+  const T* sVal = reinterpret_cast<const T*>(smem_raw + L.bval);
+  const int* gRow = reinterpret_cast<const int*>(smem_raw + L.grow);
+  const int* gCol = reinterpret_cast<const int*>(smem_raw + L.gcol);
+  const T* gVal = reinterpret_cast<const T*>(smem_raw + L.gval);
+  const int* eRow = reinterpret_cast<const int*>(smem_raw + L.erow);
+  const int* eCol = reinterpret_cast<const int*>(smem_raw + L.ecol);
+  const T* eVal = reinterpret_cast<const T*>(smem_raw + L.eval);
+  const int nw = P[kPlanNw], nst = P[kPlanNst], cb = P[kPlanCb], nchl = P[kPlanNch];
+  const int* off = P + kPlanOff;
+  const int* node = off + nst + 1;
+  const int* clo = node + nw;
+  const int* chi = clo + nw;
+  // Gather: element e of [children lambda | children P | own a | own local
+  // part], rows of kSX or kSU; R loads per thread in flight before any wait.
+  // Sources and LDS destinations are kept as offsets from global and LDS
+  // bases, so that loads stay global and stores stay in LDS.
+  {
+    constexpr int R = 8;
+    const int e1 = nchl * kSX, e2 = e1 + nchl * kSU, e3 = e2 + nw * kSX, e4 = e3 + nw * kSU;
+    T* sDst = reinterpret_cast<T*>(smem_raw);  // element offsets below are from here
+    const size_t oBL = L.bl / sizeof(T), oBP = L.bp / sizeof(T), oL = L.lam / sizeof(T),
+                 oP = L.p / sizeof(T);
+    for (int base = 0; base < e4; base += R * kSegThreads) {
+      T v[R];
+      int dst[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = base + r * kSegThreads + tid;
+        bool ok = false, from_lam = true;
+        size_t src = 0;
+        dst[r] = -1;
+        if (e < e1) {
+          const int c = e / kSX, i = e - c * kSX;
+          ok = i < nx;
+          src = (size_t)(cb + c) * LDX + i;
+          dst[r] = (int)(oBL + e);
+        } else if (e < e2) {
+          const int c = (e - e1) / kSU, i = (e - e1) - c * kSU;
+          ok = i < nu;
+          from_lam = false;
+          src = (size_t)(cb + c) * kSU + i;
+          dst[r] = (int)(oBP + (e - e1));
+        } else if (e < e3) {
+          const int k = (e - e2) / kSX, i = (e - e2) - k * kSX;
+          ok = i < nx;
+          src = (size_t)node[k] * LDX + i;
+          dst[r] = (int)(oL + (e - e2));
+        } else if (e < e4) {
+          const int k = (e - e3) / kSU, i = (e - e3) - k * kSU;
+          ok = i < nu;
+          from_lam = false;
+          src = (size_t)node[k] * kSU + i;
+          dst[r] = (int)(oP + (e - e3));
+        }
+        const T* base_p = from_lam ? a.lam : a.jv;
+        v[r] = ld_agent(base_p + (ok ? src : 0));
+        v[r] = ok ? v[r] : T(0);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (dst[r] >= 0) sDst[dst[r]] = v[r];
+    }
   }
   __syncthreads();
-  if (tid == 0) {
-    int o = 0;
-    for (int q = 0; q < nst; ++q) {
-      sOff[q] = o;
-      o += sRg[q].y - sRg[q].x;
-    }
-    sOff[nst] = o;
-  }
-  __syncthreads();
-  const int nw = sOff[nst];
-  auto node_of = [&](int k) {  // local index -> (stage index, node)
-    int q = 0;
-    while (q + 1 < nst && sOff[q + 1] <= k) ++q;
-    return make_int2(q, sRg[q].x + (k - sOff[q]));
-  };
-  for (int e = tid; e < nw * kSX; e += kSegThreads) {
-    const int k = e / kSX, i = e - k * kSX;
-    const int n = node_of(k).y;
-    sL[e] = i < nx ? a.lam[(size_t)n * LDX + i] : T(0);
-  }
-  for (int e = tid; e < nw * kSU; e += kSegThreads) {
-    const int k = e / kSU, i = e - k * kSU;
-    const int n = node_of(k).y;
-    sP[e] = i < nu ? a.jv[(size_t)n * kSU + i] : T(0);
-  }
-  for (int k = tid; k < nw; k += kSegThreads) {
-    const int n = node_of(k).y;
-    sCb[k] = a.cbeg[n];
-    sCe[k] = a.cend[n];
-  }
-  __syncthreads();
-  for (int q = nst - 1; q >= 0; --q) {
-    const int k0 = sOff[q], kw = sOff[q + 1] - k0;
-    const bool last = q == nst - 1;
-    const int cfirst = last ? cb : sRg[q + 1].x;  // first child of the stage below
-    const int cbase = last ? 0 : sOff[q + 1];     // its local index
-    const T* CL = last ? sBL : sL;
-    const T* CP = last ? sBP : sP;
-    // children's sums: lambda_n = a_n + sum, P_n = local_n + sum
-    for (int e = tid; e < kw * kSX; e += kSegThreads) {
-      const int k = k0 + e / kSX, i = e % kSX;
-      T acc = T(0);
-      if (!(last && !kids_below))
-        for (int c = sCb[k]; c < sCe[k]; ++c) acc += CL[(cbase + c - cfirst) * kSX + i];
-      sS[k * kSX + i] = acc;
-      sL[k * kSX + i] += acc;
-    }
-    for (int e = tid; e < kw * kSU; e += kSegThreads) {
-      const int k = k0 + e / kSU, i = e % kSU;
-      T acc = T(0);
-      if (!(last && !kids_below))
-        for (int c = sCb[k]; c < sCe[k]; ++c) acc += CP[(cbase + c - cfirst) * kSU + i];
-      sP[k * kSU + i] += acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kw * kSU; e += kSegThreads) {  // B' (sum lambda)
-      const int k = k0 + e / kSU, i = e % kSU;
-      T acc = T(0);
-      if (i < nu)
-        for (int p = sRow[i]; p < sRow[i + 1]; ++p) acc += sVal[p] * sS[k * kSX + sCol[p]];
-      sT[k * kSU + i] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kw * ns; e += kSegThreads) {  // G B' (sum lambda)
-      const int k = k0 + e / ns, r = e % ns;
-      T acc = T(0);
-      for (int p = gRow[r]; p < gRow[r + 1]; ++p) acc += gVal[p] * sT[k * kSU + gCol[p]];
-      sG[k * ns + r] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kw * kSU; e += kSegThreads) {  // P_n -= Pi B' (sum lambda) / (2 w)
-      const int k = k0 + e / kSU, i = e % kSU;
-      if (i < nu) {
+  // lambda chain, one thread per component, deepest stage first: the sum of
+  // the children's lambda (below the last stage: the gathered ones) and
+  // lambda_n = a_n + sum; the first stage's lambda goes out at once
+  if (tid < kSX) {
+    const int i = tid;
+    for (int q = nst - 1; q >= 0; --q) {
+      const T* CL = q == nst - 1 ? sBL : sL;
+      for (int k = off[q]; k < off[q + 1]; ++k) {
         T acc = T(0);
-        for (int p = eRow[i]; p < eRow[i + 1]; ++p) acc += eVal[p] * sG[k * ns + eCol[p]];
-        sP[k * kSU + i] -= hw * (sT[k * kSU + i] - acc);
+        for (int c = clo[k]; c < chi[k]; ++c) acc += CL[c * kSX + i];
+        sS[k * kSX + i] = acc;
+        sL[k * kSX + i] += acc;
       }
     }
+    if (P[kPlanSb] > 0 && i < nx)  // the level above reads the first stage's lambda
+      for (int k = 0; k < off[1]; ++k) st_agent(a.lam + (size_t)node[k] * LDX + i, sL[k * kSX + i]);
+  }
+  __syncthreads();
+  // the corrections Pi B' (sum lambda) / (2 w) of every node: B' (sum lambda)
+  for (int e = tid; e < nw * kSU; e += kSegThreads) {
+    const int k = e / kSU, i = e % kSU;
+    T acc = T(0);
+    if (i < nu)
+      for (int p = sRow[i]; p < sRow[i + 1]; ++p) acc += sVal[p] * sS[k * kSX + sCol[p]];
+    sT[k * kSU + i] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < nw * ns; e += kSegThreads) {  // G B' (sum lambda)
+    const int k = e / ns, r = e % ns;
+    T acc = T(0);
+    for (int p = gRow[r]; p < gRow[r + 1]; ++p) acc += gVal[p] * sT[k * kSU + gCol[p]];
+    sG[k * ns + r] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < nw * kSU; e += kSegThreads) {  // local part less the correction
+    const int k = e / kSU, i = e % kSU;
+    if (i < nu) {
+      T acc = T(0);
+      for (int p = eRow[i]; p < eRow[i + 1]; ++p) acc += eVal[p] * sG[k * ns + eCol[p]];
+      sP[k * kSU + i] -= hw * (sT[k * kSU + i] - acc);
+    }
+  }
+  __syncthreads();
+  // P chain, one thread per component, deepest stage first: P_n = (local_n -
+  // correction_n) + sum of the children's P; every P goes out
+  if (tid < kSU && tid < nu) {
+    const int i = tid;
+    for (int q = nst - 1; q >= 0; --q) {
+      const T* CP = q == nst - 1 ? sBP : sP;
+      for (int k = off[q]; k < off[q + 1]; ++k) {
+        T acc = T(0);
+        for (int c = clo[k]; c < chi[k]; ++c) acc += CP[c * kSU + i];
+        const T v = sP[k * kSU + i] + acc;
+        sP[k * kSU + i] = v;
+        st_agent(a.jv + (size_t)node[k] * kSU + i, v);
+      }
+    }
+  }
+}
+
+// After a workgroup's stores: one arrival at each upper workgroup p0 .. p1;
+// an arrival that completes an upper workgroup's inputs runs it here, then
+// arrives above it.  What crosses workgroups (lambda at a level's first
+// stage, P there, the local parts, an upper workgroup's results) is written
+// and read with agent-scope atomic stores and loads.  Before an arrival every
+// wave waits for its stores to complete and the workgroup meets at a
+// barrier, so thread 0's arrival (an atomic add) follows them; the runner's
+// threads read after the barrier that follows its arrival.  The table of the
+// first upper workgroup a workgroup may run is loaded (it is static) while
+// the stores complete; the CSR of B', G and E' stay in LDS from the
+// workgroup's own work.
+template <typename T>
+__device__ void scan_cascade(const SegArgs<T>& a, int p0, int p1) {
+  __shared__ int sStack[kUpStack];
+  __shared__ int sTop, sRun, sHave;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TopLds<T> L(a.up_plan_stride, a.up_nw, a.up_nch, a.nu, a.ns, a.nnzB, a.nnzG, a.nnzE);
+  int* sPlan = reinterpret_cast<int*>(smem_raw + L.plan);
+  const int tid = threadIdx.x;
+  const int PS = a.up_plan_stride;  // <= kSegThreads (the host checks)
+  int pre = p0;  // upper workgroup whose table is prefetched
+  int pv = pre >= 0 && tid < PS ? a.up_plan[(size_t)pre * PS + tid] : 0;
+  vm_wait_all();
+  __syncthreads();  // the workgroup's own work is done with the LDS
+  if (pre >= 0 && tid < PS) sPlan[tid] = pv;
+  if (tid == 0) {
+    int n = 0;
+    for (int u = p1; p0 >= 0 && u >= p0 && n < kUpStack; --u) sStack[n++] = u;
+    sTop = n;
+    sHave = pre;
+  }
+  __syncthreads();
+  while (true) {
+    if (tid == 0) {
+      int run = -1;
+      while (sTop > 0 && run < 0) {
+        const int u = sStack[--sTop];
+        const unsigned old = __hip_atomic_fetch_add(&a.up_cnt[u], 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == (unsigned)a.up_need[u]) {
+          // every arrival of this launch is in: the counter is free again
+          __hip_atomic_store(&a.up_cnt[u], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          run = u;
+        }
+      }
+      sRun = run;
+    }
+    __syncthreads();
+    const int u = sRun;
+    if (u < 0) return;
+    if (sHave != u) {  // not the prefetched table
+      const int v = tid < PS ? a.up_plan[(size_t)u * PS + tid] : 0;
+      __syncthreads();
+      if (tid < PS) sPlan[tid] = v;
+      if (tid == 0) sHave = u;
+      __syncthreads();
+    }
+    scan_top_body<T>(a);
+    const int q0 = sPlan[kPlanPar0], q1 = sPlan[kPlanPar1];
+    const int nv = q0 >= 0 && tid < PS ? a.up_plan[(size_t)q0 * PS + tid] : 0;  // next table
+    vm_wait_all();
+    __syncthreads();
+    if (q0 >= 0 && tid < PS) sPlan[tid] = nv;
+    if (tid == 0) {
+      int n = sTop;
+      for (int v = q1; q0 >= 0 && v >= q0 && n < kUpStack; --v) sStack[n++] = v;
+      sTop = n;
+      sHave = q0;
+    }
     __syncthreads();
   }
-  for (int e = tid; e < nw * kSU; e += kSegThreads) {
-    const int k = e / kSU, i = e - k * kSU;
-    if (i < nu) a.jv[(size_t)node_of(k).y * kSU + i] = sP[e];
-  }
-  if (sb > 0)  // the level above reads the first stage's lambda
-    for (int e = tid; e < sOff[1] * kSX; e += kSegThreads) {
-      const int k = e / kSX, i = e - k * kSX;
-      if (i < nx) a.lam[(size_t)(sRg[0].x + k) * LDX + i] = sL[e];
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,16 +1242,22 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
 
 template <typename T, int NB>
 __global__ __launch_bounds__(kSegThreads) void scan_bwd_kernel(SegArgs<T> a) {
-  if (a.n_main > 0 && (int)blockIdx.x >= a.n_main) {  // light upper levels' local parts
+  if (a.n_main > 0 && (int)blockIdx.x >= a.n_main) {  // local parts of upper workgroup j
     const DevCtl c = a.close ? bwd_ctl_peek(a) : a.ctl[0];
     if (c.done) return;
-    scan_local_body<T>(a, blockIdx.x - a.n_main, c.iter, (T)c.beta, (T)c.pw_scale);
+    const int j = (int)blockIdx.x - a.n_main;
+    scan_local_up<T>(a, j, c.iter, (T)c.beta, (T)c.pw_scale);
+    scan_cascade<T>(a, j, j);
     return;
   }
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
   const DevCtl c = bwd_ctl(a, tree);
   if (c.done) return;
   scan_bwd_body<T, NB>(a, blockIdx.x, c.iter, (T)c.beta, (T)c.pw_scale);
+  if (a.n_main > 0) {  // the levels above, in this launch
+    const int2 p = a.up_par[blockIdx.x];
+    scan_cascade<T>(a, p.x, p.y);
+  }
 }
 
 template <typename T, int NB>
@@ -1176,9 +1276,23 @@ __global__ __launch_bounds__(kSegThreads) void scan_fwd_kernel(SegArgs<T> a) {
   }
 }
 
+template <typename T>
+size_t scan_up_lds(int plan_ints, int nw, int nch, int nu, int ns, int nnzB, int nnzG, int nnzE) {
+  return (TopLds<T>(plan_ints, nw, nch, nu, ns, nnzB, nnzG, nnzE).total + 15) & ~(size_t)15;
+}
+
+// Dynamic LDS of a backward launch that also runs the upper levels.
+template <typename T>
+size_t scan_bwd_lds_with_up(const SegArgs<T>& a) {
+  const size_t b = scan_lds_bytes<T>(a, false);
+  const size_t t = scan_up_lds<T>(a.up_plan_stride, a.up_nw, a.up_nch, a.nu, a.ns, a.nnzB,
+                                  a.nnzG, a.nnzE);
+  return t > b ? t : b;
+}
+
 template <typename T, int NB>
 void launch_scan_nb(bool fwd, const SegArgs<T>& a, int n_wg, hipStream_t st) {
-  const size_t lds = scan_lds_bytes<T>(a, fwd);
+  const size_t lds = !fwd && a.n_main > 0 ? scan_bwd_lds_with_up<T>(a) : scan_lds_bytes<T>(a, fwd);
   if (fwd)
     hipLaunchKernelGGL((scan_fwd_kernel<T, NB>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
   else
@@ -1196,16 +1310,6 @@ void launch_scan(bool fwd, int nbm, const SegArgs<T>& a, int n_wg, hipStream_t s
 }
 
 template <typename T>
-size_t scan_top_lds(const SegArgs<T>& a) {
-  return (TopLds<T>(a).total + 15) & ~(size_t)15;
-}
-
-template <typename T>
-void launch_scan_top(const SegArgs<T>& a, int n_wg, hipStream_t st) {
-  hipLaunchKernelGGL((scan_top_kernel<T>), dim3(n_wg), dim3(kSegThreads), scan_top_lds<T>(a), st, a);
-}
-
-template <typename T>
 size_t scan_lds(int, const SegArgs<T>& a) {
   const size_t f = scan_lds_bytes<T>(a, true), b = scan_lds_bytes<T>(a, false);
   return f > b ? f : b;
@@ -1215,9 +1319,7 @@ template void launch_scan<double>(bool, int, const SegArgs<double>&, int, hipStr
 template void launch_scan<float>(bool, int, const SegArgs<float>&, int, hipStream_t);
 template size_t scan_lds<double>(int, const SegArgs<double>&);
 template size_t scan_lds<float>(int, const SegArgs<float>&);
-template void launch_scan_top<double>(const SegArgs<double>&, int, hipStream_t);
-template void launch_scan_top<float>(const SegArgs<float>&, int, hipStream_t);
-template size_t scan_top_lds<double>(const SegArgs<double>&);
-template size_t scan_top_lds<float>(const SegArgs<float>&);
+template size_t scan_up_lds<double>(int, int, int, int, int, int, int, int);
+template size_t scan_up_lds<float>(int, int, int, int, int, int, int, int);
 
 }  // namespace tapg

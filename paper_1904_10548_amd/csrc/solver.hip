@@ -412,18 +412,21 @@ void enqueue_iteration(tapg_solver_s* S, Slot& sl, const NetDev<T>& d, int mode,
           a.part_total = L.n_wg;
         }
         a.close = (close && mode == 0 && pass == 0 && q == 0) ? 1 : 0;
-        const bool light = sl.top_light && pass == 0;
-        a.n_main = 0;
-        a.loc_count = 0;
-        a.top_nodes = 0;
+        const bool light = sl.top_light && sl.n_up > 0 && pass == 0;
+        if (light && l != nl - 1) continue;  // the upper levels run in the bottom launch
+        a.n_main = a.n_up = 0;
         if (tc) (void)hipEventRecord(S->tev[2 * tc->next], st);
-        if (light && l == nl - 1) {  // bottom level and the upper nodes' local parts
+        if (light) {  // bottom level, the upper nodes' local parts and the upper levels
           a.n_main = L.n_wg;
-          a.loc_count = sl.loc_count;
-          launch_seg<T>(false, L.nbm, a, L.n_wg + sl.n_loc, st);
-        } else if (light) {
-          a.top_nodes = L.nw;
-          launch_scan_top<T>(a, L.n_wg, st);
+          a.n_up = sl.n_up;
+          a.up_plan = sl.d_up_plan;
+          a.up_plan_stride = sl.up_plan_stride;
+          a.up_nw = sl.up_nw;
+          a.up_nch = sl.up_nch;
+          a.up_par = sl.d_up_par;
+          a.up_need = sl.d_up_need;
+          a.up_cnt = sl.d_up_cnt;
+          launch_seg<T>(false, L.nbm, a, L.n_wg + sl.n_up, st);
         } else {
           launch_seg<T>(pass == 1, L.nbm, a, L.n_wg, st);
         }
@@ -1409,6 +1412,7 @@ void dev_init(tapg_solver_s* S) {
 }
 
 void free_chain(Slot& sl);
+void free_up(Slot& sl);
 
 void free_fwd_full(Slot& sl) {
   dfree(sl.fwd_full.d_ranges);
@@ -1431,6 +1435,7 @@ void dev_free_slot(Slot& sl) {
   dfree(sl.d_kperp); dfree(sl.d_zb); dfree(sl.d_zr);
   dfree(sl.d_ctl); dfree(sl.d_hist); dfree(sl.d_part);
   free_chain(sl);
+  free_up(sl);
   for (auto& L : sl.levels) {
     dfree(L.d_ranges);
     dfree(L.d_wgtree);
@@ -1608,27 +1613,25 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
   sl.fwd_full = L;
 }
 
-template <typename T>
-size_t top_lds_probe(tapg_solver_s* S, int nst, int nw, int nch) {
-  SegArgs<T> probe{};
-  probe.nst = nst;
-  probe.top_nodes = nw;
-  probe.nch = nch;
-  probe.nu = S->net.nu;
-  probe.ns = S->net.ns;
-  probe.nnzB = S->nnzB;
-  probe.nnzG = S->nnzG;
-  probe.nnzE = S->nnzE;
-  return scan_top_lds<T>(probe);
+void free_up(Slot& sl) {
+  dfree(sl.d_up_plan);
+  dfree(sl.d_up_par);
+  dfree(sl.d_up_need);
+  dfree(sl.d_up_cnt);
+  sl.n_up = 0;
 }
 
 // Light upper levels, where they apply (scan form, one tree, two levels or
-// more, and each upper level's workgroup inputs fit the LDS): per upper level
-// the most nodes one workgroup holds; the nodes above the bottom level and the
-// workgroups that compute their local parts.  Otherwise the slot runs every
+// more, and the upper workgroups' work fits the LDS): per upper level the most
+// nodes one workgroup holds, and the tables of the bottom launch that runs
+// them (SegArgs::n_main): upper workgroups numbered from the lowest upper
+// level up, each with its static table (nodes, children, the upper
+// workgroups above it), the upper workgroups above each bottom workgroup, the
+// arrivals that complete each upper workgroup (its child workgroups and its
+// local part) and their counters.  Otherwise the slot runs every
 // level with the full kernel.
 void setup_top_light(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
-  sl.n_loc = sl.loc_count = 0;
+  free_up(sl);
   const int nl = (int)sl.levels.size();
   // a plan whose upper levels are wider than the full kernels take needs them
   auto wide = [&] {
@@ -1647,28 +1650,132 @@ void setup_top_light(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
     refuse("scan form, one tree, two levels or more");
     return;
   }
-  for (int l = 0; l + 1 < nl; ++l) {
-    Slot::Level& L = sl.levels[l];
-    const LevelPlan& P = sl.plans[l];
+  std::vector<std::vector<std::pair<int, int>>> rp(nl);
+  for (int l = 0; l < nl; ++l) {
     int wmax = 0;
-    const std::vector<std::pair<int, int>> rp = level_ranges(t, P, wmax);
-    const int nst = P.s_end - P.s_begin + 1;
-    int nw = 0;
-    for (int w = 0; w < P.n_wg; ++w) {
-      int c = 0;
-      for (int q = 0; q < nst; ++q) c += rp[(size_t)w * nst + q].second - rp[(size_t)w * nst + q].first;
-      nw = std::max(nw, c);
-    }
-    L.nw = nw;
-    const size_t lds = S->fp32 ? top_lds_probe<float>(S, nst, nw, L.nch)
-                               : top_lds_probe<double>(S, nst, nw, L.nch);
-    if (lds > S->lds_limit) {
-      refuse("LDS");
-      return;
+    rp[l] = level_ranges(t, sl.plans[l], wmax);
+  }
+  auto nst_of = [&](int l) { return sl.plans[l].s_end - sl.plans[l].s_begin + 1; };
+  // upper workgroups, from the lowest upper level up; the owner of each node
+  // at an upper level's last stage
+  std::vector<int> wg0(nl, 0), owner(t.K, -1);
+  int n_up = 0;
+  for (int l = nl - 2; l >= 0; --l) {
+    wg0[l] = n_up;
+    n_up += sl.levels[l].n_wg;
+  }
+  for (int l = 0; l + 1 < nl; ++l) {
+    const int nst = nst_of(l);
+    for (int w = 0; w < sl.levels[l].n_wg; ++w) {
+      const auto& q = rp[l][(size_t)w * nst + nst - 1];
+      for (int n = q.first; n < q.second; ++n) owner[n] = wg0[l] + w;
     }
   }
-  sl.loc_count = t.offset[sl.levels.back().s_begin];
-  sl.n_loc = (sl.loc_count + 3) / 4;
+  // the upper workgroups above workgroup w of level l >= 1: the owners of
+  // the parents of its first stage's nodes (consecutive nodes, consecutive
+  // owners, every one a parent)
+  auto parents_of = [&](int l, int w) {
+    const auto& f = rp[l][(size_t)w * nst_of(l)];
+    return make_int2(owner[t.anc[f.first]], owner[t.anc[f.second - 1]]);
+  };
+  // tables: sizes first
+  int nw_max = 1, nch_max = 1, nst_max = 1;
+  for (int l = 0; l + 1 < nl; ++l) {
+    Slot::Level& L = sl.levels[l];
+    const int nst = nst_of(l);
+    nst_max = std::max(nst_max, nst);
+    int nw = 0;
+    for (int w = 0; w < L.n_wg; ++w) {
+      int c = 0;
+      for (int q = 0; q < nst; ++q)
+        c += rp[l][(size_t)w * nst + q].second - rp[l][(size_t)w * nst + q].first;
+      nw = std::max(nw, c);
+      const auto& lq = rp[l][(size_t)w * nst + nst - 1];
+      nch_max = std::max(nch_max, t.cend[lq.second - 1] - t.cbeg[lq.first]);
+    }
+    L.nw = nw;
+    nw_max = std::max(nw_max, nw);
+  }
+  const int PS = kPlanOff + nst_max + 1 + 3 * nw_max;
+  if (PS > kSegThreads) {
+    refuse("upper workgroups with too many nodes");
+    return;
+  }
+  const size_t lds =
+      S->fp32 ? scan_up_lds<float>(PS, nw_max, nch_max, S->net.nu, S->net.ns, S->nnzB, S->nnzG,
+                                   S->nnzE)
+              : scan_up_lds<double>(PS, nw_max, nch_max, S->net.nu, S->net.ns, S->nnzB, S->nnzG,
+                                    S->nnzE);
+  if (lds + kSegStaticLds > S->lds_limit) {
+    refuse("LDS");
+    return;
+  }
+  std::vector<int> plan((size_t)n_up * PS, 0);
+  std::vector<int> need(n_up, 1);  // 1: its local part
+  int widest = 1;
+  auto count_arrivals = [&](int2 p) {
+    if (p.x < 0 || p.y < p.x || p.y >= n_up)
+      throw Fail{TAPG_EINVAL, "light upper levels: inconsistent level ranges"};
+    for (int u = p.x; u <= p.y; ++u) need[u]++;
+    widest = std::max(widest, p.y - p.x + 1);
+  };
+  for (int l = 0; l + 1 < nl; ++l) {
+    const int nst = nst_of(l);
+    for (int w = 0; w < sl.levels[l].n_wg; ++w) {
+      int* P = plan.data() + (size_t)(wg0[l] + w) * PS;
+      const auto* rg = &rp[l][(size_t)w * nst];
+      int nw = 0;
+      for (int q = 0; q < nst; ++q) nw += rg[q].second - rg[q].first;
+      const int cb = t.cbeg[rg[nst - 1].first];
+      P[kPlanNw] = nw;
+      P[kPlanNst] = nst;
+      P[kPlanCb] = cb;
+      P[kPlanNch] = t.cend[rg[nst - 1].second - 1] - cb;
+      P[kPlanSb] = sl.plans[l].s_begin;
+      const int2 par = l > 0 ? parents_of(l, w) : make_int2(-1, -1);
+      if (l > 0) count_arrivals(par);
+      P[kPlanPar0] = par.x;
+      P[kPlanPar1] = par.y;
+      int* off = P + kPlanOff;
+      int* node = off + nst + 1;
+      int* clo = node + nw;
+      int* chi = clo + nw;
+      int k = 0;
+      for (int q = 0; q < nst; ++q) {
+        off[q] = k;
+        for (int n = rg[q].first; n < rg[q].second; ++n, ++k) {
+          node[k] = n;
+          if (q + 1 < nst) {  // children: this workgroup's nodes of the next stage
+            clo[k] = off[q] + (rg[q].second - rg[q].first) + (t.cbeg[n] - rg[q + 1].first);
+            chi[k] = clo[k] + (t.cend[n] - t.cbeg[n]);
+          } else {  // children below, from cb
+            clo[k] = t.cbeg[n] - cb;
+            chi[k] = t.cend[n] - cb;
+          }
+        }
+      }
+      off[nst] = k;
+    }
+  }
+  const int n_main = sl.levels.back().n_wg;
+  std::vector<int2> par(n_main);
+  for (int w = 0; w < n_main; ++w) {
+    par[w] = parents_of(nl - 1, w);
+    count_arrivals(par[w]);
+  }
+  if (widest * nl > kUpStack) {
+    refuse("a workgroup below too many upper workgroups");
+    return;
+  }
+  hipStream_t st = S->stream;
+  sl.d_up_plan = upload(plan, st);
+  sl.d_up_par = upload(par, st);
+  sl.d_up_need = upload(need, st);
+  sl.d_up_cnt = upload(std::vector<unsigned>(n_up, 0u), st);
+  sl.up_plan_stride = PS;
+  sl.up_nw = nw_max;
+  sl.up_nch = nch_max;
+  sl.n_up = n_up;
 }
 
 // (Re)build the level launches of a slot from a plan.
