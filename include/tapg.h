@@ -340,9 +340,11 @@ tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees
 /* The schedule of a tree (ntrees = 1) or of a batch's forest as its last
  * solve or autotune left it, written to buf (cap bytes, NUL-terminated) as the
  * environment settings that force it on a fresh solver, for instance
- * "TAPG_SCAN=1 TAPG_LEVELS=0:1,2:1,5:1 TAPG_FWD_GROUP=1" (levels: first stage
- * and workgroup group of each; forward group: last-stage nodes per forward
- * workgroup of the scan form, 0 = the bottom level's workgroups) or
+ * "TAPG_SCAN=1 TAPG_LEVELS=0:1,2:1,5:1 TAPG_FWD_GROUP=1 TAPG_TOP=1" (levels:
+ * first stage and workgroup group of each; forward group: last-stage nodes
+ * per forward workgroup of the scan form, 0 = the bottom level's workgroups;
+ * TAPG_TOP=1: light upper levels, whose work runs inside the bottom level's
+ * backward launch, so that the backward sweep is one launch) or
  * "TAPG_SEGMENTS=0" (per-stage kernels).  TAPG_EINVAL if cap is too small,
  * TAPG_ESTATE before the first solve or autotune of that tree or batch. */
 tapg_status tapg_schedule_spec(tapg_solver solver, int ntrees, const tapg_tree* trees, char* buf,

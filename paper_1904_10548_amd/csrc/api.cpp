@@ -671,7 +671,9 @@ tapg_status tapg_sweep_form(tapg_solver solver, int ntrees, const tapg_tree* tre
     if (sl.segmented) f = sl.scan ? TAPG_FORM_SCAN : solver->proj ? TAPG_FORM_PROJECTOR : TAPG_FORM_SEGMENT;
     if (form) *form = f;
     if (bwd_launches)
-      *bwd_launches = sl.segmented ? (int)sl.levels.size() : sl.N;
+      *bwd_launches = !sl.segmented                  ? sl.N
+                      : (sl.top_light && sl.n_up > 0) ? 1  // upper levels in the bottom launch
+                                                      : (int)sl.levels.size();
     return TAPG_OK;
   });
 }
