@@ -1240,9 +1240,11 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
 
 }  // namespace
 
-template <typename T, int NB>
+// UP: the bottom launch of light upper levels (SegArgs::n_main > 0); a
+// separate instance, so that the plain backward kernel carries none of it.
+template <typename T, int NB, bool UP>
 __global__ __launch_bounds__(kSegThreads) void scan_bwd_kernel(SegArgs<T> a) {
-  if (a.n_main > 0 && (int)blockIdx.x >= a.n_main) {  // local parts of upper workgroup j
+  if (UP && (int)blockIdx.x >= a.n_main) {  // local parts of upper workgroup j
     const DevCtl c = a.close ? bwd_ctl_peek(a) : a.ctl[0];
     if (c.done) return;
     const int j = (int)blockIdx.x - a.n_main;
@@ -1254,7 +1256,7 @@ __global__ __launch_bounds__(kSegThreads) void scan_bwd_kernel(SegArgs<T> a) {
   const DevCtl c = bwd_ctl(a, tree);
   if (c.done) return;
   scan_bwd_body<T, NB>(a, blockIdx.x, c.iter, (T)c.beta, (T)c.pw_scale);
-  if (a.n_main > 0) {  // the levels above, in this launch
+  if (UP) {  // the levels above, in this launch
     const int2 p = a.up_par[blockIdx.x];
     scan_cascade<T>(a, p.x, p.y);
   }
@@ -1295,8 +1297,10 @@ void launch_scan_nb(bool fwd, const SegArgs<T>& a, int n_wg, hipStream_t st) {
   const size_t lds = !fwd && a.n_main > 0 ? scan_bwd_lds_with_up<T>(a) : scan_lds_bytes<T>(a, fwd);
   if (fwd)
     hipLaunchKernelGGL((scan_fwd_kernel<T, NB>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+  else if (a.n_main > 0)
+    hipLaunchKernelGGL((scan_bwd_kernel<T, NB, true>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
   else
-    hipLaunchKernelGGL((scan_bwd_kernel<T, NB>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
+    hipLaunchKernelGGL((scan_bwd_kernel<T, NB, false>), dim3(n_wg), dim3(kSegThreads), lds, st, a);
 }
 
 template <typename T>
