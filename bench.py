@@ -250,13 +250,18 @@ def main_single(args, ds, tapg, have_torch):
         dom = max(kinds, key=lambda k: kinds[k]["ms"])
         d = kinds[dom]
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        # measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
+        # WRITE_SIZE, calibrated against a plain copy) from the committed
+        # counter summary, when it matches these kernel sources
         tb = measured_traffic(args.config, args.precision, form)
-        traffic = None
-        if tb is not None and dom in tb:
-            traffic = round(tb[dom] / (d["avg_us"] * 1e-6) / 1e9, 2)
+        traffic = round(tb[dom]) if tb is not None and dom in tb else None
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "traffic_bytes_per_launch": tb[dom] if traffic is not None else None,
+                "traffic_unit": "HBM bytes per launch",
+                "traffic_gbs": None if traffic is None else
+                round(traffic / (d["avg_us"] * 1e-6) / 1e9, 2),
+                "traffic_over_algorithmic": None if traffic is None else
+                round(traffic / (d["bytes"] / max(d["launches"], 1)), 3),
                 "kernel": f"{kernel_prefix(form)}_{dom}_kernel", "avg_launch_us": round(d["avg_us"], 3),
                 "avg_launch_us_event_pairs": round(d["avg_us_raw"], 3),
                 "event_pair_overhead_us": round(pair_us, 3),
@@ -336,14 +341,18 @@ def main_batch(args, ds, tapg):
         tapg.tapg_estimate_lipschitz(S.h, t, 100)
     lipschitz_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    tune_ms, tune_nc = tapg.tapg_autotune(S.h, trees, 10)
+    if args.no_autotune:  # the planner's schedule (or the one TAPG_* settings force)
+        tune_ms, tune_nc = None, 0
+        S.batch_solve(trees, ps, qs)  # the schedule is built with the first solve
+    else:
+        tune_ms, tune_nc = tapg.tapg_autotune(S.h, trees, 10)
     tune_s = time.perf_counter() - t0
     form, n_bwd = tapg.tapg_sweep_form(S.h, trees)
     spec = tapg.tapg_schedule_spec(S.h, trees)
     elem = 8 if prec == tapg.TAPG_FP64 else 4
     forest_bytes = sum(sweep_bytes(net.nx, net.nu, elem, K_tot, 1, kind, form) for kind in ("bwd", "fwd"))
     print(f"[bench] batch64: 64 trees, {K_tot} nodes, power {lipschitz_s:.3f}s, autotune "
-          f"{tune_s:.3f}s: {form} form, {n_bwd} backward launches, {tune_ms:.4f} ms/iter",
+          f"{tune_s:.3f}s: {form} form, {n_bwd} backward launches, {tune_ms} ms/iter",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
         st, _, res = S.batch_solve(trees, ps, qs)
@@ -398,20 +407,21 @@ def main_batch(args, ds, tapg):
         # one iteration of the whole forest (every tree running), as the
         # autotuner timed it with the schedule and form it kept
         "schedule": {"form": form, "bwd_launches": n_bwd, "spec": spec,
-                     "autotune_s": round(tune_s, 3),
-                     "autotune_candidates": tune_nc, "forest_ms_per_iter": round(tune_ms, 5),
-                     "forest_gb_per_iter": round(forest_bytes / 1e9, 4),
-                     "forest_gbs": round(forest_bytes / (tune_ms * 1e-3) / 1e9, 1)},
-        # the forest's whole iteration (every launch) as the autotuner timed it
-        # with all trees running, against the HBM peak
-        "roofline": {"bound": "hbm", "achieved": round(forest_bytes / (tune_ms * 1e-3) / 1e9, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(forest_bytes / (tune_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                     "traffic": None, "kernel": "forest iteration (every launch)",
-                     "bytes_per_iteration": int(forest_bytes),
-                     "ms_per_iteration": round(tune_ms, 5)},
+                     "autotune_s": round(tune_s, 3), "autotune_candidates": tune_nc,
+                     "forest_gb_per_iter": round(forest_bytes / 1e9, 4)},
+        "roofline": None,
         "cpu_baseline": cpu,
     }
+    if tune_ms is not None:
+        # the forest's whole iteration (every launch) as the autotuner timed it
+        # with all trees running, against the HBM peak
+        gbs = forest_bytes / (tune_ms * 1e-3) / 1e9
+        out["schedule"].update(forest_ms_per_iter=round(tune_ms, 5), forest_gbs=round(gbs, 1))
+        out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                           "kernel": "forest iteration (every launch)",
+                           "bytes_per_iteration": int(forest_bytes),
+                           "ms_per_iteration": round(tune_ms, 5)}
     S.close()
     return out
 
