@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--horizon-steps", type=int, default=168, help="closed loop: H_s")
     ap.add_argument("--ext-steps", type=int, default=2,
                     help="timed steps of each extension workload in the default run")
+    ap.add_argument("--dense-wu", action="store_true",
+                    help="single tree with a dense W_u (100 I + a seeded rank-8 coupling)")
     ap.add_argument("--no-extensions", action="store_true",
                     help="time the headline workload only")
     args = ap.parse_args()
@@ -146,7 +148,8 @@ def main():
 def extensions(args, ds, tapg, have_torch):
     """The extension workloads, timed in the same run as the headline (each a
     few steps at the paper's tolerance 5e-2): the 2,048-scenario tree and the
-    64-tree batch in FP64 and FP32 sweeps, and a closed loop."""
+    64-tree batch in FP64 and FP32 sweeps, the 128-scenario tree with a dense
+    W_u, and a closed loop."""
     ext = {}
     for cfg, prec in (("dwn2048", "fp64"), ("dwn2048", "fp32"), ("batch64", "fp64"),
                       ("batch64", "fp32")):
@@ -160,8 +163,16 @@ def extensions(args, ds, tapg, have_torch):
         ext[f"{cfg}_{prec}_tol5e-2"] = {k: r[k] for k in r if k not in (
             "metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data",
             "cpu_baseline")}
+    # the general path: a dense W_u (dense stage factors in registers)
     a = argparse.Namespace(**vars(args))
-    a.config, a.precision, a.tol = "dwn128", "fp64", 5e-2
+    a.config, a.precision, a.tol, a.dense_wu = "dwn128", "fp64", 5e-2, True
+    a.steps, a.warmup, a.no_cpu_baseline, a.max_iter = args.ext_steps, 1, True, 400000
+    print("[bench] extension dwn128 dense W_u fp64 tol 5e-2", file=sys.stderr, flush=True)
+    r = main_single(a, ds, tapg, have_torch)
+    ext["dwn128_dense_wu_fp64_tol5e-2"] = {k: r[k] for k in r if k not in (
+        "metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data", "cpu_baseline")}
+    a = argparse.Namespace(**vars(args))
+    a.config, a.precision, a.tol, a.dense_wu = "dwn128", "fp64", 5e-2, False
     print("[bench] extension closed loop", file=sys.stderr, flush=True)
     r = main_closed_loop(a, ds, tapg)
     ext["closed_loop_dwn128_fp64_tol5e-2"] = {k: r[k] for k in r if k not in (
@@ -174,6 +185,8 @@ def main_single(args, ds, tapg, have_torch):
     if have_torch:
         import torch
     P = ds.config_problem(args.config)
+    if args.dense_wu:  # the general path: dense stage factors, no projector or scan form
+        P.weights.W_u = ds.dense_input_weight(P.net.nu)
     net, w = P.net, P.weights
     prec = tapg.TAPG_FP64 if args.precision == "fp64" else tapg.TAPG_FP32
     elem = 8 if prec == tapg.TAPG_FP64 else 4

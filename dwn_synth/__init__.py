@@ -30,6 +30,7 @@ from .generate import (
     nodes_per_stage_for,
     CONFIGS,
     config_problem,
+    dense_input_weight,
 )
 from .closed_loop import LoopInputs, make_loop_inputs
 from .scenarios import make_error_paths
@@ -49,6 +50,7 @@ __all__ = [
     "make_problem",
     "nodes_per_stage_for",
     "CONFIGS",
+    "dense_input_weight",
     "config_problem",
     "LoopInputs",
     "make_loop_inputs",

@@ -284,6 +284,17 @@ def make_weights(rng: np.random.Generator, net: Network) -> Weights:
                    alpha0=alpha0, c_energy=net.is_pump.astype(np.float64))
 
 
+def dense_input_weight(nu: int, seed: int = 5, base: float = 100.0, coupling: float = 5.0,
+                       rank: int = 8) -> np.ndarray:
+    """A dense symmetric positive definite ``W_u = base I + coupling M M' / rank``
+    (``M`` seeded standard normal, ``nu x rank``): the smoothing cost couples
+    the inputs, so no stage factor reduces to a projector (the general path)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 77]))
+    M = rng.standard_normal((nu, rank))
+    W = base * np.eye(nu) + coupling * (M @ M.T) / rank
+    return 0.5 * (W + W.T)
+
+
 def make_problem(nx, nu, nd, ns, n_pumps, N, b1, S, seed, demand_model="lognormal",
                  price_model="dayahead", hour0=0, name="") -> Problem:
     """Full instance from one seed (three sub-streams: network, tree, data)."""

@@ -32,10 +32,12 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dwn128_tol1e-4.json")
 # The schedule the benchmark's autotuner chose for this tree (scan form, four
-# backward levels, forward launch on the bottom level's workgroups).
-BENCH_SPEC = {"TAPG_SCAN": "1", "TAPG_LEVELS": "0:1,2:1,4:1,6:1", "TAPG_FWD_GROUP": "0"}
+# levels, the three upper ones light, inside the bottom level's backward
+# launch; forward launch on groups of one leaf).
+BENCH_SPEC = {"TAPG_SCAN": "1", "TAPG_LEVELS": "0:1,1:1,4:1,6:1", "TAPG_FWD_GROUP": "1",
+              "TAPG_TOP": "1"}
 ENV_KEYS = ("TAPG_LEVELS", "TAPG_PROJ", "TAPG_CHAIN", "TAPG_SCAN", "TAPG_FWD_GROUP",
-            "TAPG_TEST_SERVER_SETUP_FAIL")
+            "TAPG_TOP", "TAPG_TEST_SERVER_SETUP_FAIL")
 
 
 @pytest.fixture(autouse=True)
@@ -157,6 +159,38 @@ def test_batch64_trees_in_one_fp64_forest_match_oracle(scan):
         assert np.abs(u0 - ref.u[0]).max() <= 1e-9 * su
         J = O.primal_cost(P, ref.u, ref.x)
         assert abs(r.cost - J) <= 1e-6 * max(1.0, abs(J))
+
+
+def test_dense_input_weight_at_full_size_matches_oracle():
+    """A dense W_u (100 I plus a seeded rank-8 coupling): no stage factor is a
+    projector, so the sweeps hold the dense 114 x 114 factor blocks (one per
+    stage) in registers, in the segment form.  Three full-size trees of the
+    64-tree configuration in one FP64 forest and the 128-scenario tree alone,
+    element by element against the oracle after 30 iterations."""
+    batch = _batch64([0, 1, 4])
+    single = ds.config_problem("dwn128")
+    W = ds.dense_input_weight(single.net.nu)
+    for P in batch + [single]:
+        P.weights.W_u = W
+    iters = 30
+    for group in (batch, [single]):
+        say("dense W_u", [P.tree.K for P in group])
+        with make_solver(group[0], gamma=0.0, tol=0.0, max_iter=iters, check_every=iters) as S:
+            trees = [add_tree(S, P) for P in group]
+            st, u0s, res = S.batch_solve(trees, [P.p for P in group], [P.q for P in group])
+            form = tapg.tapg_sweep_form(S.h, trees)
+            nb = tapg.tapg_factor_blocks(S.h, group[0].tree.N)
+            out = [S.primal(t) for t in trees]
+        say("form", form, "factor blocks", nb)
+        assert st == tapg.TAPG_OK and form[0] == "segment"
+        for P, r, (u, x) in zip(group, res, out):
+            ref = O.apg(P, r.gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
+            su, sx = (max(1.0, np.abs(v).max()) for v in (ref.u, ref.x))
+            assert r.iters == iters
+            assert np.abs(u - ref.u).max() <= 1e-9 * su
+            assert np.abs(x - ref.x).max() <= 1e-9 * sx
+            J = O.primal_cost(P, ref.u, ref.x)
+            assert abs(r.cost - J) <= 1e-6 * max(1.0, abs(J))
 
 
 def test_batch64_whole_forest_equals_each_tree_alone():
