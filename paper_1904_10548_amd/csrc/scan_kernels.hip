@@ -981,18 +981,30 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
       P.u[j][0] = ldc((const T*)a.jv, n * kSU + iu, ok);
       P.u[j][1] = ldc(a.kperp, n * kSU + iu, ok);
       P.u[j][2] = ldc(a.invp, n, ok);
-      P.u[j][3] = ldc(Yc, n * LDY + 2 * LDX + iu, ok);
-      P.u[j][4] = ldc((const T*)Yn, n * LDY + 2 * LDX + iu, ok);
+      // FP64: the dual iterates only where this workgroup writes the node (the
+      // owner test is the same in every lane of a wave: a scalar branch); an
+      // ancestor it only walks needs P, kperp and 1/p for the chains.  (FP32
+      // measured faster without the branch.)
+      if (sizeof(T) != sizeof(double) || P.ou[j] >= 0) {
+        P.u[j][3] = ldc(Yc, n * LDY + 2 * LDX + iu, ok);
+        P.u[j][4] = ldc((const T*)Yn, n * LDY + 2 * LDX + iu, ok);
+      } else {
+        P.u[j][3] = P.u[j][4] = T(0);
+      }
     }
 #pragma unroll
     for (int j = 0; j < kQX; ++j) {
       const bool ok = P.nx[j] >= 0 && ix < nx;
       const size_t n = (size_t)P.nx[j];
       P.x[j][0] = ldc(a.g, n * LDX + ix, ok);
-      P.x[j][1] = ldc(Yc, n * LDY + ix, ok);
-      P.x[j][2] = ldc((const T*)Yn, n * LDY + ix, ok);
-      P.x[j][3] = ldc(Yc, n * LDY + LDX + ix, ok);
-      P.x[j][4] = ldc((const T*)Yn, n * LDY + LDX + ix, ok);
+      if (sizeof(T) != sizeof(double) || P.ox[j] >= 0) {
+        P.x[j][1] = ldc(Yc, n * LDY + ix, ok);
+        P.x[j][2] = ldc((const T*)Yn, n * LDY + ix, ok);
+        P.x[j][3] = ldc(Yc, n * LDY + LDX + ix, ok);
+        P.x[j][4] = ldc((const T*)Yn, n * LDY + LDX + ix, ok);
+      } else {
+        P.x[j][1] = P.x[j][2] = P.x[j][3] = P.x[j][4] = T(0);
+      }
     }
     {
       const int kb = tid < kCN ? tid : 0;
