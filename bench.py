@@ -101,7 +101,8 @@ def main():
                     help="keep the planner's schedule and the default sweep form (profiling runs)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: offered requests/s")
     ap.add_argument("--rates", default="", help="serve: comma-separated offered rates (load curve)")
-    ap.add_argument("--requests", type=int, default=400, help="serve: timed requests")
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="serve: timed requests (per offered rate)")
     ap.add_argument("--sessions", type=int, default=32, help="serve: sessions (one tree each)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: trees in flight")
     ap.add_argument("--hbm-gb", type=float, default=64.0, help="serve: admission budget")
