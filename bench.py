@@ -62,10 +62,11 @@ def kernel_prefix(form):
     return "scan" if form == "scan" else "seg"
 
 
-def measured_traffic(workload, precision, form):
+def measured_traffic(workload, precision, form, spec=None):
     """HBM bytes per launch of each sweep kind from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, if it was taken on this workload and sweep
-    form with the current kernel sources (else None)."""
+    WRITE_SIZE counter summary, if it was taken on this workload, sweep form
+    and schedule (the settings ``spec``) with the current kernel sources
+    (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles",
                         f"{kernel_prefix(form)}_sweeps_{workload}_{precision}_hbm_counters.md")
@@ -81,6 +82,8 @@ def measured_traffic(workload, precision, form):
             sha.update(fh.read())
     if data.get("kernel_sources_sha256") != sha.hexdigest():
         return None
+    if spec is not None and sorted(data.get("spec", "").split()) != sorted(spec.split()):
+        return None  # taken under another schedule: other launches
     return data["bytes_per_launch"]
 
 
@@ -267,7 +270,7 @@ def main_single(args, ds, tapg, have_torch):
         # measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
         # WRITE_SIZE, calibrated against a plain copy) from the committed
         # counter summary, when it matches these kernel sources
-        tb = measured_traffic(args.config, args.precision, form)
+        tb = measured_traffic(args.config, args.precision, form, spec)
         traffic = round(tb[dom]) if tb is not None and dom in tb else None
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
