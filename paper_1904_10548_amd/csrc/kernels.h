@@ -78,6 +78,7 @@ enum {
   kPlanSb,      // first stage
   kPlanPar0,    // upper workgroups above it: first, last (-1: none)
   kPlanPar1,
+  kPlanTree,    // its tree (a forest's workgroups never span two trees)
   kPlanOff      // nst + 1 entries: first local index per stage; then node[nw],
                 // clo[nw], chi[nw]: a node's children as local indices (stages
                 // but the last) or as indices from cb (last stage)
@@ -202,9 +203,9 @@ struct SegArgs {
   // first node the workgroup owns; nodes before it (ancestors shared with a
   // lower-numbered workgroup) are computed but not written (nullptr: all owned)
   const int* own;
-  // Light upper levels (scan form, one tree): the whole backward sweep in the
-  // bottom level's launch.  With n_main > 0 that launch has n_main bottom
-  // workgroups and then n_up more, one per upper workgroup j (all levels above
+  // Light upper levels (scan form): the whole backward sweep in the bottom
+  // level's launch.  With n_main > 0 that launch has n_main bottom workgroups
+  // and then n_up more, one per upper workgroup j (all levels above
   // the bottom one, numbered from the lowest level up), each writing for the
   // nodes of upper workgroup j a_n = w1_n + w2_n to lam and the local part of
   // m_n, Pi (kappa_n - (w3_n + B' a_n) / (2 w)), to jv.  The upper workgroups'

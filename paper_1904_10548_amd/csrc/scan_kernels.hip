@@ -568,8 +568,8 @@ __device__ __forceinline__ void scan_bwd_body(const SegArgs<T>& a, int wg, int i
 }
 
 // ---------------------------------------------------------------------------
-// Light upper levels: the whole backward sweep of one tree in the bottom
-// level's launch (SegArgs::n_main).
+// Light upper levels: the whole backward sweep of a tree or a forest in the
+// bottom level's launch (SegArgs::n_main).
 // ---------------------------------------------------------------------------
 
 // Local parts for the nodes of upper workgroup j (from its table), 4 nodes
@@ -1256,20 +1256,22 @@ __device__ __forceinline__ double scan_fwd_body(const SegArgs<T>& a, int wg, int
 // separate instance, so that the plain backward kernel carries none of it.
 template <typename T, int NB, bool UP>
 __global__ __launch_bounds__(kSegThreads) void scan_bwd_kernel(SegArgs<T> a) {
-  if (UP && (int)blockIdx.x >= a.n_main) {  // local parts of upper workgroup j
-    const DevCtl c = a.close ? bwd_ctl_peek(a) : a.ctl[0];
-    if (c.done) return;
-    const int j = (int)blockIdx.x - a.n_main;
+  const int wg = (int)blockIdx.x;
+  if (UP && wg >= a.n_main) {  // local parts of upper workgroup j
+    const int j = wg - a.n_main;
+    const int tree = a.up_plan[(size_t)j * a.up_plan_stride + kPlanTree];
+    const DevCtl c = a.close ? bwd_ctl_peek(a, tree) : a.ctl[tree];
+    if (c.done) return;  // so do the tree's bottom workgroups: no arrivals
     scan_local_up<T>(a, j, c.iter, (T)c.beta, (T)c.pw_scale);
     scan_cascade<T>(a, j, j);
     return;
   }
-  const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
-  const DevCtl c = bwd_ctl(a, tree);
+  const int tree = a.wgtree ? a.wgtree[wg] : 0;  // a workgroup never spans two trees
+  const DevCtl c = bwd_ctl(a, tree, wg);
   if (c.done) return;
-  scan_bwd_body<T, NB>(a, blockIdx.x, c.iter, (T)c.beta, (T)c.pw_scale);
+  scan_bwd_body<T, NB>(a, wg, c.iter, (T)c.beta, (T)c.pw_scale);
   if (UP) {  // the levels above, in this launch
-    const int2 p = a.up_par[blockIdx.x];
+    const int2 p = a.up_par[wg];
     scan_cascade<T>(a, p.x, p.y);
   }
 }

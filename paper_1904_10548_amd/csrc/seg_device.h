@@ -12,15 +12,16 @@ namespace {
 // Control state of a backward launch's tree: read from ctl, or, in the first
 // backward launch of an iteration that closes the previous one, advanced from
 // ctl_prev by every workgroup alike and written (with the residual history
-// entry) by the tree's first workgroup of the launch.
+// entry) by the tree's first workgroup (wg: index among the level's) of the
+// launch.
 template <typename T>
-__device__ inline DevCtl bwd_ctl(const SegArgs<T>& a, int tree) {
+__device__ inline DevCtl bwd_ctl(const SegArgs<T>& a, int tree, int wg) {
   if (!a.close) return a.ctl[tree];
   const DevCtl p = a.ctl_prev[tree];
   bool record;
   double res = 0.0;
   const DevCtl n = ctl_advance(p, &record, &res);
-  const bool writer = blockIdx.x == 0 || (a.wgtree && a.wgtree[blockIdx.x - 1] != tree);
+  const bool writer = wg == 0 || (a.wgtree && a.wgtree[wg - 1] != tree);
   if (writer && threadIdx.x == 0) {
     a.ctl[tree] = n;
     if (record) a.hist[(size_t)tree * a.hist_stride + p.iter] = res;
@@ -28,14 +29,13 @@ __device__ inline DevCtl bwd_ctl(const SegArgs<T>& a, int tree) {
   return n;
 }
 
-// The state of a single tree's first backward launch as every workgroup
-// advances it (bwd_ctl without the write: for workgroups that are not the
-// tree's first).
+// The state of a tree's first backward launch as every workgroup advances it
+// (bwd_ctl without the write: for workgroups that are not the tree's first).
 template <typename T>
-__device__ inline DevCtl bwd_ctl_peek(const SegArgs<T>& a) {
+__device__ inline DevCtl bwd_ctl_peek(const SegArgs<T>& a, int tree) {
   bool record;
   double res = 0.0;
-  return ctl_advance(a.ctl_prev[0], &record, &res);
+  return ctl_advance(a.ctl_prev[tree], &record, &res);
 }
 
 template <typename T>

@@ -440,7 +440,7 @@ __device__ __forceinline__ void seg_bwd_body(const SegArgs<T>& a, int wg, int it
 template <typename T, int NB, bool PROJ>
 __global__ __launch_bounds__(kSegThreads) void seg_bwd_kernel(SegArgs<T> a) {
   const int tree = a.wgtree ? a.wgtree[blockIdx.x] : 0;  // a workgroup never spans two trees
-  const DevCtl c = bwd_ctl(a, tree);
+  const DevCtl c = bwd_ctl(a, tree, (int)blockIdx.x);
   if (c.done) return;
   seg_bwd_body<T, NB, PROJ>(a, blockIdx.x, c.iter, (T)c.beta, (T)c.pw_scale);
 }

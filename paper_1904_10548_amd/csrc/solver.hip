@@ -1621,12 +1621,12 @@ void free_up(Slot& sl) {
   sl.n_up = 0;
 }
 
-// Light upper levels, where they apply (scan form, one tree, two levels or
-// more, and the upper workgroups' work fits the LDS): per upper level the most
-// nodes one workgroup holds, and the tables of the bottom launch that runs
-// them (SegArgs::n_main): upper workgroups numbered from the lowest upper
-// level up, each with its static table (nodes, children, the upper
-// workgroups above it), the upper workgroups above each bottom workgroup, the
+// Light upper levels, where they apply (scan form, two levels or more, and
+// the upper workgroups' work fits the LDS): per upper level the most nodes
+// one workgroup holds, and the tables of the bottom launch that runs them
+// (SegArgs::n_main): upper workgroups numbered from the lowest upper level
+// up, each with its static table (nodes, children, the upper workgroups above
+// it, its tree), the upper workgroups above each bottom workgroup, the
 // arrivals that complete each upper workgroup (its child workgroups and its
 // local part) and their counters.  Otherwise the slot runs every
 // level with the full kernel.
@@ -1646,8 +1646,8 @@ void setup_top_light(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
                                   std::to_string(kSegNbMax) + " nodes per stage need light "
                                   "upper levels, which do not apply here (" + why + ")"};
   };
-  if (!sl.top_light || !sl.scan || t.ntrees != 1 || nl < 2) {
-    refuse("scan form, one tree, two levels or more");
+  if (!sl.top_light || !sl.scan || nl < 2) {
+    refuse("scan form, two levels or more");
     return;
   }
   std::vector<std::vector<std::pair<int, int>>> rp(nl);
@@ -1736,6 +1736,12 @@ void setup_top_light(tapg_solver_s* S, const TreeHost& t, Slot& sl) {
       if (l > 0) count_arrivals(par);
       P[kPlanPar0] = par.x;
       P[kPlanPar1] = par.y;
+      {  // the tree of its first node (level ranges never span two trees)
+        const int n0 = rg[0].first;
+        int k = 0;
+        while (k + 1 < t.ntrees && t.seg_begin(sl.plans[l].s_begin, k + 1) <= n0) ++k;
+        P[kPlanTree] = k;
+      }
       int* off = P + kPlanOff;
       int* node = off + nst + 1;
       int* clo = node + nw;
@@ -2529,10 +2535,10 @@ double autotune_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters, i
     }
   }
   sl.fwd_group = bfg;
-  // light upper levels (scan form, one tree): they change what the levels
-  // above the bottom one cost, so every plan is timed again with them
+  // light upper levels (scan form): they change what the levels above the
+  // bottom one cost, so every plan is timed again with them
   bool btop = top_env;
-  if (bscan && t.ntrees == 1 && !top_forced) {
+  if (bscan && !top_forced) {
     for (size_t i = 0; i < cands.size(); ++i) {
       sl.top_light = true;
       build_levels(S, t, sl, cands[i]);

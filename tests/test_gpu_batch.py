@@ -26,7 +26,7 @@ SHAPES = [(2, 4), (3, 3), ("irregular", 3, 20), (1, 1), (2, 8)]
 
 @pytest.fixture(autouse=True)
 def _default_schedule():
-    for k in ("TAPG_LEVELS", "TAPG_PROJ", "TAPG_CHAIN", "TAPG_SCAN", "TAPG_FWD_GROUP"):
+    for k in ("TAPG_LEVELS", "TAPG_PROJ", "TAPG_CHAIN", "TAPG_SCAN", "TAPG_FWD_GROUP", "TAPG_TOP"):
         os.environ.pop(k, None)
     os.environ["TAPG_USE_GRAPH"] = "1"
     os.environ["TAPG_SEGMENTS"] = "1"
@@ -46,23 +46,37 @@ def _gamma_for(batch):
     return 0.9 / max(Ls)
 
 
-@pytest.mark.parametrize("scan,fwd_group", [(None, None), ("1", None), ("1", "1")])
-def test_batch_fixed_iterations_matches_oracle_per_tree(scan, fwd_group):
+def _force(scan=None, fwd_group=None, top=None, levels="0:1,2:1,3:1"):
+    """Schedule switches; light upper levels come with a plan of three levels
+    (the default plan of a small forest may have one)."""
+    for k, v in (("TAPG_SCAN", scan), ("TAPG_FWD_GROUP", fwd_group), ("TAPG_TOP", top),
+                 ("TAPG_LEVELS", levels if top else None)):
+        if v:
+            os.environ[k] = v
+
+
+@pytest.mark.parametrize("scan,fwd_group,top", [(None, None, None), ("1", None, None),
+                                                ("1", "1", None), ("1", None, "1"),
+                                                ("1", "1", "1")])
+def test_batch_fixed_iterations_matches_oracle_per_tree(scan, fwd_group, top):
     """Every tree of a forest against its own oracle run: the default form, the
-    scan form, and the scan form's forward launch on one leaf per workgroup."""
-    if scan:
-        os.environ["TAPG_SCAN"] = scan
-    if fwd_group:
-        os.environ["TAPG_FWD_GROUP"] = fwd_group
+    scan form, the scan form's forward launch on one leaf per workgroup, and
+    the scan form with light upper levels (every tree's upper levels inside
+    the bottom level's backward launch)."""
+    _force(scan, fwd_group, top)
     batch = tiny_batch(SHAPES)
     gamma = _gamma_for(batch)
     iters = 300
-    say("batch fixed", [P.tree.K for P in batch], "iters", iters, "scan", scan, "fwd", fwd_group)
+    say("batch fixed", [P.tree.K for P in batch], "iters", iters, "scan", scan, "fwd", fwd_group,
+        "top", top)
     with make_solver(batch[0], gamma=gamma, tol=0.0, max_iter=iters, check_every=64) as S:
         trees = [add_tree(S, P) for P in batch]
         st, u0s, res = S.batch_solve(trees, [P.p for P in batch], [P.q for P in batch])
         out = [(S.primal(t), S.dual(t), tapg.tapg_residual_history(S.h, t, iters)) for t in trees]
+        form = tapg.tapg_sweep_form(S.h, trees)
     assert st == tapg.TAPG_OK
+    if top:  # one backward launch per iteration
+        assert form[0] == "scan" and form[1] == 1
     for P, r, u0, ((u, x), y, hist) in zip(batch, res, u0s, out):
         ref = O.apg(P, gamma, O.StageFactors(P.net, P.weights.W_u, P.tree), iters)
         assert r.iters == iters
@@ -79,11 +93,14 @@ def test_batch_fixed_iterations_matches_oracle_per_tree(scan, fwd_group):
 
 
 @pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
-@pytest.mark.parametrize("check_every", [50, 7])
-def test_batch_equals_single_tree_solves_to_tolerance(precision, check_every):
+@pytest.mark.parametrize("check_every,top", [(50, None), (7, None), (7, "1")])
+def test_batch_equals_single_tree_solves_to_tolerance(precision, check_every, top):
     """Auto step size per tree and a tolerance: every tree stops at the same
     iteration as its own tapg_solve, with the same iterate; trees stop at
-    different iterations inside the batch (and inside runs of odd length)."""
+    different iterations inside the batch (and inside runs of odd length),
+    also with light upper levels (scan form), where a stopped tree's upper
+    workgroups take no part in the launches that follow."""
+    _force(scan=top, top=top)
     batch = tiny_batch(SHAPES, seed=23)
     # FP32 sweeps: a tolerance above their floor (the FP64 residual of an FP32
     # dual cannot resolve steps below the dual's rounding over gamma)
@@ -137,16 +154,14 @@ def test_batch_warm_start_and_resolve():
         assert abs(r1[k].cost - single[k].cost) <= 1e-9 * max(1.0, abs(single[k].cost))
 
 
-@pytest.mark.parametrize("scan,fwd_group", [(None, None), ("1", "2")])
-def test_batch_of_full_size_trees_fp32(scan, fwd_group):
+@pytest.mark.parametrize("scan,fwd_group,top", [(None, None, None), ("1", "2", None),
+                                                ("1", "2", "1")])
+def test_batch_of_full_size_trees_fp32(scan, fwd_group, top):
     """Three Barcelona-sized trees of the 64-tree configuration, FP32 sweeps
-    (the default form, and the scan form with its forward launch on pairs of
-    leaves): each tree's cost after a fixed number of iterations within 1e-4 of
-    the FP64 oracle's."""
-    if scan:
-        os.environ["TAPG_SCAN"] = scan
-    if fwd_group:
-        os.environ["TAPG_FWD_GROUP"] = fwd_group
+    (the default form, the scan form with its forward launch on pairs of
+    leaves, and that with light upper levels): each tree's cost after a fixed
+    number of iterations within 1e-4 of the FP64 oracle's."""
+    _force(scan, fwd_group, top, levels="0:1,2:1,5:2,7:4")
     batch = [ds.config_problem("batch64", i) for i in range(3)]
     iters = 30
     gamma = 0.0
