@@ -16,11 +16,14 @@
 // j_n = kappa_n - Pi kappa_n + P_n, and z_n = Pi u_anc + Pi j_n / p_n.)
 // Only vector additions remain on the chain from stage to stage; the products
 // with Pi, B and B' are per node.  A workgroup therefore takes its stages in
-// chunks of 16 node-stages (16 / NB stages of NB nodes): each per-node product
+// chunks of 8 node-stages (8 / NB stages of NB nodes): each per-node product
 // runs over the whole chunk at once, spread over all 512 threads, and each
 // chain is walked by one thread per vector component, with the values of the
 // neighbouring stage in registers.  A chunk costs five barriers (backward) or
-// four (forward) however many stages it holds.
+// four (forward) however many stages it holds.  Eight is the fewest the
+// thread mapping allows (one x-element per thread); it keeps the next chunk's
+// prefetched inputs small enough for FP32 kernels to fit two workgroups per
+// compute unit, and shortens the wait on each chunk's loads in FP64 as well.
 //
 // The workgroups, levels and node ranges are those of the segment kernels, so
 // the schedule and the forest layout are shared (the forward launch may also
@@ -34,7 +37,7 @@ namespace tapg {
 
 namespace {
 
-constexpr int kCN = 16;   // node-stages per chunk
+constexpr int kCN = 8;    // node-stages per chunk
 constexpr int kSU = 128;  // padded u-dimension of the segment layout
 constexpr int kSX = 64;   // x rows in LDS (nx <= 64 on this path)
 constexpr int kQU = kCN * kSU / kSegThreads;  // u-elements per thread and chunk
