@@ -320,8 +320,10 @@ void tapg_server_destroy(tapg_server srv);
  * spread of its cost constants, on the tree (ntrees = 1) or on the batch's forest
  * (ntrees > 1, as tapg_batch_solve would form it), and keeps the fastest for it
  * and for every later tree or batch of the same shape on this solver (TAPG_LEVELS,
- * if set, still wins).  *ms_per_iter (may be NULL): the winner's time per
- * iteration; *candidates (may be NULL): plans timed.  The timing runs overwrite
+ * if set, still wins).  Where the scan form applies, every plan is timed in
+ * both forms, in the scan form with each grouping of its forward launch, and
+ * then (scan form chosen) with light upper levels.  *ms_per_iter (may be NULL):
+ * the winner's time per iteration; *candidates (may be NULL): schedules timed.  The timing runs overwrite
  * the tree's iterates (solve again before querying).  TAPG_EINVAL when the
  * segment kernels do not apply. */
 tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees, int iters,
@@ -334,8 +336,7 @@ tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees
  * factors unrolled into subtree and root-path sums) applies when A = I and the
  * projector form applies; untuned trees and forests use the segment form
  * (TAPG_SCAN=1: the scan form), and tapg_autotune keeps whichever form is
- * faster for the shape (measured: scan for a single 128-scenario tree, segment
- * for wide trees and forests).
+ * faster for the shape.
  * TAPG_ESTATE before the first solve or autotune of that tree or batch. */
 /* The schedule of a tree (ntrees = 1) or of a batch's forest as its last
  * solve or autotune left it, written to buf (cap bytes, NUL-terminated) as the

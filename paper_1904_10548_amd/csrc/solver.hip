@@ -2496,44 +2496,38 @@ double autotune_impl(tapg_solver_s* S, const TreeHost& t, Slot& sl, int iters, i
   const bool top_forced = te && te[0];
   const bool top_env = top_forced && te[0] == '1';
   sl.top_light = top_env;
-  // both sweep forms where the scan form applies: it wins on narrow trees
-  // (fewer launches, shorter chains), the segment form on wide forests (two
-  // workgroups per compute unit against one)
+  // both sweep forms where the scan form applies: the scan form has fewer
+  // launches and shorter chains, the segment form fits more workgroups per
+  // compute unit in FP64; which wins depends on the shape
   std::vector<bool> forms = S->scan ? std::vector<bool>{true, false} : std::vector<bool>{false};
-  if (ncand) *ncand = (int)(cands.size() * forms.size());
+  if (ncand) *ncand = (int)(cands.size() * (S->scan ? 5 : 1));
+  // the scan form's forward launch: the bottom level's workgroups, or groups
+  // of 1, 2 or 4 last-stage nodes (more workgroups, each walking its
+  // ancestors); each grouping with every plan, since the best plan differs
+  // between groupings and a grouping can reverse the choice of form
+  const int fg0 = sl.fwd_group;
   double best = 1e300;
   size_t bi = 0;
   bool bscan = false;
+  int bfg = fg0;
   for (bool form : forms) {
     sl.scan = form;
-    for (size_t i = 0; i < cands.size(); ++i) {
-      build_levels(S, t, sl, cands[i]);
-      const double ms = time_levels<T>(S, t, sl, iters);
-      if (ms < best) {
-        best = ms;
-        bi = i;
-        bscan = form;
+    const std::vector<int> groups = form ? std::vector<int>{0, 1, 2, 4} : std::vector<int>{fg0};
+    for (int fg : groups) {
+      sl.fwd_group = fg;
+      for (size_t i = 0; i < cands.size(); ++i) {
+        build_levels(S, t, sl, cands[i]);
+        const double ms = time_levels<T>(S, t, sl, iters);
+        if (ms < best) {
+          best = ms;
+          bi = i;
+          bscan = form;
+          bfg = form ? fg : fg0;
+        }
       }
     }
   }
   sl.scan = bscan;
-  // the scan form's forward launch: the bottom level's workgroups, or groups of
-  // 1, 2 or 4 last-stage nodes (more workgroups, each walking its ancestors)
-  int bfg = sl.fwd_group;  // the grouping the plans were timed with
-  if (bscan) {
-    const int fg0 = sl.fwd_group;
-    for (int fg : {0, 1, 2, 4}) {
-      if (fg == fg0) continue;
-      sl.fwd_group = fg;
-      build_levels(S, t, sl, cands[bi]);
-      const double ms = time_levels<T>(S, t, sl, iters);
-      if (ncand) ++*ncand;
-      if (ms < best) {
-        best = ms;
-        bfg = fg;
-      }
-    }
-  }
   sl.fwd_group = bfg;
   // light upper levels (scan form): they change what the levels above the
   // bottom one cost, so every plan is timed again with them
