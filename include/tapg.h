@@ -334,9 +334,9 @@ tapg_status tapg_autotune(tapg_solver solver, int ntrees, const tapg_tree* trees
  * TAPG_FORM_*, *bwd_launches (may be NULL) the backward launches per
  * iteration.  The scan form (Sec. 4.4 recursions with A = I and the projector
  * factors unrolled into subtree and root-path sums) applies when A = I and the
- * projector form applies; untuned trees and forests use the segment form
- * (TAPG_SCAN=1: the scan form), and tapg_autotune keeps whichever form is
- * faster for the shape.
+ * projector form applies; untuned trees and forests then use it (TAPG_SCAN=0:
+ * the segment form), and tapg_autotune keeps whichever form is faster for the
+ * shape.
  * TAPG_ESTATE before the first solve or autotune of that tree or batch. */
 /* The schedule of a tree (ntrees = 1) or of a batch's forest as its last
  * solve or autotune left it, written to buf (cap bytes, NUL-terminated) as the

@@ -1376,7 +1376,7 @@ void dev_init(tapg_solver_s* S) {
     }
     const char* se = std::getenv("TAPG_SCAN");
     S->scan = S->proj && ai && h.nx <= 64 && !(se && se[0] == '0');
-    S->scan_default = S->scan && se && se[0] == '1';
+    S->scan_default = S->scan;  // untuned shapes: the scan form wherever it applies
   }
   if (S->stream == nullptr) {
     TAPG_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));

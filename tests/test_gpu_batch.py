@@ -55,14 +55,14 @@ def _force(scan=None, fwd_group=None, top=None, levels="0:1,2:1,3:1"):
             os.environ[k] = v
 
 
-@pytest.mark.parametrize("scan,fwd_group,top", [(None, None, None), ("1", None, None),
+@pytest.mark.parametrize("scan,fwd_group,top", [("0", None, None), (None, None, None),
                                                 ("1", "1", None), ("1", None, "1"),
                                                 ("1", "1", "1")])
 def test_batch_fixed_iterations_matches_oracle_per_tree(scan, fwd_group, top):
-    """Every tree of a forest against its own oracle run: the default form, the
-    scan form, the scan form's forward launch on one leaf per workgroup, and
-    the scan form with light upper levels (every tree's upper levels inside
-    the bottom level's backward launch)."""
+    """Every tree of a forest against its own oracle run: the segment form,
+    the default (scan) form, the scan form's forward launch on one leaf per
+    workgroup, and the scan form with light upper levels (every tree's upper
+    levels inside the bottom level's backward launch)."""
     _force(scan, fwd_group, top)
     batch = tiny_batch(SHAPES)
     gamma = _gamma_for(batch)
@@ -93,14 +93,14 @@ def test_batch_fixed_iterations_matches_oracle_per_tree(scan, fwd_group, top):
 
 
 @pytest.mark.parametrize("precision", [tapg.TAPG_FP64, tapg.TAPG_FP32])
-@pytest.mark.parametrize("check_every,top", [(50, None), (7, None), (7, "1")])
-def test_batch_equals_single_tree_solves_to_tolerance(precision, check_every, top):
+@pytest.mark.parametrize("check_every,scan,top", [(50, "0", None), (7, None, None), (7, "1", "1")])
+def test_batch_equals_single_tree_solves_to_tolerance(precision, check_every, scan, top):
     """Auto step size per tree and a tolerance: every tree stops at the same
     iteration as its own tapg_solve, with the same iterate; trees stop at
     different iterations inside the batch (and inside runs of odd length),
     also with light upper levels (scan form), where a stopped tree's upper
     workgroups take no part in the launches that follow."""
-    _force(scan=top, top=top)
+    _force(scan=scan, top=top)
     batch = tiny_batch(SHAPES, seed=23)
     # FP32 sweeps: a tolerance above their floor (the FP64 residual of an FP32
     # dual cannot resolve steps below the dual's rounding over gamma)
@@ -154,11 +154,11 @@ def test_batch_warm_start_and_resolve():
         assert abs(r1[k].cost - single[k].cost) <= 1e-9 * max(1.0, abs(single[k].cost))
 
 
-@pytest.mark.parametrize("scan,fwd_group,top", [(None, None, None), ("1", "2", None),
+@pytest.mark.parametrize("scan,fwd_group,top", [("0", None, None), ("1", "2", None),
                                                 ("1", "2", "1")])
 def test_batch_of_full_size_trees_fp32(scan, fwd_group, top):
     """Three Barcelona-sized trees of the 64-tree configuration, FP32 sweeps
-    (the default form, the scan form with its forward launch on pairs of
+    (the segment form, the scan form with its forward launch on pairs of
     leaves, and that with light upper levels): each tree's cost after a fixed
     number of iterations within 1e-4 of the FP64 oracle's."""
     _force(scan, fwd_group, top, levels="0:1,2:1,5:2,7:4")
