@@ -328,5 +328,28 @@ void launch_widen(const T* src, double* dst, size_t n, hipStream_t st);
 template <typename T>
 void launch_copy_rows(const T* src, int ld_src, T* dst, int ld_dst, const int* idx, int rows,
                       int width, bool scatter, hipStream_t st);
+// Several arrays gathered or scattered by the same row map in one launch
+// (elements of 4 or 8 bytes, copied bit for bit).
+constexpr int kRowArrays = 8;
+struct RowCopies {
+  const void* src[kRowArrays];
+  void* dst[kRowArrays];
+  int ld_src[kRowArrays], ld_dst[kRowArrays], width[kRowArrays], bytes[kRowArrays];
+  int n = 0;
+  template <typename E>
+  void add(const E* s, int lds, E* d, int ldd, int w) {
+    static_assert(sizeof(E) == 4 || sizeof(E) == 8, "row copies move 4- or 8-byte elements");
+    if (n >= kRowArrays) throw Fail{TAPG_EINVAL, "row copies: too many arrays in one launch"};
+    src[n] = s;
+    dst[n] = d;
+    ld_src[n] = lds;
+    ld_dst[n] = ldd;
+    width[n] = w;
+    bytes[n] = (int)sizeof(E);
+    ++n;
+  }
+};
+void launch_copy_row_sets(const RowCopies& c, const int* idx, int rows, bool scatter,
+                          hipStream_t st);
 
 }  // namespace tapg

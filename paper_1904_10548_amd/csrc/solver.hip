@@ -688,9 +688,10 @@ void upload_pq(tapg_solver_s* S, Slot& sl, const std::vector<double>& pq64, hipS
   TAPG_HIP(hipMemcpyAsync(sl.d_zr, zr.data(), zr.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
-// Per-solve data step of a slot's K nodes (kappa, g; kperp for the scan form).
+// Per-solve data step of a slot's K nodes (kappa, g; kperp for the scan form,
+// or with all_forms wherever the solver allows the scan form).
 template <typename T>
-void data_step(tapg_solver_s* S, Slot& sl, int K, hipStream_t st) {
+void data_step(tapg_solver_s* S, Slot& sl, int K, hipStream_t st, bool all_forms = false) {
   const NetworkHost& h = S->net;
   launch_data_step<T>(K, h.nx, h.nu, h.nd, S->LDX, S->LDU, (const int*)sl.d_stage,
                       (const double*)sl.d_prob64, (const double*)sl.d_demand,
@@ -699,7 +700,8 @@ void data_step(tapg_solver_s* S, Slot& sl, int K, hipStream_t st) {
                       (const double*)S->d64.F, (const double*)S->dx.alpha0,
                       (const double*)S->dx.cE, S->cfg.W_alpha, static_cast<T*>(sl.d_kappa),
                       static_cast<T*>(sl.d_g), h.ns, (const double*)S->dx.Gm,
-                      (const double*)S->dx.E, sl.scan ? static_cast<T*>(sl.d_kperp) : nullptr,
+                      (const double*)S->dx.E,
+                      (sl.scan || (all_forms && S->scan)) ? static_cast<T*>(sl.d_kperp) : nullptr,
                       st);
 }
 
@@ -2070,24 +2072,6 @@ void forest_data_step(tapg_solver_s* S, const TreeHost& f, Slot& sl) {
   TAPG_HIP(hipGetLastError());
 }
 
-// Per-tree cost and violations of a forest's current primal into B.d_red.
-template <typename T>
-void forest_cost(tapg_solver_s* S, const TreeHost& f, Slot& sl, Batch& B) {
-  const NetworkHost& h = S->net;
-  launch_cost<T>(f.K, h.nx, h.nu, h.nd, h.ns, S->LDX, S->LDU, (const int*)sl.d_anc,
-                 (const double*)sl.d_prob64, (const double*)sl.d_demand,
-                 (const double*)sl.d_price, (const T*)sl.d_u, (const T*)sl.d_x,
-                 (const double*)sl.d_pq64, (const double*)S->d64.A, (const double*)S->d64.B,
-                 (const double*)S->dx.Gd, (const double*)S->dx.E, (const double*)S->dx.Ed,
-                 (const double*)S->dx.Wu, (const double*)S->dx.alpha0, (const double*)S->dx.cE,
-                 (const double*)S->d64.xmin, (const double*)S->d64.xmax,
-                 (const double*)S->d64.xs, (const double*)S->d64.umin,
-                 (const double*)S->d64.umax, S->cfg.W_alpha, S->cfg.W_x, S->cfg.W_s, sl.d_part,
-                 S->dx.red, S->stream);
-  launch_cost_reduce_forest(sl.d_part, B.d_tstart, f.N, f.ntrees, B.d_red, S->stream);
-  TAPG_HIP(hipGetLastError());
-}
-
 template <typename T>
 void batch_impl(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
                 const std::vector<Slot*>& own, const double* const* p, const double* const* q,
@@ -2269,6 +2253,12 @@ void live_init_impl(tapg_solver_s* S, LiveTree& j) {
   o.last_pq.assign((size_t)S->LDX + S->LDU, 0.0);
   for (int i = 0; i < S->net.nx; ++i) o.last_pq[i] = j.p[i];
   for (int i = 0; i < S->net.nu; ++i) o.last_pq[S->LDX + i] = j.q[i];
+  // the tree's data step and (p, q) in its own slot, once per request: every
+  // forest it runs in gathers the rows, and its cost is evaluated there
+  data_step<T>(S, o, j.t->K, st, true);
+  TAPG_HIP(hipMemcpyAsync(o.d_pq64, o.last_pq.data(), o.last_pq.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+  TAPG_HIP(hipStreamSynchronize(st));
   o.gap_valid = false;
   j.ctl = DevCtl{};
   j.ctl.max_iter = S->cfg.max_iter;
@@ -2291,15 +2281,6 @@ void live_enter_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
   Batch& B = get_batch(S, live_trees(js), false);
   const TreeHost& f = B.forest;
   Slot& sl = dev_slot(S, f);
-  for (int k = 0; k < nt; ++k) {  // demand and price from each tree's own slot
-    const int* idx = B.d_map + B.map_off[k];
-    const Slot& o = *js[k]->own;
-    const int nd = js[k]->t->nd;
-    launch_copy_rows<double>(static_cast<const double*>(o.d_demand), nd,
-                             static_cast<double*>(sl.d_demand), nd, idx, js[k]->t->K, nd, true, st);
-    launch_copy_rows<double>(static_cast<const double*>(o.d_price), 1,
-                             static_cast<double*>(sl.d_price), 1, idx, js[k]->t->K, 1, true, st);
-  }
   if (!sl.segmented)
     throw Fail{TAPG_EINVAL, "batched solves need the segment kernels (nx, nu <= 128, sparse B)"};
   std::vector<double> pq64((size_t)nt * PQ, 0.0);
@@ -2312,16 +2293,25 @@ void live_enter_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
   }
   upload_pq<T>(S, sl, pq64, st);
   TAPG_HIP(hipMemcpyAsync(sl.d_ctl, c.data(), c.size() * sizeof(DevCtl), hipMemcpyHostToDevice, st));
-  for (int k = 0; k < nt; ++k) {  // both dual buffers, as the tree left them
+  // each tree's rows from its own slot, one launch per tree: demand and price,
+  // both dual buffers as the tree left them, and its data step (kappa, g,
+  // kperp)
+  for (int k = 0; k < nt; ++k) {
     const int* idx = B.d_map + B.map_off[k];
     const Slot& o = *js[k]->own;
-    launch_copy_rows<T>(static_cast<const T*>(o.d_Y0), LDY, static_cast<T*>(sl.d_Y0), LDY, idx,
-                        js[k]->t->K, LDY, true, st);
-    launch_copy_rows<T>(static_cast<const T*>(o.d_Y1), LDY, static_cast<T*>(sl.d_Y1), LDY, idx,
-                        js[k]->t->K, LDY, true, st);
+    const int nd = js[k]->t->nd;
+    RowCopies rc;
+    rc.add(static_cast<const double*>(o.d_demand), nd, static_cast<double*>(sl.d_demand), nd, nd);
+    rc.add(static_cast<const double*>(o.d_price), 1, static_cast<double*>(sl.d_price), 1, 1);
+    rc.add(static_cast<const T*>(o.d_Y0), LDY, static_cast<T*>(sl.d_Y0), LDY, LDY);
+    rc.add(static_cast<const T*>(o.d_Y1), LDY, static_cast<T*>(sl.d_Y1), LDY, LDY);
+    rc.add(static_cast<const T*>(o.d_kappa), LDU, static_cast<T*>(sl.d_kappa), LDU, LDU);
+    rc.add(static_cast<const T*>(o.d_g), LDX, static_cast<T*>(sl.d_g), LDX, LDX);
+    if (sl.scan)
+      rc.add(static_cast<const T*>(o.d_kperp), LDU, static_cast<T*>(sl.d_kperp), LDU, LDU);
+    launch_copy_row_sets(rc, idx, js[k]->t->K, true, st);
   }
   TAPG_HIP(hipGetLastError());
-  forest_data_step<T>(S, f, sl);
   const int chunk = std::max(1, std::min(S->cfg.check_every, S->cfg.max_iter));
   ensure_graph<T>(S, sl, live_graph_iters(chunk));
   TAPG_HIP(hipStreamSynchronize(st));
@@ -2358,35 +2348,46 @@ void live_leave_impl(tapg_solver_s* S, const std::vector<LiveTree*>& js) {
   hipStream_t st = S->stream;
   const int LDX = S->LDX, LDU = S->LDU, LDY = S->LDY;
   const int nt = (int)js.size();
+  const NetworkHost& h = S->net;
   bool any_done = false;
   for (LiveTree* j : js) any_done = any_done || j->ctl.done;
   std::vector<double> red((size_t)3 * nt, 0.0);
-  if (any_done) {
-    forest_cost<T>(S, B->forest, sl, *B);
-    TAPG_HIP(hipMemcpyAsync(red.data(), B->d_red, red.size() * 8, hipMemcpyDeviceToHost, st));
-  }
   for (int k = 0; k < nt; ++k) {
     LiveTree& j = *js[k];
     Slot& o = *j.own;
     const int* idx = B->d_map + B->map_off[k];
     const int Kk = j.t->K;
-    launch_copy_rows<T>(static_cast<const T*>(sl.d_Y0), LDY, static_cast<T*>(o.d_Y0), LDY, idx,
-                        Kk, LDY, false, st);
-    launch_copy_rows<T>(static_cast<const T*>(sl.d_Y1), LDY, static_cast<T*>(o.d_Y1), LDY, idx,
-                        Kk, LDY, false, st);
+    {  // both dual buffers and, for a stopped tree, its primal: one launch
+      RowCopies rc;
+      rc.add(static_cast<const T*>(sl.d_Y0), LDY, static_cast<T*>(o.d_Y0), LDY, LDY);
+      rc.add(static_cast<const T*>(sl.d_Y1), LDY, static_cast<T*>(o.d_Y1), LDY, LDY);
+      if (j.ctl.done) {
+        rc.add(static_cast<const T*>(sl.d_u), LDU, static_cast<T*>(o.d_u), LDU, LDU);
+        rc.add(static_cast<const T*>(sl.d_x), LDX, static_cast<T*>(o.d_x), LDX, LDX);
+      }
+      launch_copy_row_sets(rc, idx, Kk, false, st);
+    }
     const int a = std::min(j.it0, o.hist_cap), b = std::min(j.ctl.iter, o.hist_cap);
     if (b > a)
       TAPG_HIP(hipMemcpyAsync(o.d_hist + a, sl.d_hist + (size_t)k * sl.hist_cap + a,
                               (size_t)(b - a) * 8, hipMemcpyDeviceToDevice, st));
     o.last_iter_parity = j.ctl.iter & 1;
-    if (j.ctl.done) {
-      launch_copy_rows<T>(static_cast<const T*>(sl.d_u), LDU, static_cast<T*>(o.d_u), LDU, idx,
-                          Kk, LDU, false, st);
-      launch_copy_rows<T>(static_cast<const T*>(sl.d_x), LDX, static_cast<T*>(o.d_x), LDX, idx,
-                          Kk, LDX, false, st);
+    if (j.ctl.done) {  // its cost and violations in its own slot (into B.d_red)
+      launch_cost<T>(Kk, h.nx, h.nu, h.nd, h.ns, LDX, LDU, (const int*)o.d_anc,
+                     (const double*)o.d_prob64, (const double*)o.d_demand,
+                     (const double*)o.d_price, (const T*)o.d_u, (const T*)o.d_x,
+                     (const double*)o.d_pq64, (const double*)S->d64.A, (const double*)S->d64.B,
+                     (const double*)S->dx.Gd, (const double*)S->dx.E, (const double*)S->dx.Ed,
+                     (const double*)S->dx.Wu, (const double*)S->dx.alpha0,
+                     (const double*)S->dx.cE, (const double*)S->d64.xmin,
+                     (const double*)S->d64.xmax, (const double*)S->d64.xs,
+                     (const double*)S->d64.umin, (const double*)S->d64.umax, S->cfg.W_alpha,
+                     S->cfg.W_x, S->cfg.W_s, o.d_part, B->d_red + (size_t)3 * k, st);
     }
   }
   TAPG_HIP(hipGetLastError());
+  if (any_done)
+    TAPG_HIP(hipMemcpyAsync(red.data(), B->d_red, red.size() * 8, hipMemcpyDeviceToHost, st));
   TAPG_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < nt; ++k) {
     LiveTree& j = *js[k];

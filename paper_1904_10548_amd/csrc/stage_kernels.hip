@@ -646,6 +646,25 @@ __global__ __launch_bounds__(kThreads) void copy_rows_kernel(const T* src, int l
   for (int i = threadIdx.x; i < width; i += kThreads) dst[rd * ld_dst + i] = src[rs * ld_src + i];
 }
 
+__global__ __launch_bounds__(kThreads) void copy_row_sets_kernel(RowCopies c, const int* idx,
+                                                                 int rows, int scatter) {
+  const int r = blockIdx.x;
+  if (r >= rows) return;
+  const size_t rs = scatter ? (size_t)r : (size_t)idx[r];
+  const size_t rd = scatter ? (size_t)idx[r] : (size_t)r;
+  for (int q = 0; q < c.n; ++q) {
+    if (c.bytes[q] == 8) {
+      const unsigned long long* s = static_cast<const unsigned long long*>(c.src[q]) + rs * c.ld_src[q];
+      unsigned long long* d = static_cast<unsigned long long*>(c.dst[q]) + rd * c.ld_dst[q];
+      for (int i = threadIdx.x; i < c.width[q]; i += kThreads) d[i] = s[i];
+    } else {
+      const unsigned* s = static_cast<const unsigned*>(c.src[q]) + rs * c.ld_src[q];
+      unsigned* d = static_cast<unsigned*>(c.dst[q]) + rd * c.ld_dst[q];
+      for (int i = threadIdx.x; i < c.width[q]; i += kThreads) d[i] = s[i];
+    }
+  }
+}
+
 // Averaged primal iterate (Sec. 4.3; the averaged sequence of accelerated
 // dual gradient projection): ua = (1 - theta_nu) ua + theta_nu u_hat(w^nu), the
 // same for x, with theta_nu of the iteration that just wrote u and x
@@ -773,6 +792,12 @@ void launch_copy_rows(const T* src, int ld_src, T* dst, int ld_dst, const int* i
   if (rows <= 0) return;
   hipLaunchKernelGGL((copy_rows_kernel<T>), dim3(rows), dim3(kThreads), 0, st, src, ld_src, dst,
                      ld_dst, idx, rows, width, scatter ? 1 : 0);
+}
+void launch_copy_row_sets(const RowCopies& c, const int* idx, int rows, bool scatter,
+                          hipStream_t st) {
+  if (rows <= 0 || c.n == 0) return;
+  hipLaunchKernelGGL(copy_row_sets_kernel, dim3(rows), dim3(kThreads), 0, st, c, idx, rows,
+                     scatter ? 1 : 0);
 }
 template void launch_copy_rows<double>(const double*, int, double*, int, const int*, int, int,
                                        bool, hipStream_t);
