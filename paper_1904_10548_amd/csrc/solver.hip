@@ -139,12 +139,56 @@ std::vector<T> colmajor(const Mat& M, int ld, bool transpose_first) {
   return out;
 }
 
-// Set-up copies are synchronous: the host vectors are often temporaries.
+// Set-up copies (tables, structure) go through a pinned staging buffer of the
+// calling thread: the host vector, often a temporary, is copied there and the
+// device copy is queued on the stream, with no wait.  A staged region is
+// written again only after every device this thread has copied to from the
+// buffer has been synchronised (devices, unlike streams, outlive solvers).
+// Larger copies wait for the stream and copy at once.
+struct UploadStage {
+  static constexpr size_t kCap = 8u << 20;
+  unsigned char* base = nullptr;
+  size_t off = 0;
+  std::vector<int> devices;  // since the last reuse of the buffer
+};
+
+UploadStage& upload_stage() {
+  thread_local UploadStage u;  // left to the process's end (pinned host memory)
+  return u;
+}
+
 template <typename T>
 T* upload(const std::vector<T>& v, hipStream_t st) {
   T* d = dmalloc<T>(v.size());
-  TAPG_HIP(hipStreamSynchronize(st));
-  TAPG_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  const size_t n = v.size() * sizeof(T);
+  if (n == 0) return d;
+  UploadStage& u = upload_stage();
+  if (n > UploadStage::kCap / 4) {
+    TAPG_HIP(hipStreamSynchronize(st));
+    TAPG_HIP(hipMemcpy(d, v.data(), n, hipMemcpyHostToDevice));
+    return d;
+  }
+  if (u.base == nullptr)
+    TAPG_HIP(hipHostMalloc(reinterpret_cast<void**>(&u.base), UploadStage::kCap,
+                           hipHostMallocPortable));
+  size_t at = (u.off + 255) & ~(size_t)255;
+  if (at + n > UploadStage::kCap) {  // reuse: every copy out of the buffer has completed
+    int cur = 0;
+    TAPG_HIP(hipGetDevice(&cur));
+    for (int dev : u.devices) {
+      TAPG_HIP(hipSetDevice(dev));
+      TAPG_HIP(hipDeviceSynchronize());
+    }
+    TAPG_HIP(hipSetDevice(cur));
+    u.devices.clear();
+    at = 0;
+  }
+  int dev = 0;
+  TAPG_HIP(hipGetDevice(&dev));
+  if (std::find(u.devices.begin(), u.devices.end(), dev) == u.devices.end()) u.devices.push_back(dev);
+  std::memcpy(u.base + at, v.data(), n);
+  TAPG_HIP(hipMemcpyAsync(d, u.base + at, n, hipMemcpyHostToDevice, st));
+  u.off = at + n;
   return d;
 }
 
@@ -1606,6 +1650,7 @@ void build_fwd_full(tapg_solver_s* S, const TreeHost& t, Slot& sl, const LevelPl
       L.d_wgtree = upload(wt, st);
     }
   } catch (...) {
+    (void)hipStreamSynchronize(st);  // no queued upload into a block given back
     dfree(L.d_ranges);
     dfree(L.d_wgx);
     dfree(sl.d_own);
@@ -1835,6 +1880,7 @@ void build_levels(tapg_solver_s* S, const TreeHost& t, Slot& sl, const std::vect
       ptot += P.n_wg;
     }
   } catch (...) {
+    (void)hipStreamSynchronize(st);  // no queued upload into a block given back
     for (auto& L : levels) {
       dfree(L.d_ranges);
       dfree(L.d_wgtree);
@@ -1945,6 +1991,7 @@ Slot& dev_slot(tapg_solver_s* S, const TreeHost& t) {
       sl.part_cap = std::max(tot, 4 * K);
       sl.d_part = dmalloc<double>(sl.part_cap);
     } catch (...) {
+      (void)hipStreamSynchronize(st);  // no queued upload into a block given back
       dev_free_slot(sl);
       throw;
     }
@@ -1999,6 +2046,7 @@ Batch& get_batch(tapg_solver_s* S, const std::vector<const TreeHost*>& trees,
       b.d_tstart = upload(b.forest.tstart, st);
       b.d_red = dmalloc<double>((size_t)3 * nt);
     } catch (...) {
+      (void)hipStreamSynchronize(S->stream);  // no queued upload into a block given back
       dfree(b.d_map); dfree(b.d_tstart); dfree(b.d_red);
       throw;
     }
