@@ -62,11 +62,24 @@ def kernel_prefix(form):
     return "scan" if form == "scan" else "seg"
 
 
-def measured_traffic(workload, precision, form, spec=None):
-    """HBM bytes per launch of each sweep kind from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, if it was taken on this workload, sweep form
-    and schedule (the settings ``spec``) with the current kernel sources
-    (else None)."""
+# The schedule settings that shape each sweep's launches: the backward
+# launches do not depend on the forward launch's grouping, nor the forward
+# launch on light upper levels.
+SPEC_KEYS = {"bwd": ("TAPG_SCAN", "TAPG_LEVELS", "TAPG_TOP"),
+             "fwd": ("TAPG_SCAN", "TAPG_LEVELS", "TAPG_FWD_GROUP")}
+
+
+def _spec_items(spec, kind):
+    d = dict(kv.split("=", 1) for kv in spec.split())
+    return {k: d.get(k) for k in SPEC_KEYS[kind]}
+
+
+def measured_traffic(workload, precision, form, spec=None, kind=None):
+    """HBM bytes per launch of each sweep kind (or of ``kind`` alone) from the
+    committed FETCH_SIZE / WRITE_SIZE counter summary, if it was taken on this
+    workload, sweep form and schedule (the settings ``spec``; with ``kind``
+    only those that shape that sweep's launches) with the current kernel
+    sources (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles",
                         f"{kernel_prefix(form)}_sweeps_{workload}_{precision}_hbm_counters.md")
@@ -82,8 +95,13 @@ def measured_traffic(workload, precision, form, spec=None):
             sha.update(fh.read())
     if data.get("kernel_sources_sha256") != sha.hexdigest():
         return None
-    if spec is not None and sorted(data.get("spec", "").split()) != sorted(spec.split()):
-        return None  # taken under another schedule: other launches
+    taken = data.get("spec", "")
+    if kind is not None:
+        if spec is not None and _spec_items(taken, kind) != _spec_items(spec, kind):
+            return None  # taken under another schedule: other launches
+        return data["bytes_per_launch"].get(kind)
+    if spec is not None and sorted(taken.split()) != sorted(spec.split()):
+        return None
     return data["bytes_per_launch"]
 
 
@@ -270,8 +288,8 @@ def main_single(args, ds, tapg, have_torch):
         # measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
         # WRITE_SIZE, calibrated against a plain copy) from the committed
         # counter summary, when it matches these kernel sources
-        tb = measured_traffic(args.config, args.precision, form, spec)
-        traffic = round(tb[dom]) if tb is not None and dom in tb else None
+        tb = measured_traffic(args.config, args.precision, form, spec, kind=dom)
+        traffic = round(tb) if tb is not None else None
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch",
