@@ -139,22 +139,25 @@ std::vector<T> colmajor(const Mat& M, int ld, bool transpose_first) {
   return out;
 }
 
-// Set-up copies (tables, structure) go through a pinned staging buffer of the
-// calling thread: the host vector, often a temporary, is copied there and the
-// device copy is queued on the stream, with no wait.  A staged region is
-// written again only after every device this thread has copied to from the
-// buffer has been synchronised (devices, unlike streams, outlive solvers).
-// Larger copies wait for the stream and copy at once.
+// Set-up copies (tables, structure) go through one pinned staging buffer of
+// the process (allocated once, kept to the process's end): the host vector,
+// often a temporary, is copied there, the device copy is queued on the
+// stream with no wait, and an event recorded behind it.  A staged region is
+// written again only after the events of every copy out of the buffer have
+// completed (an event stays valid after its stream is gone).  Larger copies
+// wait for the stream and copy at once.
 struct UploadStage {
   static constexpr size_t kCap = 8u << 20;
+  std::mutex mu;
   unsigned char* base = nullptr;
   size_t off = 0;
-  std::vector<int> devices;  // since the last reuse of the buffer
+  std::vector<std::pair<int, hipEvent_t>> pending;  // (device, event) since the last reuse
+  std::map<int, std::vector<hipEvent_t>> idle;      // per device (events belong to one)
 };
 
 UploadStage& upload_stage() {
-  thread_local UploadStage u;  // left to the process's end (pinned host memory)
-  return u;
+  static UploadStage* u = new UploadStage;  // never destroyed: outlives every solver
+  return *u;
 }
 
 template <typename T>
@@ -162,32 +165,45 @@ T* upload(const std::vector<T>& v, hipStream_t st) {
   T* d = dmalloc<T>(v.size());
   const size_t n = v.size() * sizeof(T);
   if (n == 0) return d;
-  UploadStage& u = upload_stage();
   if (n > UploadStage::kCap / 4) {
     TAPG_HIP(hipStreamSynchronize(st));
     TAPG_HIP(hipMemcpy(d, v.data(), n, hipMemcpyHostToDevice));
     return d;
   }
+  UploadStage& u = upload_stage();
+  std::lock_guard<std::mutex> lk(u.mu);
   if (u.base == nullptr)
     TAPG_HIP(hipHostMalloc(reinterpret_cast<void**>(&u.base), UploadStage::kCap,
                            hipHostMallocPortable));
   size_t at = (u.off + 255) & ~(size_t)255;
   if (at + n > UploadStage::kCap) {  // reuse: every copy out of the buffer has completed
-    int cur = 0;
-    TAPG_HIP(hipGetDevice(&cur));
-    for (int dev : u.devices) {
-      TAPG_HIP(hipSetDevice(dev));
-      TAPG_HIP(hipDeviceSynchronize());
+    for (auto& pe : u.pending) {
+      TAPG_HIP(hipEventSynchronize(pe.second));
+      u.idle[pe.first].push_back(pe.second);
     }
-    TAPG_HIP(hipSetDevice(cur));
-    u.devices.clear();
+    u.pending.clear();
     at = 0;
   }
   int dev = 0;
   TAPG_HIP(hipGetDevice(&dev));
-  if (std::find(u.devices.begin(), u.devices.end(), dev) == u.devices.end()) u.devices.push_back(dev);
+  hipEvent_t ev = nullptr;
+  auto& pool = u.idle[dev];
+  if (pool.empty()) {
+    TAPG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  } else {
+    ev = pool.back();
+    pool.pop_back();
+  }
   std::memcpy(u.base + at, v.data(), n);
-  TAPG_HIP(hipMemcpyAsync(d, u.base + at, n, hipMemcpyHostToDevice, st));
+  hipError_t e = hipMemcpyAsync(d, u.base + at, n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(ev, st);
+  if (e != hipSuccess) {  // nothing queued from this region that the event does not cover
+    (void)hipStreamSynchronize(st);
+    pool.push_back(ev);
+    dfree(d);
+    throw Fail{TAPG_EDEVICE, std::string("upload: ") + hipGetErrorString(e)};
+  }
+  u.pending.emplace_back(dev, ev);
   u.off = at + n;
   return d;
 }
