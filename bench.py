@@ -138,7 +138,7 @@ def main():
 
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                          "(sharding a tree or a batch across GPUs is not built)"}))
         sys.exit(2)
 
     import dwn_synth as ds
